@@ -1,0 +1,56 @@
+"""BF16 distance form with top-k re-rank (oracle, FP64).  Test infra only.
+
+The precision form of the search: the PCA-space vectors are rounded to
+bfloat16 (round to nearest, ties to even, from their float32 values), all
+exemplar distances are ranked on the rounded vectors, the k best candidates
+(k = 8) are kept, and those k are re-ranked with the unrounded vectors; the
+winner is the re-ranked minimum (ties to the lowest exemplar id).
+
+The oracle evaluates the distances of the rounded vectors exactly in FP64,
+i.e. the value the BF16 computation approximates; the GPU accumulates the
+same products in FP32.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import exact
+
+
+def round_bf16(a) -> np.ndarray:
+    """float32 values rounded to the nearest bfloat16 (ties to even), as float64."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    bits = f.view(np.uint32).astype(np.uint64)
+    lsb = (bits >> np.uint64(16)) & np.uint64(1)
+    rounded = ((bits + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return rounded.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def brute_topk(Qp, Zp, k: int = 8):
+    """Top-k exemplar ids per query by the distance of the bf16-rounded vectors."""
+    return exact.topk(round_bf16(Qp), round_bf16(Zp), k)
+
+
+def rerank(Q, Z, cand):
+    """Re-rank candidate ids with unrounded vectors; returns (nn, d2)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    nq = Q.shape[0]
+    nn = np.empty(nq, dtype=np.int64)
+    d2 = np.empty(nq)
+    for q in range(nq):
+        c = np.asarray(cand[q], dtype=np.int64)
+        diff = Z[c] - Q[q][None, :]
+        dd = np.einsum("ij,ij->i", diff, diff)
+        o = np.lexsort((c, dd))[0]
+        nn[q] = c[o]
+        d2[q] = dd[o]
+    return nn, d2
+
+
+def brute_nn(Qp, Zp, k: int = 8, Q_full=None, Z_full=None):
+    """BF16 top-k then FP64 re-rank in PCA space (or full D if given)."""
+    cand, _ = brute_topk(Qp, Zp, k)
+    if Q_full is not None:
+        return rerank(Q_full, Z_full, cand)[0], cand
+    return rerank(Qp, Zp, cand)[0], cand

@@ -1,0 +1,492 @@
+"""Pins for the FP64 oracle: each check comes from the paper or from
+mathematics, never from the oracle re-typed.  CPU only."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bf16, exact, irls, mlp, mstep, pca, solve, tree, vectors
+from paper_2006_11851_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_kv(name):
+    out = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, v = line.split()
+        out[k] = int(v)
+    return out
+
+
+def _tiny_problem(seed, Hz=8, Wz=8, H=12, W=12):
+    r = np.random.default_rng(seed)
+    Z = vectors.rgbs(r.integers(0, 256, size=(Hz, Wz, 3)).astype(np.uint8))
+    X = vectors.rgbs(r.integers(0, 256, size=(H, W, 3)).astype(np.uint8))
+    return Z, X
+
+
+# ---------------------------------------------------------------- vectors
+
+def test_guidance_channel_values():
+    u8 = np.zeros((4, 3, 3), np.uint8)
+    u8[1, 2] = (255, 0, 51)
+    img = vectors.rgbs(u8, 0.5)
+    assert np.allclose(img[:, 0, 3], 0.5 * np.array([0.5, 1.5, 2.5, 3.5]) / 4)
+    assert np.allclose(img[1, 2, :3], [1.0, 0.0, 0.2])
+
+
+def test_window_counts_match_workload_sizes():
+    # exemplar windows at stride 1 and the clamped / x-wrapped output grid
+    assert vectors.n_exemplar_windows(512, 512, 16) == 247009
+    assert vectors.n_exemplar_windows(1024, 1024, 8) == 1034289
+    assert vectors.output_grid(1024, 1024, 16, 4)[0].size == 64768
+    assert vectors.output_grid(128, 128, 8, 4)[0].size == 992
+    assert vectors.output_grid(2048, 2048, 8, 2)[0].size == 1045504
+
+
+def test_window_layout_literal():
+    Z, X = _tiny_problem(0)
+    w, s = 4, 2
+    Zm = vectors.exemplar_matrix(Z, w)
+    Qm = vectors.query_matrix(X, w, s)
+    e = 7
+    u, v = vectors.exemplar_corner(e, 8, 8, w)
+    for dy in range(w):
+        for dx in range(w):
+            for c in range(4):
+                assert Zm[e, (dy * w + dx) * 4 + c] == Z[v + dy, u + dx, c]
+    uq, vq = vectors.output_grid(12, 12, w, s)
+    q = 5  # second row of windows wraps in x
+    for dy in range(w):
+        for dx in range(w):
+            assert np.array_equal(Qm[q, (dy * w + dx) * 4 : (dy * w + dx) * 4 + 4], X[vq[q] + dy, (uq[q] + dx) % 12])
+
+
+# ---------------------------------------------------------------- exact NN
+
+def _triple_loop_nn(Q, Zm):
+    nn, best = [], []
+    for q in range(Q.shape[0]):
+        bd, be = None, None
+        for e in range(Zm.shape[0]):
+            acc = 0.0
+            for k in range(Q.shape[1]):
+                t = Q[q, k] - Zm[e, k]
+                acc += t * t
+            if bd is None or acc < bd:
+                bd, be = acc, e
+        nn.append(be)
+        best.append(bd)
+    return np.array(nn), np.array(best)
+
+
+def test_exact_nn_matches_pure_python_triple_loop():
+    Z, X = _tiny_problem(1)
+    Zm = vectors.exemplar_matrix(Z, 4)
+    Q = vectors.query_matrix(X, 4, 2)[:12]
+    nn_ref, d_ref = _triple_loop_nn(Q, Zm)
+    nn, d2, _ = exact.exact_nn(Q, Zm)
+    assert np.array_equal(nn, nn_ref)
+    assert np.allclose(d2, d_ref, rtol=1e-13, atol=0)
+
+
+def test_exact_copy_case_and_lowest_id_ties():
+    # exemplar with repeated content: identical windows must resolve to the lowest id
+    r = np.random.default_rng(3)
+    base = r.integers(0, 256, size=(8, 4, 3)).astype(np.uint8)
+    Zu8 = np.concatenate([base, base], axis=1)  # 8 x 8, left half == right half
+    Z = vectors.rgbs(Zu8)
+    w = 4
+    Zm = vectors.exemplar_matrix(Z, w)
+    # queries are copies of exemplar windows from the right half
+    picks = np.array([4 + 5 * 0, 4 + 5 * 2, 3 + 5 * 4])
+    Q = Zm[picks]
+    nn, d2, _ = exact.exact_nn(Q, Zm)
+    assert np.all(d2 == 0.0)
+    for p, n in zip(picks, nn):
+        same = np.nonzero(np.all(Zm == Zm[p], axis=1))[0]
+        assert n == same.min()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fast_topk_equals_direct(seed):
+    r = np.random.default_rng(seed)
+    Zm = r.normal(size=(300, 12))
+    Zm[100:140] = Zm[0:40]  # exact duplicates
+    Q = np.concatenate([r.normal(size=(20, 12)), Zm[[3, 105, 250]]])
+    a = exact.topk(Q, Zm, 8)
+    b = exact.topk_direct(Q, Zm, 8)
+    assert np.array_equal(a[0], b[0])
+    assert np.allclose(a[1], b[1], rtol=1e-15, atol=0)
+
+
+# ---------------------------------------------------------------- PCA
+
+def test_pca_orthonormal_full_rank_reconstruction_and_svd():
+    r = np.random.default_rng(4)
+    Z = r.normal(size=(200, 24)) @ np.diag(np.linspace(3, 0.1, 24))
+    mu, B, lam, ret = pca.basis(Z, 24)
+    assert np.abs(B.T @ B - np.eye(24)).max() < 1e-12
+    P = pca.project(Z, mu, B)
+    assert np.abs(mu + P @ B.T - Z).max() < 1e-12
+    assert abs(ret - 1.0) < 1e-12
+    # eigenvalues against the singular values of the centred data
+    s = np.linalg.svd(Z - Z.mean(0), compute_uv=False)
+    assert np.allclose(lam, s**2 / Z.shape[0], rtol=1e-10, atol=1e-14)
+    _, C = pca.covariance(Z)
+    assert abs(lam.sum() - np.trace(C)) < 1e-12 * np.trace(C)
+    Bd = pca.basis(Z, 6)[1]
+    assert np.abs(C @ Bd - Bd @ np.diag(lam[:6])).max() < 1e-12
+    # sign convention: largest-magnitude entry of every column is positive
+    for j in range(6):
+        assert Bd[np.argmax(np.abs(Bd[:, j])), j] > 0
+
+
+def test_pca_full_rank_search_equals_full_dimension_search():
+    Z, X = _tiny_problem(5, 10, 10, 12, 12)
+    w = 2  # D = 16 < N = 81: full rank possible
+    Zm = vectors.exemplar_matrix(Z, w)
+    Q = vectors.query_matrix(X, w, 2)
+    mu, B, _, _ = pca.basis(Zm, Zm.shape[1])
+    nn_full = exact.exact_nn(Q, Zm)[0]
+    nn_pca = exact.topk(pca.project(Q, mu, B), pca.project(Zm, mu, B), 1)[0][:, 0]
+    assert np.array_equal(nn_full, nn_pca)
+
+
+def test_pca_variance_target_rule():
+    r = np.random.default_rng(6)
+    Z = r.normal(size=(500, 10)) * np.array([10, 5, 2, 1, 0.5, 0.1, 0.1, 0.1, 0.1, 0.1])
+    mu, B, lam, ret = pca.basis(Z, 0, 0.95)
+    d = B.shape[1]
+    frac = np.cumsum(lam) / lam.sum()
+    assert frac[d - 1] >= 0.95 and (d == 1 or frac[d - 2] < 0.95)
+
+
+# ---------------------------------------------------------------- tree
+
+def _proj_problem(seed, N=400, d=6):
+    r = np.random.default_rng(seed)
+    centres = r.normal(scale=4, size=(7, d))
+    Zp = centres[r.integers(0, 7, N)] + r.normal(size=(N, d))
+    Qp = centres[r.integers(0, 7, 60)] + r.normal(size=(60, d))
+    return Zp, Qp
+
+
+def test_tree_depth_zero_is_exhaustive():
+    Zp, Qp = _proj_problem(0)
+    t = tree.build(Zp, 4, 0)
+    assert t.n_leaves == 1
+    nn, _, _, _ = tree.tree_nn(Qp, Zp, t)
+    assert np.array_equal(nn, exact.topk(Qp, Zp, 1)[0][:, 0])
+
+
+def test_tree_partition_and_lloyd_fixed_point():
+    Zp, _ = _proj_problem(1)
+    t = tree.build(Zp, 4, 3, seed=0)
+    assert np.array_equal(np.sort(t.perm), np.arange(Zp.shape[0]))
+    assert t.leaf_off[-1] == Zp.shape[0]
+    # leaves: depth limit or fewer than b members
+    for node in range(t.n_nodes):
+        if t.n_children[node] == 0:
+            l = t.leaf_of_node[node]
+            m = t.leaf_off[l + 1] - t.leaf_off[l]
+            assert t.node_depth[node] == 3 or m < 4
+    # every internal node: children centroids are member means, members nearest own centroid
+    def members(node):
+        if t.n_children[node] == 0:
+            return t.leaf_members(t.leaf_of_node[node])
+        f, n = t.first_child[node], t.n_children[node]
+        return np.concatenate([members(f + j) for j in range(n)])
+
+    converged = 0
+    for node in range(t.n_nodes):
+        n = t.n_children[node]
+        if n == 0:
+            continue
+        f = t.first_child[node]
+        own = [members(f + j) for j in range(n)]
+        for j in range(n):
+            assert np.allclose(t.centroids[f + j], Zp[own[j]].mean(0), atol=1e-12)
+        allm = np.concatenate(own)
+        lab = np.concatenate([np.full(o.size, j) for j, o in enumerate(own)])
+        dd = ((Zp[allm][:, None, :] - t.centroids[f : f + n][None]) ** 2).sum(-1)
+        if np.array_equal(np.argmin(dd, 1), lab):
+            converged += 1
+    assert converged == sum(1 for node in range(t.n_nodes) if t.n_children[node] > 0)
+
+
+def test_descent_against_brute_force_on_hand_tree():
+    # root with two children, the second split again: 3 leaves
+    c = np.array([[0, 0], [-1, 0], [1, 0], [1, 1], [1, -1]], float)
+    t = tree.Tree(
+        centroids=c,
+        first_child=np.array([1, 0, 3, 0, 0]),
+        n_children=np.array([2, 0, 2, 0, 0]),
+        leaf_of_node=np.array([-1, 0, -1, 1, 2]),
+        node_depth=np.array([0, 1, 1, 2, 2]),
+        leaf_off=np.array([0, 1, 2, 3]),
+        perm=np.array([0, 1, 2]),
+    )
+    r = np.random.default_rng(7)
+    Q = r.normal(size=(200, 2)) * 2
+    leaves, _ = tree.descend(t, Q)
+    for q, l in zip(Q, leaves):
+        if np.sum((q - c[1]) ** 2) <= np.sum((q - c[2]) ** 2):
+            assert l == 0
+        else:
+            assert l == (1 if np.sum((q - c[3]) ** 2) <= np.sum((q - c[4]) ** 2) else 2)
+
+
+# ---------------------------------------------------------------- weights / energy
+
+def test_irls_identity_and_smooth_rho():
+    r, delta = 0.8, 1e-3
+    d = np.array([1e-3, 2e-3, 0.1, 1.0, 7.5])
+    # Eqs. 6-8: W d^2 = d^r for d >= delta
+    assert np.allclose(irls.weights(d, r, delta) * d**2, d**r, rtol=1e-14)
+    # continuity and C1 at delta
+    h = 1e-9
+    lo = irls.rho(np.array([delta - h]), r, delta)[0]
+    hi = irls.rho(np.array([delta + h]), r, delta)[0]
+    slope = r * delta ** (r - 1)
+    assert abs((hi - lo) - 2 * h * slope) < 1e-3 * 2 * h * slope
+    # both branches give delta^r at delta
+    small_at_delta = (1 - r / 2) * delta**r + (r / 2) * delta ** (r - 2) * delta**2
+    assert abs(small_at_delta - delta**r) < 1e-15
+    dlo = (irls.rho(np.array([delta - h]), r, delta)[0] - irls.rho(np.array([delta - 2 * h]), r, delta)[0]) / h
+    dhi = (irls.rho(np.array([delta + 2 * h]), r, delta)[0] - irls.rho(np.array([delta + h]), r, delta)[0]) / h
+    assert abs(dlo - r * delta ** (r - 1)) < 1e-3 * r * delta ** (r - 1)
+    assert abs(dhi - r * delta ** (r - 1)) < 1e-3 * r * delta ** (r - 1)
+    E, E2 = irls.energy(np.array([0.0, 0.5, 2.0]), r, delta)
+    assert abs(E2 - 4.25) < 1e-15
+    assert abs(E - (irls.rho(np.array([0.0]), r, delta)[0] + 0.5**r + 2.0**r)) < 1e-14
+
+
+# ---------------------------------------------------------------- M-step
+
+def _literal_patch_blend(X, Z, nn, Wq, w, s, o):
+    """Per-patch gather, written straight from the definition (slow)."""
+    H, W = X.shape[:2]
+    Hz, Wz = Z.shape[:2]
+    u, v = vectors.output_grid(H, W, w, s)
+    ex, ey = vectors.exemplar_corner(np.asarray(nn), Hz, Wz, w)
+    out = X.copy()
+    for b in range(-1, H // 2 + 1):
+        for a in range(W // 2):
+            rows = [y for y in (2 * b + o, 2 * b + o + 1) if 0 <= y < H]
+            cols = [(2 * a + o) % W, (2 * a + o + 1) % W]
+            if len(rows) == 0 or (o == 0 and (b < 0 or b >= H // 2)):
+                continue
+            cover = [q for q in range(u.size)
+                     if all(v[q] <= y <= v[q] + w - 1 for y in rows)
+                     and all((c - u[q]) % W < w for c in cols)]
+            if not cover:
+                continue
+            for y in rows:
+                for c in cols:
+                    num = np.zeros(3)
+                    den = 0.0
+                    for q in cover:
+                        num += Wq[q] * Z[ey[q] + y - v[q], ex[q] + (c - u[q]) % W, :3]
+                        den += Wq[q]
+                    out[y, c, :3] = num / den
+    return out
+
+
+@pytest.mark.parametrize("o", [0, 1])
+def test_mstep_equals_literal_patch_definition(o):
+    Z, X = _tiny_problem(8, 10, 10, 12, 12)
+    w, s = 4, 2
+    r = np.random.default_rng(9)
+    nq = vectors.output_grid(12, 12, w, s)[0].size
+    nn = r.integers(0, vectors.n_exemplar_windows(10, 10, w), nq)
+    Wq = r.uniform(0.2, 3.0, nq)
+    got, _ = mstep.mstep(X, Z, nn, Wq, w, s, o)
+    ref = _literal_patch_blend(X, Z, nn, Wq, w, s, o)
+    assert np.abs(got - ref).max() < 1e-13
+
+
+def test_mstep_is_weighted_least_squares_minimiser():
+    # explicit system: every window contributes W_q ||x_q - z_q||^2 over RGB
+    Z, X = _tiny_problem(10, 8, 8, 8, 8)
+    w, s = 4, 2
+    r = np.random.default_rng(11)
+    u, v = vectors.output_grid(8, 8, w, s)
+    nn = r.integers(0, vectors.n_exemplar_windows(8, 8, w), u.size)
+    Wq = r.uniform(0.1, 5.0, u.size)
+    Zm = vectors.exemplar_matrix(Z, w)
+    H = W = 8
+    rows, rhs = [], []
+    for q in range(u.size):
+        for dy in range(w):
+            for dx in range(w):
+                for c in range(3):
+                    row = np.zeros(H * W * 3)
+                    row[((v[q] + dy) * W + (u[q] + dx) % W) * 3 + c] = math.sqrt(Wq[q])
+                    rows.append(row)
+                    rhs.append(math.sqrt(Wq[q]) * Zm[nn[q], (dy * w + dx) * 4 + c])
+    sol = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)[0].reshape(H, W, 3)
+    got, _ = mstep.mstep(X, Z, nn, Wq, w, s, 0)
+    assert np.abs(got[..., :3] - sol).max() < 1e-12
+    assert np.array_equal(got[..., 3], X[..., 3])
+
+
+def test_mstep_hand_computed_averages():
+    H = W = 8
+    w, s = 4, 4  # windows tile the output: each pixel covered once, patches inside one window
+    Zu8 = np.zeros((8, 8, 3), np.uint8)
+    Zu8[:, :4] = 40
+    Zu8[:, 4:] = 200
+    Z = vectors.rgbs(Zu8)
+    X = vectors.rgbs(np.zeros((H, W, 3), np.uint8))
+    nq = vectors.output_grid(H, W, w, s)[0].size
+    nn = np.zeros(nq, np.int64)  # all windows copy exemplar corner (0, 0): colour 40
+    got, _ = mstep.mstep(X, Z, nn, np.ones(nq), w, s, 0)
+    assert np.allclose(got[..., :3], 40 / 255.0)  # single covering window: a copy
+    # two covering windows with constant colours a, b and weights W1, W2
+    w, s = 4, 2
+    X = vectors.rgbs(np.zeros((4, 8, 3), np.uint8))
+    u, v = vectors.output_grid(4, 8, w, s)
+    ida = 0  # corner (0,0): colour 40
+    idb = 4  # corner (4,0): colour 200
+    nn = np.where(u % 4 == 0, ida, idb)
+    Wq = np.where(u % 4 == 0, 2.0, 0.5)
+    got, _ = mstep.mstep(X, Z, nn, Wq, w, s, 0)
+    # pixel column 2: covered by windows at u = 0 (a) and u = 2 (b)
+    a, b = 40 / 255.0, 200 / 255.0
+    assert np.allclose(got[:, 2, :3], (2.0 * a + 0.5 * b) / 2.5)
+    got, _ = mstep.mstep(X, Z, nn, np.ones(nq if False else u.size), w, s, 0)
+    assert np.allclose(got[:, 2, :3], (a + b) / 2)
+    # constant exemplar reproduces the constant
+    Zc = vectors.rgbs(np.full((8, 8, 3), 77, np.uint8))
+    r = np.random.default_rng(1)
+    got, _ = mstep.mstep(X, Zc, r.integers(0, 25, u.size), r.uniform(0.1, 2, u.size), w, s, 1)
+    assert np.allclose(got[..., :3], 77 / 255.0)
+
+
+def test_patch_counts_from_paper_example():
+    g = _golden_kv("patch_counts.txt")
+    w, s = g["w"], g["stride"]
+    H = W = 32
+    pc0, xc = mstep.covering_counts(H, W, w, s, 0)
+    pc1, _ = mstep.covering_counts(H, W, w, s, 1)
+    inner = (slice(8, 24), slice(8, 24))
+    assert np.all(xc[inner] == g["per_pixel"])
+    # four pixels of a patch, each counted on its own
+    assert 4 * g["per_pixel"] == g["per_four_pixels"]
+    assert np.all(pc1[inner] == g["per_patch_wholly_containing"])
+    assert np.all(pc0[inner] == g["per_pixel"])  # aligned patches: 16 windows cover the whole patch
+
+
+# ---------------------------------------------------------------- iteration / multiscale
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_energy_non_increasing_random_tiny(seed):
+    Z, X = _tiny_problem(20 + seed, 10, 10, 12, 12)
+    tr = solve.Trace()
+    solve.iterate(X, Z, 4, 2, 6, "exact", trace=tr)
+    E = np.array(tr.E)
+    assert np.all(np.diff(E) <= 1e-12 * E[:-1])
+
+
+def test_energy_non_increasing_ex64_out128():
+    wl = synth.workload("ex64_out128")
+    ex = wl.exemplar()
+    init, _ = synth.row_matched_init(wl.init_seed, ex, wl.out_size, wl.out_size, wl.w[0])
+    Z = vectors.rgbs(ex)
+    X = vectors.rgbs(init)
+    tr = solve.Trace()
+    solve.iterate(X, Z, wl.w[0], wl.stride[0], 3, "exact", trace=tr)
+    E = np.array(tr.E)
+    assert np.all(np.diff(E) <= 1e-12 * E[:-1])
+    assert E[-1] < E[0]
+
+
+def test_pyramid_and_upsampling_closed_forms():
+    c = np.full((16, 12, 3), 0.37)
+    assert np.allclose(solve.blur_decimate(c), 0.37)
+    assert solve.blur_decimate(c).shape == (8, 6, 3)
+    pyr = solve.exemplar_pyramid(vectors.rgbs(np.zeros((32, 32, 3), np.uint8)), 3)
+    assert [p.shape[:2] for p in pyr] == [(8, 8), (16, 16), (32, 32)]
+    assert np.allclose(pyr[0][:, 0, 3], 0.5 * (np.arange(8) + 0.5) / 8)
+    # linear ramp in y is reproduced exactly away from the clamped border rows
+    Hc, Wc = 8, 6
+    X = np.zeros((Hc, Wc, 4))
+    X[..., 0] = (np.arange(Hc) * 0.1)[:, None]
+    up = solve.upsample2(X)
+    y = np.arange(2 * Hc)
+    expect = 0.1 * ((y + 0.5) / 2 - 0.5)
+    assert np.allclose(up[1:-1, :, 0], expect[1:-1, None], atol=1e-15)
+    # blur of a linear ramp along x is the ramp (symmetric kernel), away from mirrored borders
+    ramp = np.broadcast_to(np.arange(16.0)[None, :, None], (8, 16, 1)).copy()
+    assert np.allclose(solve.blur_decimate(ramp)[:, 1:-1, 0], np.arange(16.0)[0::2][1:-1])
+
+
+# ---------------------------------------------------------------- BF16
+
+def test_bf16_rounding_golden():
+    for line in open(os.path.join(GOLDEN, "bf16_rounding.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        a, b = line.split()
+        assert bf16.round_bf16(np.array([float.fromhex(a)]))[0] == float.fromhex(b)
+
+
+def test_bf16_rerank_invariant():
+    r = np.random.default_rng(13)
+    Zp = r.normal(size=(3000, 16)).astype(np.float32).astype(np.float64)
+    Qp = (Zp[r.integers(0, 3000, 200)] + 0.05 * r.normal(size=(200, 16))).astype(np.float32).astype(np.float64)
+    nn_exact = exact.topk(Qp, Zp, 1)[0][:, 0]
+    nn_bf, cand = bf16.brute_nn(Qp, Zp, 8)
+    inside = np.array([nn_exact[i] in cand[i] for i in range(200)])
+    assert inside.mean() > 0.9
+    assert np.array_equal(nn_bf[inside], nn_exact[inside])
+
+
+# ---------------------------------------------------------------- MLP
+
+def test_mlp_gradient_central_differences():
+    n_in, h, n_out = 5, 7, 6
+    r = np.random.default_rng(14)
+    theta = r.normal(scale=0.5, size=mlp.n_params(n_in, h, n_out))
+    q = r.normal(size=(9, n_in))
+    lab = r.integers(0, n_out, 9)
+    sc = r.uniform(0.5, 2.0, n_in)
+    loss, g = mlp.loss_and_grad(theta, q, lab, n_in, h, n_out, sc)
+    assert abs(loss - mlp.loss_only(theta, q, lab, n_in, h, n_out, sc)) < 1e-14
+    hstep = 1e-6
+    num = np.empty_like(theta)
+    for i in range(theta.size):
+        tp = theta.copy()
+        tm = theta.copy()
+        tp[i] += hstep
+        tm[i] -= hstep
+        num[i] = (mlp.loss_only(tp, q, lab, n_in, h, n_out, sc) - mlp.loss_only(tm, q, lab, n_in, h, n_out, sc)) / (2 * hstep)
+    assert np.abs(num - g).max() <= 1e-6 * max(1.0, np.abs(g).max())
+
+
+def test_gelu_special_values_and_adam_first_step():
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    # GELU(x) = x Phi(x); Phi(1) = 0.841344746068543 (standard normal table)
+    assert abs(mlp.gelu(np.array([1.0]))[0] - 0.841344746068543) < 1e-12
+    assert abs(mlp.gelu(np.array([-1.0]))[0] + (1 - 0.841344746068543)) < 1e-12
+    g = np.array([0.3, -2.0, 1e-3])
+    th, m, v = mlp.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=0.0)
+    assert np.allclose(th, -0.01 * np.sign(g), rtol=1e-12)
+
+
+def test_mlp_proposal_margin():
+    logits = np.array([[0.0, 2.0, 1.0, 2.0, -1.0]])
+    top, margin = mlp.propose(logits, 4)
+    assert list(top[0]) == [1, 3, 2, 0]
+    assert abs(margin[0]) < 1e-15  # two equal maxima
+    logits = np.array([[math.log(3.0), 0.0, 0.0]])
+    top, margin = mlp.propose(logits, 2)
+    assert abs(margin[0] - (3 / 5 - 1 / 5)) < 1e-15
