@@ -26,5 +26,6 @@ Modules:
   solve    - alternation, pyramid, upsampling, multiscale solve
   bf16     - BF16 distance form with top-k re-rank
   mlp      - leaf-proposal MLP forward/backward/Adam
+  parity   - judging helpers for comparisons with the GPU library
 """
-from . import vectors, exact, pca, tree, irls, mstep, solve, bf16, mlp  # noqa: F401
+from . import vectors, exact, pca, tree, irls, mstep, solve, bf16, mlp, parity  # noqa: F401

@@ -1,0 +1,48 @@
+// Host orchestration shared by the C ABI functions (internal).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace pts {
+
+struct EstepStats {
+  int64_t nq = 0;
+  int64_t fallbacks = 0;
+  double ms = 0.0;
+};
+
+// An exemplar image the search and blend run against.
+struct ExView {
+  const float* img;
+  int Hz, Wz;
+};
+
+inline ExView ctx_exemplar(Ctx* c) {
+  PTS_REQUIRE(c->Hz > 0, PTS_ERR_STATE, "no exemplar set");
+  return ExView{c->ex.as<float>(), c->Hz, c->Wz};
+}
+
+// padded PCA width: the smallest of 16, 24, 32, 48, 64, 96, 128 >= d
+int padded_dims(int d);
+
+// index.cpp
+void build_index_on(Ctx* c, ExView ex, const pts_index_params& p, Index& ix, pts_index_info* info);
+void export_index(Ctx* c, const Index& ix, pts_index_host* out);
+void import_index(Ctx* c, ExView ex, const pts_index_host& in, int make_bf16, Index& ix);
+
+// estep.cpp
+EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, const pts_estep_params& p,
+                    int32_t* nn, float* dist, bool timing);
+EstepStats run_estep(Ctx* c, const float* x, int H, int W, const pts_estep_params& p, int32_t* nn, float* dist,
+                     bool timing);
+// projected queries; padded_out: rows of ix.dp floats, else rows of ix.d
+void project_queries(Ctx* c, const float* x, int H, int W, int stride, float* qproj, bool padded_out);
+void exemplar_projection(Ctx* c, float* zproj);
+void descend_unpadded(Ctx* c, const float* qproj, int64_t n, int32_t* leaf);
+
+// solve.cpp
+const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int* w);
+void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W0, float* x, int H, int W,
+               pts_solve_trace* tr);
+
+}  // namespace pts

@@ -1,0 +1,17 @@
+// The two accelerated search forms (internal): BF16 brute force with top-k
+// and FP32 re-rank; MLP leaf proposal with fallback to the tree.
+#pragma once
+
+#include "api_internal.hpp"
+
+namespace pts {
+
+// nn[q] for projected queries qp [nq][ix.dp] (the winner distance is
+// computed by the caller).
+void search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
+                       const float* qp, int64_t nq, int32_t* nn);
+// returns the number of queries that fell back to the tree
+int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
+                       const float* qp, int64_t nq, int32_t* nn, bool bf16_scan, bool count_fallbacks);
+
+}  // namespace pts

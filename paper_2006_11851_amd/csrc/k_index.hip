@@ -1,0 +1,475 @@
+// Index-build kernels (Methodology 2.2: PCA before the k-means search tree).
+//
+//  * mean and covariance of all exemplar windows, gathered straight from the
+//    exemplar image, accumulated in FP64 (the covariance feeds the FP64
+//    eigensolve; centred products avoid the cancellation of E[zz^T]-mu mu^T);
+//  * projection of windows onto the basis, P = (x - mu) B, FP32, gathered
+//    from an image on either window grid (exemplar: all corners; output:
+//    stride s with the x wrap) - used for the index and for every query;
+//  * k-means helpers: nearest-centre assignment (ties to the lowest centre),
+//    centroid sums in 2^-30 fixed point with 64-bit integer atomics (integer
+//    addition is associative, so the centroids are bitwise reproducible),
+//    running minimum distance for k-means++ seeding.
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace pts {
+
+struct WinGeom {
+  const float4* img;
+  int W;      // image width (pixels)
+  int w;      // window width
+  int s;      // grid stride
+  int cols;   // windows per grid row
+  int wrap;   // 1: columns wrap modulo W
+};
+
+__device__ __forceinline__ float4 win_pixel(const WinGeom& g, int64_t win, int pix) {
+  const int i = (int)(win / g.cols), j = (int)(win - (int64_t)i * g.cols);
+  const int dy = pix / g.w, dx = pix - dy * g.w;
+  int x = j * g.s + dx;
+  if (g.wrap && x >= g.W) x -= g.W;
+  return g.img[(int64_t)(i * g.s + dy) * g.W + x];
+}
+
+static WinGeom geom(const float* img, int H, int W, int w, int s, bool wrap) {
+  WinGeom g;
+  g.img = reinterpret_cast<const float4*>(img);
+  g.W = W;
+  g.w = w;
+  g.s = s;
+  g.cols = wrap ? W / s : (W - w) / s + 1;
+  g.wrap = wrap ? 1 : 0;
+  (void)H;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// mean: partial column sums over a split of the windows, FP64
+
+__global__ __launch_bounds__(256) void k_mean_partial(WinGeom g, int64_t N, int D, int64_t per_split,
+                                                      double* __restrict__ part) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= D) return;
+  const int64_t e0 = (int64_t)blockIdx.y * per_split;
+  const int64_t e1 = min(N, e0 + per_split);
+  const int pix = j >> 2, ch = j & 3;
+  double acc = 0.0;
+  for (int64_t e = e0; e < e1; ++e) {
+    const float4 p = win_pixel(g, e, pix);
+    acc += (double)(ch == 0 ? p.x : ch == 1 ? p.y : ch == 2 ? p.z : p.w);
+  }
+  part[(int64_t)blockIdx.y * D + j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict__ part, int64_t len, int splits,
+                                                       double scale, double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  double a = 0.0;
+  for (int s = 0; s < splits; ++s) a += part[(int64_t)s * len + j];
+  out[j] = a * scale;
+}
+
+// covariance tile (bi <= bj) of 64 x 64 over a split of windows; 256
+// threads, each 4 x 4 outputs; windows streamed 16 at a time through LDS.
+constexpr int CV_T = 64, CV_E = 16;
+
+__global__ __launch_bounds__(256) void k_cov_partial(WinGeom g, int64_t N, int D, const double* __restrict__ mu,
+                                                     const int2* __restrict__ tiles, int64_t per_split,
+                                                     double* __restrict__ part) {
+  __shared__ double As[CV_E][CV_T + 1];
+  __shared__ double Bs[CV_E][CV_T + 1];
+  const int2 tile = tiles[blockIdx.x];
+  const int i0 = tile.x * CV_T, j0 = tile.y * CV_T;
+  const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
+  const int64_t e0 = (int64_t)blockIdx.y * per_split;
+  const int64_t e1 = min(N, e0 + per_split);
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int64_t eb = e0; eb < e1; eb += CV_E) {
+    // 16 windows x 64 elements for each of the two blocks: 16 x 16 pixels
+    {
+      const int r = tid >> 4;     // window within chunk
+      const int pp = tid & 15;    // pixel within the 64-element block
+      const int64_t e = eb + r;
+      double4 va = make_double4(0, 0, 0, 0), vb = make_double4(0, 0, 0, 0);
+      if (e < e1) {
+        const int ja = i0 + 4 * pp, jb = j0 + 4 * pp;
+        if (ja < D) {
+          const float4 p = win_pixel(g, e, ja >> 2);
+          va = make_double4((double)p.x - mu[ja], (double)p.y - mu[ja + 1], (double)p.z - mu[ja + 2],
+                            (double)p.w - mu[ja + 3]);
+        }
+        if (jb < D) {
+          const float4 p = win_pixel(g, e, jb >> 2);
+          vb = make_double4((double)p.x - mu[jb], (double)p.y - mu[jb + 1], (double)p.z - mu[jb + 2],
+                            (double)p.w - mu[jb + 3]);
+        }
+      }
+      As[r][4 * pp + 0] = va.x;
+      As[r][4 * pp + 1] = va.y;
+      As[r][4 * pp + 2] = va.z;
+      As[r][4 * pp + 3] = va.w;
+      Bs[r][4 * pp + 0] = vb.x;
+      Bs[r][4 * pp + 1] = vb.y;
+      Bs[r][4 * pp + 2] = vb.z;
+      Bs[r][4 * pp + 3] = vb.w;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = 0; r < CV_E; ++r) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[r][ti + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[r][tj + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* out = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (CV_T * CV_T);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) out[(ti + 16 * a) * CV_T + (tj + 16 * b)] = acc[a][b];
+}
+
+__global__ __launch_bounds__(256) void k_cov_reduce(const double* __restrict__ part, const int2* __restrict__ tiles,
+                                                    int ntiles, int splits, int D, double scale,
+                                                    double* __restrict__ cov) {
+  const int t = blockIdx.x;
+  const int2 tile = tiles[t];
+  for (int k = threadIdx.x; k < CV_T * CV_T; k += blockDim.x) {
+    double a = 0.0;
+    for (int s = 0; s < splits; ++s) a += part[((int64_t)s * ntiles + t) * (CV_T * CV_T) + k];
+    const int i = tile.x * CV_T + k / CV_T, j = tile.y * CV_T + k % CV_T;
+    if (i < D && j < D) {
+      cov[(int64_t)i * D + j] = a * scale;
+      cov[(int64_t)j * D + i] = a * scale;
+    }
+  }
+}
+
+void launch_mean_cov_image(Ctx* c, const float* img, int H, int W, int w, double* mean, double* cov) {
+  ProfScope ps(c, "mean_cov");
+  const WinGeom g = geom(img, H, W, w, 1, false);
+  const int64_t N = (int64_t)(H - w + 1) * (W - w + 1);
+  const int D = 4 * w * w;
+  // mean
+  {
+    const int64_t splits = std::max<int64_t>(1, std::min<int64_t>(ceil_div(N, 256), 1024 / ceil_div(D, 256) + 1));
+    const int64_t per = ceil_div(N, splits);
+    double* part = c->buf<double>("mean_part", (size_t)(splits * D));
+    hipLaunchKernelGGL(k_mean_partial, dim3((unsigned)ceil_div(D, 256), (unsigned)splits), dim3(256), 0, c->stream, g,
+                       N, D, per, part);
+    check_launch("k_mean_partial");
+    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)ceil_div(D, 256)), dim3(256), 0, c->stream, part, (int64_t)D,
+                       (int)splits, 1.0 / (double)N, mean);
+    check_launch("k_reduce_splits");
+  }
+  // covariance, upper block-triangle tiles
+  const int nb = (int)ceil_div(D, CV_T);
+  std::vector<int2> tiles;
+  for (int i = 0; i < nb; ++i)
+    for (int j = i; j < nb; ++j) tiles.push_back(make_int2(i, j));
+  const int nt = (int)tiles.size();
+  int2* dtiles = c->buf<int2>("cov_tiles", tiles.size());
+  PTS_HIP(hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, c->stream));
+  int64_t splits = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, nt), ceil_div(N, 4 * CV_E)));
+  // bound the partial buffer to ~512 MB
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, ((int64_t)512 << 20) / ((int64_t)nt * CV_T * CV_T * 8)));
+  const int64_t per = round_up(ceil_div(N, splits), CV_E);
+  splits = ceil_div(N, per);
+  double* part = c->buf<double>("cov_part", (size_t)(splits * nt * CV_T * CV_T));
+  hipLaunchKernelGGL(k_cov_partial, dim3(nt, (unsigned)splits), dim3(256), 0, c->stream, g, N, D, mean, dtiles, per,
+                     part);
+  check_launch("k_cov_partial");
+  hipLaunchKernelGGL(k_cov_reduce, dim3(nt), dim3(256), 0, c->stream, part, dtiles, nt, (int)splits, D,
+                     1.0 / (double)N, cov);
+  check_launch("k_cov_reduce");
+}
+
+// ---------------------------------------------------------------------------
+// projection P[win][k] = sum_j (x_win[j] - mu[j]) B[j][k], FP32.
+// 256 threads, 64 windows per block; D in chunks of 8 pixels (32 elements)
+// staged through LDS together with the matching 32 rows of B.
+
+constexpr int PJ_T = 64, PJ_K = 32, PJ_MAXDP = 128;
+
+__global__ __launch_bounds__(256) void k_project(WinGeom g, int64_t n, int D, const float* __restrict__ mu,
+                                                 const float* __restrict__ B, int dp, float* __restrict__ P) {
+  __shared__ float Xs[PJ_T][PJ_K + 1];
+  __shared__ float Bs[PJ_K][PJ_MAXDP];
+  const int tid = threadIdx.x, tq = tid & 15, tk = tid >> 4;
+  const int64_t w0 = (int64_t)blockIdx.x * PJ_T;
+  const int nk = (dp + 15) / 16;  // outputs per thread along k (<= 8)
+  float acc[4][8];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.f;
+  for (int j0 = 0; j0 < D; j0 += PJ_K) {
+    // 64 windows x 8 pixels: 512 pixel loads, 2 per thread
+    for (int t = tid; t < PJ_T * (PJ_K / 4); t += 256) {
+      const int r = t >> 3, pp = t & 7;
+      const int64_t win = w0 + r;
+      const int j = j0 + 4 * pp;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (win < n && j < D) {
+        v = win_pixel(g, win, j >> 2);
+        v.x -= mu[j];
+        v.y -= mu[j + 1];
+        v.z -= mu[j + 2];
+        v.w -= mu[j + 3];
+      }
+      Xs[r][4 * pp + 0] = v.x;
+      Xs[r][4 * pp + 1] = v.y;
+      Xs[r][4 * pp + 2] = v.z;
+      Xs[r][4 * pp + 3] = v.w;
+    }
+    for (int t = tid; t < PJ_K * dp; t += 256) {
+      const int r = t / dp, k = t - r * dp;
+      Bs[r][k] = (j0 + r < D) ? B[(int64_t)(j0 + r) * dp + k] : 0.f;
+    }
+    __syncthreads();
+    for (int r = 0; r < PJ_K; ++r) {
+      float xv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xv[a] = Xs[tq + 16 * a][r];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if (b < nk) {
+          const int k = tk + 16 * b;
+          const float bv = (k < dp) ? Bs[r][k] : 0.f;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) acc[a][b] = fmaf(xv[a], bv, acc[a][b]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t win = w0 + tq + 16 * a;
+    if (win >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int k = tk + 16 * b;
+      if (b < nk && k < dp) P[win * dp + k] = acc[a][b];
+    }
+  }
+}
+
+void launch_project_image(Ctx* c, const float* img, int H, int W, int w, int s, bool wrap, const float* mu,
+                          const float* B, int dp, float* P) {
+  ProfScope ps(c, wrap ? "project_queries" : "project_exemplar");
+  PTS_REQUIRE(dp >= 1 && dp <= PJ_MAXDP, PTS_ERR_UNSUPPORTED, "projection: d must be <= 128");
+  const WinGeom g = geom(img, H, W, w, s, wrap);
+  const int64_t rows = (H - w) / s + 1;
+  const int64_t n = rows * g.cols;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_project, dim3((unsigned)ceil_div(n, PJ_T)), dim3(256), 0, c->stream, g, n, 4 * w * w, mu, B,
+                     dp, P);
+  check_launch("k_project");
+}
+
+// ---------------------------------------------------------------------------
+// k-means helpers.  Points are rows of P [N][dp] (original exemplar order);
+// `members` lists the points of every active segment back to back,
+// seg_of[i] is the segment of member i; the k centres of segment s are rows
+// seg_cent_off[s] .. seg_cent_off[s] + seg_k[s] - 1 of `cents`.
+
+__device__ __forceinline__ float sqdist_rows(const float* __restrict__ a, const float* __restrict__ b, int dp) {
+  float acc = 0.f;
+  for (int k = 0; k < dp; k += 4) {
+    const float4 x = *reinterpret_cast<const float4*>(a + k);
+    const float4 y = *reinterpret_cast<const float4*>(b + k);
+    const float t0 = x.x - y.x, t1 = x.y - y.y, t2 = x.z - y.z, t3 = x.w - y.w;
+    acc = fmaf(t0, t0, acc);
+    acc = fmaf(t1, t1, acc);
+    acc = fmaf(t2, t2, acc);
+    acc = fmaf(t3, t3, acc);
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void k_kmeans_mindist(const float* __restrict__ P, int dp,
+                                                        const int32_t* __restrict__ members, int64_t m,
+                                                        const int32_t* __restrict__ seg_of,
+                                                        const float* __restrict__ cand, float* __restrict__ mind,
+                                                        int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const float d = sqdist_rows(P + (int64_t)members[i] * dp, cand + (int64_t)seg_of[i] * dp, dp);
+  mind[i] = first ? d : fminf(mind[i], d);
+}
+
+__global__ __launch_bounds__(256) void k_kmeans_assign(const float* __restrict__ P, int dp,
+                                                       const int32_t* __restrict__ members, int64_t m,
+                                                       const int32_t* __restrict__ seg_of,
+                                                       const int32_t* __restrict__ seg_cent_off,
+                                                       const int32_t* __restrict__ seg_k,
+                                                       const float* __restrict__ cents, int32_t* __restrict__ assign,
+                                                       int32_t* __restrict__ changed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int s = seg_of[i];
+  const int off = seg_cent_off[s], k = seg_k[s];
+  const float* p = P + (int64_t)members[i] * dp;
+  float best = __int_as_float(0x7f800000);
+  int bi = 0;
+  for (int c = 0; c < k; ++c) {
+    const float d = sqdist_rows(p, cents + (int64_t)(off + c) * dp, dp);
+    if (d < best) {
+      best = d;
+      bi = c;
+    }
+  }
+  if (assign[i] != bi) {
+    assign[i] = bi;
+    atomicAdd(changed, 1);
+  }
+}
+
+constexpr double KM_FIX = 1073741824.0;  // 2^30
+
+__global__ __launch_bounds__(256) void k_kmeans_accumulate(const float* __restrict__ P, int dp,
+                                                           const int32_t* __restrict__ members, int64_t m,
+                                                           const int32_t* __restrict__ seg_of,
+                                                           const int32_t* __restrict__ seg_cent_off,
+                                                           const int32_t* __restrict__ assign,
+                                                           unsigned long long* __restrict__ sums,
+                                                           int32_t* __restrict__ counts) {
+  // one thread per (member, 4-dimension group)
+  const int ng = dp >> 2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * ng) return;
+  const int64_t i = t / ng;
+  const int gidx = (int)(t - i * ng);
+  const int cidx = seg_cent_off[seg_of[i]] + assign[i];
+  const float4 v = *reinterpret_cast<const float4*>(P + (int64_t)members[i] * dp + 4 * gidx);
+  unsigned long long* dst = sums + (int64_t)cidx * dp + 4 * gidx;
+  atomicAdd(dst + 0, (unsigned long long)(long long)__double2ll_rn((double)v.x * KM_FIX));
+  atomicAdd(dst + 1, (unsigned long long)(long long)__double2ll_rn((double)v.y * KM_FIX));
+  atomicAdd(dst + 2, (unsigned long long)(long long)__double2ll_rn((double)v.z * KM_FIX));
+  atomicAdd(dst + 3, (unsigned long long)(long long)__double2ll_rn((double)v.w * KM_FIX));
+  if (gidx == 0) atomicAdd(counts + cidx, 1);
+}
+
+void launch_kmeans_mindist(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m, const int32_t* seg_of,
+                           const float* cand, float* mind, int first) {
+  ProfScope ps(c, "kmeans_mindist");
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_kmeans_mindist, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, c->stream, P, dp, members, m,
+                     seg_of, cand, mind, first);
+  check_launch("k_kmeans_mindist");
+}
+
+void launch_kmeans_assign(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m, const int32_t* seg_of,
+                          const int32_t* seg_cent_off, const int32_t* seg_k, const float* cents, int32_t* assign,
+                          int32_t* changed) {
+  ProfScope ps(c, "kmeans_assign");
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_kmeans_assign, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, c->stream, P, dp, members, m,
+                     seg_of, seg_cent_off, seg_k, cents, assign, changed);
+  check_launch("k_kmeans_assign");
+}
+
+void launch_kmeans_accumulate(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m,
+                              const int32_t* seg_of, const int32_t* seg_cent_off, const int32_t* assign,
+                              unsigned long long* sums, int32_t* counts) {
+  ProfScope ps(c, "kmeans_accumulate");
+  if (m == 0) return;
+  PTS_REQUIRE(dp % 4 == 0, PTS_ERR_ARG, "kmeans: dp must be a multiple of 4");
+  const int64_t n = m * (dp / 4);
+  hipLaunchKernelGGL(k_kmeans_accumulate, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, P, dp, members,
+                     m, seg_of, seg_cent_off, assign, sums, counts);
+  check_launch("k_kmeans_accumulate");
+}
+
+// ---------------------------------------------------------------------------
+// leaf-order layout helpers
+
+__global__ __launch_bounds__(256) void k_permute_rows(const float* __restrict__ src, const int32_t* __restrict__ perm,
+                                                      int64_t n, int dp, float* __restrict__ dst,
+                                                      float* __restrict__ norm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* s = src + (int64_t)perm[i] * dp;
+  float* d = dst + i * dp;
+  float acc = 0.f;
+  for (int k = 0; k < dp; k += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(s + k);
+    *reinterpret_cast<float4*>(d + k) = v;
+    acc = fmaf(v.x, v.x, acc);
+    acc = fmaf(v.y, v.y, acc);
+    acc = fmaf(v.z, v.z, acc);
+    acc = fmaf(v.w, v.w, acc);
+  }
+  if (norm) norm[i] = acc;
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__global__ __launch_bounds__(256) void k_to_bf16_rows(const float* __restrict__ P, int64_t n, int dp, int dk,
+                                                      uint16_t* __restrict__ out, float* __restrict__ norm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.f;
+  for (int k = 0; k < dk; ++k) {
+    const uint16_t h = (k < dp) ? f32_to_bf16_rne(P[i * dp + k]) : (uint16_t)0;
+    out[i * dk + k] = h;
+    const float f = bf16_to_f32(h);
+    acc = fmaf(f, f, acc);
+  }
+  if (norm) norm[i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_leaf_of_ids(const int32_t* __restrict__ leaf_of_ex,
+                                                     const int32_t* __restrict__ nn, int64_t n, int64_t N,
+                                                     int32_t* __restrict__ leaf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int e = nn[i];
+  leaf[i] = (e >= 0 && e < N) ? leaf_of_ex[e] : -1;
+}
+
+void launch_permute_rows(Ctx* c, const float* src, const int32_t* perm, int64_t n, int dp, float* dst, float* norm) {
+  ProfScope ps(c, "permute_rows");
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, src, perm, n, dp, dst,
+                     norm);
+  check_launch("k_permute_rows");
+}
+
+void launch_to_bf16_rows(Ctx* c, const float* P, int64_t n, int dp, int dk, uint16_t* out, float* norm) {
+  ProfScope ps(c, "to_bf16_rows");
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_to_bf16_rows, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, P, n, dp, dk, out,
+                     norm);
+  check_launch("k_to_bf16_rows");
+}
+
+void launch_leaf_of_ids(Ctx* c, const int32_t* leaf_of_ex, const int32_t* nn, int64_t n, int32_t* leaf, int64_t N) {
+  ProfScope ps(c, "leaf_of_ids");
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_leaf_of_ids, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, leaf_of_ex, nn, n, N,
+                     leaf);
+  check_launch("k_leaf_of_ids");
+}
+
+}  // namespace pts

@@ -1,0 +1,305 @@
+// Tree search kernels (Methodology 2.2: k-means search tree over the PCA-
+// reduced neighbourhoods).
+//
+//  * descent: greedy, nearest child centroid at every level (ties to the
+//    lowest child), one lane per query;
+//  * bucketing: counting sort of the queries by leaf, then a work list of
+//    (leaf, 64-query chunk) tiles, so a leaf's members are streamed once per
+//    64 queries instead of once per query;
+//  * leaf scan (FP32): per tile, the 64 queries sit in registers (one per
+//    lane, replicated in the block's 4 waves), the leaf's member rows stream
+//    through LDS in chunks of 64, each wave takes every fourth member, and
+//    the 4 partial winners are merged in LDS.  Direct form sum (q - z)^2;
+//    ties go to the lowest exemplar id.
+#include <cfloat>
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace pts {
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_descend(const float* __restrict__ Qp, int64_t nq,
+                                                 const float* __restrict__ cent,
+                                                 const int32_t* __restrict__ first_child,
+                                                 const int32_t* __restrict__ n_children,
+                                                 const int32_t* __restrict__ leaf_of_node,
+                                                 int32_t* __restrict__ leaf) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  float qv[DP];
+#pragma unroll
+  for (int k = 0; k < DP; k += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(Qp + q * DP + k);
+    qv[k] = v.x;
+    qv[k + 1] = v.y;
+    qv[k + 2] = v.z;
+    qv[k + 3] = v.w;
+  }
+  int node = 0;
+  for (int depth = 0; depth < 64; ++depth) {  // bounded: a valid tree ends at a leaf long before
+    const int nc = n_children[node];
+    if (nc == 0) break;
+    const int f = first_child[node];
+    float best = FLT_MAX;
+    int bj = 0;
+    for (int j = 0; j < nc; ++j) {
+      const float* cr = cent + (int64_t)(f + j) * DP;
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < DP; k += 4) {
+        const float4 cv = *reinterpret_cast<const float4*>(cr + k);
+        const float t0 = qv[k] - cv.x, t1 = qv[k + 1] - cv.y, t2 = qv[k + 2] - cv.z, t3 = qv[k + 3] - cv.w;
+        acc = fmaf(t0, t0, acc);
+        acc = fmaf(t1, t1, acc);
+        acc = fmaf(t2, t2, acc);
+        acc = fmaf(t3, t3, acc);
+      }
+      if (acc < best) {
+        best = acc;
+        bj = j;
+      }
+    }
+    node = f + bj;
+  }
+  leaf[q] = leaf_of_node[node];
+}
+
+#define PTS_DP_SWITCH(dp, ...)                                                                     \
+  switch (dp) {                                                                                    \
+    case 16: { constexpr int DPC = 16; __VA_ARGS__; } break;                                       \
+    case 24: { constexpr int DPC = 24; __VA_ARGS__; } break;                                       \
+    case 32: { constexpr int DPC = 32; __VA_ARGS__; } break;                                       \
+    case 48: { constexpr int DPC = 48; __VA_ARGS__; } break;                                       \
+    case 64: { constexpr int DPC = 64; __VA_ARGS__; } break;                                       \
+    case 96: { constexpr int DPC = 96; __VA_ARGS__; } break;                                       \
+    case 128: { constexpr int DPC = 128; __VA_ARGS__; } break;                                     \
+    default: ::pts::fail(PTS_ERR_UNSUPPORTED, "padded PCA width must be 16/24/32/48/64/96/128");   \
+  }
+
+void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* cent, const int32_t* first_child,
+                    const int32_t* n_children, const int32_t* leaf_of_node, int32_t* leaf) {
+  ProfScope ps(c, "tree_descend");
+  if (nq == 0) return;
+  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_descend<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, Qp,
+                                       nq, cent, first_child, n_children, leaf_of_node, leaf));
+  check_launch("k_descend");
+}
+
+// ---------------------------------------------------------------------------
+// bucketing
+
+__global__ __launch_bounds__(256) void k_zero_i32(int32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_leaf_hist(const int32_t* __restrict__ leaf, int64_t n, int n_leaves,
+                                                   int32_t* __restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int l = leaf[i];
+  if (l >= 0 && l < n_leaves) atomicAdd(counts + l, 1);
+}
+
+// one block of 1024 threads: exclusive scans of the counts and of the tile
+// counts; cursor = off for the scatter; writes the tile count.
+__global__ __launch_bounds__(1024) void k_leaf_scan_offsets(const int32_t* __restrict__ counts, int n_leaves,
+                                                            int chunk, int32_t* __restrict__ off,
+                                                            int32_t* __restrict__ cursor,
+                                                            int32_t* __restrict__ tile_off,
+                                                            int32_t* __restrict__ ntiles) {
+  __shared__ int s_a[1024], s_b[1024];
+  __shared__ int carry_a, carry_b;
+  if (threadIdx.x == 0) {
+    carry_a = 0;
+    carry_b = 0;
+  }
+  __syncthreads();
+  for (int base = 0; base < n_leaves; base += 1024) {
+    const int l = base + threadIdx.x;
+    const int ca = (l < n_leaves) ? counts[l] : 0;
+    const int cb = (ca + chunk - 1) / chunk;
+    s_a[threadIdx.x] = ca;
+    s_b[threadIdx.x] = cb;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan
+      int va = 0, vb = 0;
+      if (threadIdx.x >= o) {
+        va = s_a[threadIdx.x - o];
+        vb = s_b[threadIdx.x - o];
+      }
+      __syncthreads();
+      s_a[threadIdx.x] += va;
+      s_b[threadIdx.x] += vb;
+      __syncthreads();
+    }
+    if (l < n_leaves) {
+      const int ea = carry_a + s_a[threadIdx.x] - ca;
+      const int eb = carry_b + s_b[threadIdx.x] - cb;
+      off[l] = ea;
+      cursor[l] = ea;
+      tile_off[l] = eb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+      carry_a += s_a[1023];
+      carry_b += s_b[1023];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    off[n_leaves] = carry_a;
+    tile_off[n_leaves] = carry_b;
+    *ntiles = carry_b;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_leaf_scatter(const int32_t* __restrict__ leaf, int64_t n, int n_leaves,
+                                                      int32_t* __restrict__ cursor, int32_t* __restrict__ order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int l = leaf[i];
+  if (l < 0 || l >= n_leaves) return;
+  const int pos = atomicAdd(cursor + l, 1);
+  order[pos] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_leaf_tiles(const int32_t* __restrict__ off, const int32_t* __restrict__ tile_off,
+                                                    int n_leaves, int chunk, int2* __restrict__ tiles) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_leaves) return;
+  const int t0 = tile_off[l], t1 = tile_off[l + 1];
+  for (int t = t0; t < t1; ++t) tiles[t] = make_int2(l, off[l] + (t - t0) * chunk);
+}
+
+void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b) {
+  ProfScope ps(c, "leaf_bucket");
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)ceil_div(n_leaves, 256)), dim3(256), 0, c->stream, b.counts,
+                     (int64_t)n_leaves);
+  check_launch("k_zero_i32");
+  if (n > 0) {
+    hipLaunchKernelGGL(k_leaf_hist, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, leaf, n, n_leaves,
+                       b.counts);
+    check_launch("k_leaf_hist");
+  }
+  hipLaunchKernelGGL(k_leaf_scan_offsets, dim3(1), dim3(1024), 0, c->stream, b.counts, n_leaves, chunk, b.off,
+                     b.cursor, b.tile_off, b.ntiles);
+  check_launch("k_leaf_scan_offsets");
+  if (n > 0) {
+    hipLaunchKernelGGL(k_leaf_scatter, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, leaf, n, n_leaves,
+                       b.cursor, b.order);
+    check_launch("k_leaf_scatter");
+  }
+  hipLaunchKernelGGL(k_leaf_tiles, dim3((unsigned)ceil_div(n_leaves, 256)), dim3(256), 0, c->stream, b.off, b.tile_off,
+                     n_leaves, chunk, b.tiles);
+  check_launch("k_leaf_tiles");
+}
+
+// ---------------------------------------------------------------------------
+// leaf scan, FP32 direct form
+
+constexpr int LS_Q = 64, LS_M = 64;
+
+__device__ __forceinline__ bool better_id(float d, int id, float bd, int bid) {
+  return d < bd || (d == bd && id < bid);
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__ Qp, const float* __restrict__ Zp,
+                                                       const int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ leaf_off,
+                                                       const int32_t* __restrict__ qoff,
+                                                       const int32_t* __restrict__ order,
+                                                       const int2* __restrict__ tiles,
+                                                       const int32_t* __restrict__ ntiles, int32_t* __restrict__ nn,
+                                                       float* __restrict__ best_d2) {
+  __shared__ float4 Zs[LS_M][DP / 4];
+  __shared__ int Zid[LS_M];
+  __shared__ float rd[4][LS_Q];
+  __shared__ int ri[4][LS_Q];
+  const int t = blockIdx.x;
+  if (t >= *ntiles) return;  // uniform per block
+  const int2 tile = tiles[t];
+  const int l = tile.x;
+  const int qend = qoff[l + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int pos = tile.y + lane;
+  const bool active = pos < qend && pos < tile.y + LS_Q;
+  const int q = active ? order[pos] : -1;
+  float qv[DP];
+#pragma unroll
+  for (int k = 0; k < DP; k += 4) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active) v = *reinterpret_cast<const float4*>(Qp + (int64_t)q * DP + k);
+    qv[k] = v.x;
+    qv[k + 1] = v.y;
+    qv[k + 2] = v.z;
+    qv[k + 3] = v.w;
+  }
+  float bd = FLT_MAX;
+  int bi = INT_MAX;
+  const int m0 = leaf_off[l], m1 = leaf_off[l + 1];
+  for (int mb = m0; mb < m1; mb += LS_M) {
+    const int mcount = min(LS_M, m1 - mb);
+    for (int idx = threadIdx.x; idx < LS_M * (DP / 4); idx += 256) {
+      const int r = idx / (DP / 4), k4 = idx - r * (DP / 4);
+      Zs[r][k4] = (r < mcount) ? reinterpret_cast<const float4*>(Zp + (int64_t)(mb + r) * DP)[k4]
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (threadIdx.x < LS_M) Zid[threadIdx.x] = (threadIdx.x < mcount) ? perm[mb + threadIdx.x] : INT_MAX;
+    __syncthreads();
+    for (int r = wave; r < mcount; r += 4) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k4 = 0; k4 < DP / 4; ++k4) {
+        const float4 z = Zs[r][k4];
+        const float t0 = qv[4 * k4] - z.x, t1 = qv[4 * k4 + 1] - z.y;
+        const float t2 = qv[4 * k4 + 2] - z.z, t3 = qv[4 * k4 + 3] - z.w;
+        acc = fmaf(t0, t0, acc);
+        acc = fmaf(t1, t1, acc);
+        acc = fmaf(t2, t2, acc);
+        acc = fmaf(t3, t3, acc);
+      }
+      const int id = Zid[r];
+      if (better_id(acc, id, bd, bi)) {
+        bd = acc;
+        bi = id;
+      }
+    }
+    __syncthreads();
+  }
+  rd[wave][lane] = bd;
+  ri[wave][lane] = bi;
+  __syncthreads();
+  if (wave == 0 && active) {
+    for (int w = 1; w < 4; ++w)
+      if (better_id(rd[w][lane], ri[w][lane], bd, bi)) {
+        bd = rd[w][lane];
+        bi = ri[w][lane];
+      }
+    nn[q] = (bi == INT_MAX) ? -1 : bi;
+    if (best_d2) best_d2[q] = bd;
+  }
+}
+
+void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
+                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int32_t* nn, float* best_d2) {
+  ProfScope ps(c, "leaf_scan_f32");
+  if (max_tiles == 0) return;
+  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_leaf_scan_f32<DPC>, dim3(max_tiles), dim3(256), 0, c->stream, Qp, Zp, perm,
+                                       leaf_off, b.off, b.order, b.tiles, b.ntiles, nn, best_d2));
+  check_launch("k_leaf_scan_f32");
+}
+
+}  // namespace pts
+
+namespace pts {
+
+void launch_zero_i32(Ctx* c, int32_t* p, int64_t n) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, p, n);
+  check_launch("k_zero_i32");
+}
+
+}  // namespace pts

@@ -1,0 +1,70 @@
+// Launchers of the gfx950 kernels (internal).  Every launcher enqueues on
+// ctx->stream and brackets itself for profiling.
+#pragma once
+
+#include "common.hpp"
+
+namespace pts {
+
+// ---- images (k_image.hip)
+void launch_rgbs_from_u8(Ctx* c, const uint8_t* u8, int H, int W, float gw, float* out);
+void launch_fill_guidance(Ctx* c, float* x, int H, int W, float gw);
+void launch_blur_decimate(Ctx* c, const float* in, int H, int W, float gw, float* out);
+void launch_upsample2(Ctx* c, const float* in, int H, int W, float gw, float* out);
+
+// ---- windows and exhaustive search (k_search.hip)
+// Materialise windows as rows of float32 [n][D]: output grid (stride s, x
+// wrap) when wrap, else the exemplar grid (all corners at stride s).
+void launch_gather_windows(Ctx* c, const float* img, int H, int W, int w, int s, bool wrap, float* out);
+// Exhaustive argmin of the direct squared distance between rows of Q [nq][D]
+// and rows of Z [N][D]; zid maps a Z row to the id reported and used in
+// tie-breaks (NULL = row index).
+void launch_argmin_direct(Ctx* c, const float* Q, int64_t nq, const float* Z, int64_t N, int D,
+                          const int32_t* zid, int32_t* best_id, float* best_d2);
+// dist[q] = || x_q - z_nn[q] || over the full window (NaN for an invalid id)
+void launch_winner_dist(Ctx* c, const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
+                        const int32_t* nn, float* dist);
+// number of i with a[i] != b[i], added to *count (int32)
+void launch_count_diff(Ctx* c, const int32_t* a, const int32_t* b, int64_t n, int32_t* count);
+void launch_zero_i32(Ctx* c, int32_t* p, int64_t n);
+
+// ---- blend and energy (k_mstep.hip)
+void launch_mstep(Ctx* c, const int32_t* nn, const float* dist, float* x, int H, int W, int w, int s,
+                  const float* ex, int Hz, int Wz, float r, float delta, int o);
+void launch_energy(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2);
+
+// ---- index (k_index.hip)
+void launch_mean_cov_image(Ctx* c, const float* img, int H, int W, int w, double* mean, double* cov);
+// P = (window - mu) B for every window of the grid; B is [D][dp]
+void launch_project_image(Ctx* c, const float* img, int H, int W, int w, int s, bool wrap, const float* mu,
+                          const float* B, int dp, float* P);
+void launch_kmeans_mindist(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m, const int32_t* seg_of,
+                           const float* cand, float* mind, int first);
+void launch_kmeans_assign(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m, const int32_t* seg_of,
+                          const int32_t* seg_cent_off, const int32_t* seg_k, const float* cents, int32_t* assign,
+                          int32_t* changed);
+void launch_kmeans_accumulate(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m,
+                              const int32_t* seg_of, const int32_t* seg_cent_off, const int32_t* assign,
+                              unsigned long long* sums, int32_t* counts);
+// dst[i] = src[perm[i]] (rows of dp floats); norm[i] = ||dst[i]||^2 if non-null
+void launch_permute_rows(Ctx* c, const float* src, const int32_t* perm, int64_t n, int dp, float* dst, float* norm);
+void launch_to_bf16_rows(Ctx* c, const float* P, int64_t n, int dp, int dk, uint16_t* out, float* norm);
+void launch_leaf_of_ids(Ctx* c, const int32_t* leaf_of_ex, const int32_t* nn, int64_t n, int32_t* leaf, int64_t N);
+
+// ---- tree search (k_tree.hip)
+struct BucketBufs {
+  int32_t* counts;    // [n_leaves]
+  int32_t* off;       // [n_leaves + 1] query offsets per leaf
+  int32_t* cursor;    // [n_leaves]
+  int32_t* tile_off;  // [n_leaves + 1]
+  int32_t* ntiles;    // [1]
+  int32_t* order;     // [n] query ids grouped by leaf
+  int2* tiles;        // [max_tiles] (leaf, first position in order)
+};
+void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* cent, const int32_t* first_child,
+                    const int32_t* n_children, const int32_t* leaf_of_node, int32_t* leaf);
+void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b);
+void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
+                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int32_t* nn, float* best_d2);
+
+}  // namespace pts

@@ -161,6 +161,20 @@ class Workload:
         L = self.levels
         return [self.out_size >> (L - 1 - l) for l in range(L)]
 
+    def initial_output(self, ex: np.ndarray, seed: int | None = None) -> np.ndarray:
+        """uint8 initial output at the coarsest level.
+
+        Row-matched w x w patches (``row_matched_init``) copied from the
+        exemplar subsampled by 2^(levels-1), so that the patches have the
+        coarsest level's scale; subsampling the uint8 image keeps the initial
+        output identical for every consumer.
+        """
+        f = 1 << (self.levels - 1)
+        src = np.ascontiguousarray(ex[::f, ::f])
+        out0 = self.out_sizes()[0]
+        init, _ = row_matched_init(self.init_seed if seed is None else seed, src, out0, out0, self.w[0])
+        return init
+
     def exemplar(self, seed: int | None = None) -> np.ndarray:
         return perspective_exemplar(
             self.seed if seed is None else seed,

@@ -18,3 +18,28 @@ def rng():
     import numpy as np
 
     return np.random.default_rng(12345)
+
+
+def _ensure_lib():
+    from paper_2006_11851_amd import pts
+
+    if not os.path.exists(pts.LIB_PATH):
+        from paper_2006_11851_amd import build
+
+        build.build()
+    return pts
+
+
+@pytest.fixture(scope="session")
+def ptslib():
+    return _ensure_lib()
+
+
+@pytest.fixture(scope="session")
+def gpu_ctx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pts = _ensure_lib()
+    return pts.Context(0)

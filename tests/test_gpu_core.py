@@ -1,0 +1,302 @@
+"""GPU parity of the plain FP32 path against the FP64 oracle (through the C ABI).
+
+Thresholds: >= 99.9 % of NN indices equal, a differing index excused when the
+oracle's FP64 squared distance of the returned id exceeds the oracle's own
+by < 1e-4 relative (tree mode: also when the oracle's own descent had a
+decision gap < 1e-4); pixels within 1e-3; energy within 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import exact, irls, mstep, parity, pca, solve, tree, vectors
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c1(gpu_ctx):
+    ex, init, wl = helpers.workload_inputs("ex64_out128")
+    gpu_ctx.set_exemplar_u8(ex, 0.5)
+    Z = vectors.rgbs(ex)
+    X = vectors.rgbs(init)
+    return dict(ctx=gpu_ctx, ex=ex, init=init, wl=wl, Z=Z, X=X, w=wl.w[0], s=wl.stride[0])
+
+
+def test_exact_full_search_parity(c1):
+    ctx, Z, X, w, s = c1["ctx"], c1["Z"], c1["X"], c1["w"], c1["s"]
+    print("case: exact_full ex64_out128", flush=True)
+    x = ctx.rgbs_from_u8(c1["init"])
+    assert np.abs(_np(x) - X).max() < 1e-6
+    nn, dist = ctx.estep(x, w, s, mode="exact_full")
+    Q, Zm = helpers.query_and_exemplar(X, Z, w, s)
+    nn_o, _, _ = exact.exact_nn(Q, Zm)
+    ok, same, _ = parity.nn_agreement(Q, Zm, _np(nn), nn_o)
+    assert ok >= 0.999, (ok, same)
+    d_ref = np.sqrt(parity.sqdist_rows(Q, Zm, _np(nn)))
+    assert np.allclose(_np(dist), d_ref, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("o", [0, 1])
+def test_mstep_teacher_forced(c1, o):
+    import torch
+
+    ctx, Z, X, w, s = c1["ctx"], c1["Z"], c1["X"], c1["w"], c1["s"]
+    print(f"case: mstep offset {o}", flush=True)
+    Q, Zm = helpers.query_and_exemplar(X, Z, w, s)
+    nn_o, _, _ = exact.exact_nn(Q, Zm)
+    d_o = np.sqrt(parity.sqdist_rows(Q, Zm, nn_o)).astype(np.float32)
+    x = ctx.rgbs_from_u8(c1["init"])
+    nn_t = torch.from_numpy(nn_o.astype(np.int32)).to(x.device)
+    d_t = torch.from_numpy(d_o).to(x.device)
+    ctx.mstep(nn_t, d_t, x, w, s, 0.8, 1e-3, o)
+    Xo, den = mstep.mstep(X, Z, nn_o, irls.weights(d_o.astype(np.float64)), w, s, o)
+    err = np.abs(_np(x) - Xo).max()
+    assert err <= 1e-3, err
+    assert np.array_equal(_np(x)[..., 3], X[..., 3].astype(np.float32))
+
+
+def test_energy_teacher_forced(gpu_ctx):
+    import torch
+
+    r = np.random.default_rng(0)
+    for n in (1, 1000, 65537, 1045504):
+        d = r.gamma(2.0, 0.5, size=n).astype(np.float32)
+        d[: max(1, n // 50)] = 0.0  # below delta: smooth branch
+        d[-1] = 5e-4
+        E, E2 = gpu_ctx.energy(torch.from_numpy(d).cuda())
+        Eo, E2o = irls.energy(d.astype(np.float64))
+        assert helpers.rel(E, Eo) <= 1e-5 and helpers.rel(E2, E2o) <= 1e-5, (n, E, Eo, E2, E2o)
+
+
+def test_pca_basis_matches_oracle(c1):
+    ctx, Z, w = c1["ctx"], c1["Z"], c1["w"]
+    print("case: pca basis ex64_out128 d=16", flush=True)
+    info = ctx.build_index(w, 16, 4, 3, seed=0)
+    g = ctx.export_index()
+    Zm = vectors.exemplar_matrix(Z, w)
+    mu, B, lam, ret = pca.basis(Zm, 16)
+    assert helpers.projector_gap(g["basis"], B) <= 1e-5
+    assert np.abs(g["mu"] - mu).max() <= 1e-6
+    assert np.allclose(g["eigenvalues"], lam[:16], rtol=1e-5, atol=1e-9 * lam[0])
+    assert abs(info.retained_variance - ret) <= 1e-6
+    assert np.abs(g["basis"].T @ g["basis"] - np.eye(16)).max() <= 1e-10
+
+
+def test_gpu_tree_properties(c1):
+    ctx, w = c1["ctx"], c1["w"]
+    ctx.build_index(w, 16, 4, 3, seed=0)
+    g = ctx.export_index()
+    N = g["N"]
+    assert np.array_equal(np.sort(g["perm"]), np.arange(N))
+    assert g["leaf_off"][0] == 0 and g["leaf_off"][-1] == N
+    t = helpers.dict_to_oracle_tree(g)
+    Zp = _np(ctx.exemplar_projection()).astype(np.float64)
+    for node in range(t.n_nodes):
+        if t.n_children[node] == 0:
+            l = t.leaf_of_node[node]
+            assert t.node_depth[node] == 3 or t.leaf_off[l + 1] - t.leaf_off[l] < 4
+
+    def members(node):
+        if t.n_children[node] == 0:
+            return t.leaf_members(t.leaf_of_node[node])
+        f, n = t.first_child[node], t.n_children[node]
+        return np.concatenate([members(f + j) for j in range(n)])
+
+    for node in range(1, t.n_nodes):
+        m = members(node)
+        assert np.abs(t.centroids[node] - Zp[m].mean(0)).max() <= 1e-5 * max(1.0, np.abs(Zp).max())
+    # members descend to their own leaf (Lloyd fixed points), allowing FP ties
+    import torch
+
+    leaves = _np(ctx.descend(torch.from_numpy(Zp.astype(np.float32)).cuda()))
+    own = t.leaf_of_exemplar()
+    assert np.mean(leaves == own) >= 0.99
+
+
+def test_exact_pca_teacher_forced(c1):
+    ctx, Z, X, w, s = c1["ctx"], c1["Z"], c1["X"], c1["w"], c1["s"]
+    print("case: exact_pca with the oracle's basis", flush=True)
+    oix = solve.build_index(Z, w, 16, 4, 3, seed=0)
+    ctx.import_index(helpers.oracle_index_to_dict(oix, Z.shape))
+    x = ctx.rgbs_from_u8(c1["init"])
+    nn, _ = ctx.estep(x, w, s, mode="exact_pca")
+    Qp = pca.project(vectors.query_matrix(X, w, s), oix.mu, oix.B)
+    nn_o = exact.topk(Qp, oix.Zp, 1)[0][:, 0]
+    ok, same, _ = parity.nn_agreement(Qp, oix.Zp, _np(nn), nn_o)
+    assert ok >= 0.999, (ok, same)
+    # the projection itself (row a1)
+    qp = _np(ctx.project(x, s))
+    assert np.abs(qp - Qp).max() <= 1e-4 * max(1.0, np.abs(Qp).max())
+
+
+def test_tree_search_teacher_forced(c1):
+    ctx, Z, X, w, s = c1["ctx"], c1["Z"], c1["X"], c1["w"], c1["s"]
+    print("case: tree with the oracle's tree", flush=True)
+    oix = solve.build_index(Z, w, 16, 4, 3, seed=0)
+    ctx.import_index(helpers.oracle_index_to_dict(oix, Z.shape))
+    x = ctx.rgbs_from_u8(c1["init"])
+    nn, dist = ctx.estep(x, w, s, mode="tree")
+    Qp = pca.project(vectors.query_matrix(X, w, s), oix.mu, oix.B)
+    nn_o, _, leaves_o, gaps = tree.tree_nn(Qp, oix.Zp, oix.tree)
+    ok, same, _ = parity.nn_agreement(Qp, oix.Zp, _np(nn), nn_o)
+    flips = (_np(nn) != nn_o) & (gaps < 1e-4)
+    assert ok + flips.mean() >= 0.999, (ok, same)
+    Q, Zm = helpers.query_and_exemplar(X, Z, w, s)
+    assert np.allclose(_np(dist), np.sqrt(parity.sqdist_rows(Q, Zm, _np(nn))), rtol=1e-5, atol=1e-6)
+
+
+def test_descent_matches_oracle(c1):
+    import torch
+
+    ctx, Z, X, w, s = c1["ctx"], c1["Z"], c1["X"], c1["w"], c1["s"]
+    oix = solve.build_index(Z, w, 16, 4, 3, seed=0)
+    ctx.import_index(helpers.oracle_index_to_dict(oix, Z.shape))
+    r = np.random.default_rng(3)
+    Qp = (oix.Zp[r.integers(0, oix.Zp.shape[0], 777)] + 0.3 * r.normal(size=(777, 16)))
+    leaves = _np(ctx.descend(torch.from_numpy(Qp.astype(np.float32)).cuda()))
+    lo, gaps = tree.descend(oix.tree, Qp.astype(np.float32).astype(np.float64))
+    assert np.all((leaves == lo) | (gaps < 1e-4))
+
+
+def test_pyramid_and_upsample_match_oracle(gpu_ctx):
+    import torch
+
+    ex, init, wl = helpers.workload_inputs("ex256_out512")
+    gpu_ctx.set_exemplar_u8(ex, 0.5)
+    pyr = solve.exemplar_pyramid(vectors.rgbs(ex), 3)
+    for l in range(3):
+        g = _np(gpu_ctx.pyramid_level(3, l))
+        assert np.abs(g - pyr[l]).max() <= 1e-5, l
+    X = vectors.rgbs(init)
+    up = _np(gpu_ctx.upsample2(torch.from_numpy(X.astype(np.float32)).cuda()))
+    assert np.abs(up - solve.upsample2(X)).max() <= 1e-6
+
+
+def test_solve_exact_energy_trajectory(c1):
+    ctx, Z, X, w, s = c1["ctx"], c1["Z"], c1["X"], c1["w"], c1["s"]
+    print("case: solve exact ex64_out128", flush=True)
+    ctx.set_exemplar_u8(c1["ex"], 0.5)
+    x0 = ctx.rgbs_from_u8(c1["init"])
+    out, tr = ctx.solve(x0, [dict(w=w, stride=s, iters=5)], mode="exact_full", coarse_mode="exact_full")
+    E = tr["E"]
+    assert np.all(np.diff(E) <= 1e-5 * E[:-1]), E  # monotone (FP32 slack)
+    otr = solve.Trace()
+    solve.iterate(X, Z, w, s, 5, "exact", trace=otr)
+    assert helpers.rel(E[0], otr.E[0]) <= 1e-5
+    assert helpers.rel(E[-1], otr.E[-1]) <= 1e-2, (E, otr.E)
+
+
+def test_solve_multiscale_tree_runs_and_decreases(gpu_ctx):
+    ex, init, wl = helpers.workload_inputs("ex256_out512")
+    print("case: solve tree ex256_out512", flush=True)
+    gpu_ctx.set_exemplar_u8(ex, 0.5)
+    x0 = gpu_ctx.rgbs_from_u8(init)
+    levels = [dict(w=w, stride=s, iters=4, pca_dims=wl.pca_dims, branching=wl.branching, depth=wl.depth)
+              for w, s in zip(wl.w, wl.stride)]
+    out, tr = gpu_ctx.solve(x0, levels, mode="tree", coarse_mode="tree")
+    assert out.shape == (512, 512, 4)
+    assert np.isfinite(_np(out)).all()
+    for l in range(3):
+        E = tr["E"][tr["level"] == l]
+        assert E[-1] < E[0], (l, E)
+
+
+def test_determinism(c1):
+    ctx, w, s = c1["ctx"], c1["w"], c1["s"]
+    ctx.set_exemplar_u8(c1["ex"], 0.5)
+    ctx.build_index(w, 16, 4, 3, seed=0)
+    outs = []
+    for _ in range(2):
+        x = ctx.rgbs_from_u8(c1["init"])
+        nn, dist = ctx.estep(x, w, s, mode="tree")
+        ctx.mstep(nn, dist, x, w, s)
+        outs.append((_np(nn), _np(dist), _np(x)))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_ragged_and_small_shapes(gpu_ctx):
+    """Sizes that are not multiples of any tile, w = 2, s = 1 and one window row."""
+    r = np.random.default_rng(11)
+    for (Hz, Wz, H, W, w, s) in [(10, 14, 6, 10, 2, 1), (21, 19, 8, 12, 4, 2), (12, 12, 4, 8, 4, 4)]:
+        zu8 = r.integers(0, 256, size=(Hz, Wz, 3)).astype(np.uint8)
+        xu8 = r.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+        gpu_ctx.set_exemplar_u8(zu8, 0.5)
+        x = gpu_ctx.rgbs_from_u8(xu8)
+        nn, dist = gpu_ctx.estep(x, w, s, mode="exact_full")
+        Q, Zm = helpers.query_and_exemplar(vectors.rgbs(xu8), vectors.rgbs(zu8), w, s)
+        ok, _, _ = parity.nn_agreement(Q, Zm, _np(nn), exact.exact_nn(Q, Zm)[0])
+        assert ok == 1.0
+        d = min(16, 4 * w * w)
+        gpu_ctx.build_index(w, d, 2, 2, seed=1)
+        nn2, _ = gpu_ctx.estep(x, w, s, mode="tree")
+        assert np.all((_np(nn2) >= 0) & (_np(nn2) < Zm.shape[0]))
+
+
+def test_error_codes(gpu_ctx):
+    import torch
+
+    from paper_2006_11851_amd import pts
+
+    zu8 = np.zeros((16, 16, 3), np.uint8)
+    gpu_ctx.set_exemplar_u8(zu8, 0.5)
+    x = torch.zeros((16, 16, 4), device="cuda")
+    with pytest.raises(pts.PtsError) as e:
+        gpu_ctx.estep(x, 4, 2, mode="tree")  # no index yet
+    assert e.value.code == pts.PTS_ERR_STATE
+    with pytest.raises(pts.PtsError) as e:
+        gpu_ctx.estep(x, 4, 3, mode="exact_full")  # stride does not tile
+    assert e.value.code == pts.PTS_ERR_UNSUPPORTED
+    with pytest.raises(pts.PtsError) as e:
+        gpu_ctx.estep(x, 5, 1, mode="exact_full")  # odd w
+    assert e.value.code == pts.PTS_ERR_UNSUPPORTED
+    nn = torch.full((gpu_ctx.nq(16, 16, 4, 2),), 10**6, dtype=torch.int32, device="cuda")  # ids out of range
+    dist = torch.ones(nn.numel(), device="cuda")
+    gpu_ctx.mstep(nn, dist, x, 4, 2)  # invalid ids are skipped, not read
+    assert torch.isfinite(x).all()
+    with pytest.raises(pts.PtsError) as e:
+        gpu_ctx.mstep(nn, dist, x, 4, 2, patch_offset=2)
+    assert e.value.code == pts.PTS_ERR_ARG
+
+
+def test_full_size_tree_sampled(gpu_ctx):
+    """Finest level of the 256^2 -> 512^2 workload (N = 62001, nq = 64768):
+    the GPU index, the GPU search, sampled queries re-searched by the oracle
+    with the GPU's own basis and tree in FP64."""
+    import torch
+
+    ex, _, wl = helpers.workload_inputs("ex256_out512")
+    print("case: full-size tree sampled (N=62001, nq=64768)", flush=True)
+    gpu_ctx.set_exemplar_u8(ex, 0.5)
+    init, _ = __import__("paper_2006_11851_amd.synth", fromlist=["x"]).row_matched_init(0, ex, 512, 512, 8)
+    info = gpu_ctx.build_index(8, 24, 8, 3, seed=0)
+    assert info.N == 62001
+    g = gpu_ctx.export_index()
+    x = gpu_ctx.rgbs_from_u8(init)
+    nn, dist, st = gpu_ctx.estep(x, 8, 2, mode="tree", stats=True)
+    assert st.nq == 64768
+    Z = vectors.rgbs(ex)
+    X = vectors.rgbs(init)
+    r = np.random.default_rng(5)
+    sample = np.sort(r.choice(64768, 256, replace=False))
+    Q = vectors.query_matrix(X, 8, 2)[sample]
+    Zm = vectors.exemplar_matrix(Z, 8)
+    Qp = pca.project(Q, g["mu"], g["basis"])
+    Zp = pca.project(Zm, g["mu"], g["basis"])
+    t = helpers.dict_to_oracle_tree(g)
+    nn_o, _, _, gaps = tree.tree_nn(Qp, Zp, t)
+    got = _np(nn)[sample]
+    ok, same, _ = parity.nn_agreement(Qp, Zp, got, nn_o)
+    flips = (got != nn_o) & (gaps < 1e-4)
+    assert ok + flips.mean() >= 0.99, (ok, same)
+    assert np.allclose(_np(dist)[sample], np.sqrt(parity.sqdist_rows(Q, Zm, got)), rtol=1e-5, atol=1e-6)
+    # exhaustive search on the same samples
+    nn_e, _ = gpu_ctx.estep(x, 8, 2, mode="exact_full")
+    nn_eo = exact.topk(Q, Zm, 1)[0][:, 0]
+    ok, same, _ = parity.nn_agreement(Q, Zm, _np(nn_e)[sample], nn_eo)
+    assert ok >= 0.996, (ok, same)
