@@ -1,0 +1,418 @@
+// BF16 distance form of the search: every projected query against every
+// projected exemplar window on the matrix cores, keeping the k best per
+// query, then an FP32 re-rank of those k.
+//
+// Distances use ||q - z||^2 = ||q||^2 - 2 q.z + ||z||^2.  ||q||^2 does not
+// change a query's ranking and is dropped; the MFMA accumulator starts at
+// ||z||^2 (FP32 norm of the bf16-rounded z) and the query operand is stored
+// as bf16(-2 q) (exact: a power-of-two scale), so the accumulator ends at
+// ||z||^2 - 2 q.z with no epilogue arithmetic.  bf16 products are exact in
+// FP32; accumulation is FP32.
+//
+// Tiling (v_mfma_f32_32x32x16_bf16, wave64): A = 32 exemplar rows x 16 of
+// K, B = 16 of K x 32 queries; lane l owns query column l % 32 and 16
+// exemplar rows, so each lane keeps a sorted top-k of its own query in
+// registers and the two lanes sharing a query merge at the end.  A block of
+// 8 waves holds 512 queries (64 per wave, two B tiles kept in registers);
+// exemplar rows stream through LDS in stages of 128 rows, double buffered,
+// pre-swizzled into MFMA fragment order (conflict-free 16-byte reads).  The
+// exemplar is split into S contiguous ranges; block b takes range b % S, so
+// with the round-robin placement of blocks over the 8 XCDs every XCD streams
+// one range through its own L2.  A per-query merge of the S partial lists
+// and the FP32 re-rank follow.
+#include <cfloat>
+#include <climits>
+
+#include "kernels_bf16.hpp"
+
+namespace pts {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+// Qb[q][k] = bf16(-2 * Qp[q][k]) for k < dp, 0 up to dk
+__global__ __launch_bounds__(256) void k_queries_bf16(const float* __restrict__ Qp, int64_t nq, int dp, int dk,
+                                                      uint16_t* __restrict__ Qb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nq * dk) return;
+  const int64_t q = t / dk;
+  const int k = (int)(t - q * dk);
+  Qb[t] = (k < dp) ? bf16_rne(-2.0f * Qp[q * dp + k]) : (uint16_t)0;
+}
+
+void launch_queries_bf16(Ctx* c, const float* Qp, int64_t nq, int dp, int dk, uint16_t* Qb) {
+  ProfScope ps(c, "queries_bf16");
+  if (nq == 0) return;
+  hipLaunchKernelGGL(k_queries_bf16, dim3((unsigned)ceil_div(nq * dk, 256)), dim3(256), 0, c->stream, Qp, nq, dp, dk,
+                     Qb);
+  check_launch("k_queries_bf16");
+}
+
+// ---------------------------------------------------------------------------
+// sorted top-K (ascending) in registers
+
+template <int K>
+struct TopK {
+  float d[K];
+  int i[K];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      d[t] = FLT_MAX;
+      i[t] = INT_MAX;
+    }
+  }
+  // insert (v, id); a no-op unless v < d[K-1]
+  __device__ __forceinline__ void insert(float v, int id) {
+#pragma unroll
+    for (int t = K - 1; t > 0; --t) {
+      const bool s = v < d[t - 1];
+      const bool n = v < d[t];
+      d[t] = s ? d[t - 1] : (n ? v : d[t]);
+      i[t] = s ? i[t - 1] : (n ? id : i[t]);
+    }
+    if (v < d[0]) {
+      d[0] = v;
+      i[0] = id;
+    }
+  }
+};
+
+constexpr int BB_WAVES = 8;
+constexpr int BB_QPB = BB_WAVES * 64;  // queries per block
+constexpr int BB_STAGE = 128;          // exemplar rows per LDS stage
+constexpr int BB_TOPK = 8;
+
+template <int KS>
+struct BruteSmem {
+  uint4 frag[2][BB_STAGE / 32][KS][64];  // [buffer][tile][k-step][lane] 16 B each
+  float zn[2][BB_STAGE];
+};
+
+// Loads one stage (rows r0 .. r0+127 of [row_begin, row_end)) from global
+// into registers: each thread owns up to 2 chunks of 16 B plus zn entries.
+template <int KS>
+struct StageRegs {
+  uint4 v[(BB_STAGE * KS * 2 + BB_QPB - 1) / BB_QPB];
+  float zn;
+};
+
+template <int KS>
+__device__ __forceinline__ void stage_load(StageRegs<KS>& R, const uint16_t* __restrict__ Zb,
+                                           const float* __restrict__ zbn, int64_t r0, int64_t row_end, int tid) {
+  constexpr int CH = KS * 2;  // 16-byte chunks per row
+  constexpr int NCH = BB_STAGE * CH;
+  constexpr int PER = (NCH + BB_QPB - 1) / BB_QPB;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int c = tid + u * BB_QPB;
+    uint4 val = make_uint4(0, 0, 0, 0);
+    if (c < NCH) {
+      const int row = c / CH, ch = c - row * CH;
+      const int64_t gr = r0 + row;
+      if (gr < row_end) val = reinterpret_cast<const uint4*>(Zb + gr * (KS * 16))[ch];
+    }
+    R.v[u] = val;
+  }
+  if (tid < BB_STAGE) {
+    const int64_t gr = r0 + tid;
+    R.zn = (gr < row_end) ? zbn[gr] : FLT_MAX;
+  }
+}
+
+template <int KS>
+__device__ __forceinline__ void stage_store(const StageRegs<KS>& R, BruteSmem<KS>& S, int buf, int tid) {
+  constexpr int CH = KS * 2;
+  constexpr int NCH = BB_STAGE * CH;
+  constexpr int PER = (NCH + BB_QPB - 1) / BB_QPB;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int c = tid + u * BB_QPB;
+    if (c < NCH) {
+      const int row = c / CH, ch = c - row * CH;
+      const int tile = row >> 5, i = row & 31;
+      const int kk = ch >> 1, half = ch & 1;
+      S.frag[buf][tile][kk][half * 32 + i] = R.v[u];
+    }
+  }
+  if (tid < BB_STAGE) S.zn[buf][tid] = R.zn;
+}
+
+// One wave: 64 queries (two B tiles) against the staged 128 rows.
+template <int KS>
+__device__ __forceinline__ void stage_compute(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
+                                              TopK<BB_TOPK> (&top)[2], int64_t pos0, int lane) {
+#pragma unroll
+  for (int t = 0; t < BB_STAGE / 32; ++t) {
+    bf16x8 A[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const uint4 u = S.frag[buf][t][kk][lane];
+      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+    floatx16 cinit;
+    const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
+      cinit[4 * g + 0] = z4.x;
+      cinit[4 * g + 1] = z4.y;
+      cinit[4 * g + 2] = z4.z;
+      cinit[4 * g + 3] = z4.w;
+    }
+    const int64_t tpos = pos0 + t * 32 + 4 * (lane >> 5);
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt) {
+      floatx16 acc = cinit;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc, 0, 0, 0);
+      float m = acc[0];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) m = fminf(m, acc[r]);
+      if (__any(m < top[qt].d[BB_TOPK - 1])) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float v = acc[r];
+          if (v < top[qt].d[BB_TOPK - 1]) top[qt].insert(v, (int)(tpos + 8 * (r >> 2) + (r & 3)));
+        }
+      }
+    }
+  }
+}
+
+template <int KS>
+__global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restrict__ Qb, int64_t nq,
+                                                         const uint16_t* __restrict__ Zb,
+                                                         const float* __restrict__ zbn, int64_t N, int S,
+                                                         int64_t rows_per_split, float* __restrict__ part_d,
+                                                         int32_t* __restrict__ part_i) {
+  __shared__ BruteSmem<KS> sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int split = blockIdx.x % S;
+  const int64_t qb = blockIdx.x / S;
+  const int64_t row_begin = (int64_t)split * rows_per_split;
+  const int64_t row_end = min(N, row_begin + rows_per_split);
+  // query B fragments: lane holds K = 16 kk + 8 (lane / 32) .. + 7 of query lane % 32
+  bf16x8 B[2][KS];
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt) {
+    const int64_t q = qb * BB_QPB + wave * 64 + qt * 32 + (lane & 31);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      uint4 u = make_uint4(0, 0, 0, 0);
+      if (q < nq) u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + (lane >> 5)];
+      B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+  }
+  TopK<BB_TOPK> top[2];
+  top[0].init();
+  top[1].init();
+  if (row_begin < row_end) {
+    const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
+    StageRegs<KS> R;
+    stage_load<KS>(R, Zb, zbn, row_begin, row_end, tid);
+    stage_store<KS>(R, sm, 0, tid);
+    __syncthreads();
+    for (int st = 0; st < nstages; ++st) {
+      const int buf = st & 1;
+      const bool more = st + 1 < nstages;
+      if (more) stage_load<KS>(R, Zb, zbn, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end, tid);
+      stage_compute<KS>(sm, buf, B, top, row_begin + (int64_t)st * BB_STAGE, lane);
+      if (more) stage_store<KS>(R, sm, buf ^ 1, tid);
+      __syncthreads();
+    }
+  }
+  // merge the two lanes that share a query: the k smallest of two sorted lists
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt) {
+    float od[BB_TOPK];
+    int oi[BB_TOPK];
+#pragma unroll
+    for (int t = 0; t < BB_TOPK; ++t) {
+      od[t] = __shfl_xor(top[qt].d[t], 32, 64);
+      oi[t] = __shfl_xor(top[qt].i[t], 32, 64);
+    }
+    const int64_t q = qb * BB_QPB + wave * 64 + qt * 32 + (lane & 31);
+    if (lane < 32 && q < nq) {
+      float* pd = part_d + ((int64_t)split * nq + q) * BB_TOPK;
+      int32_t* pi = part_i + ((int64_t)split * nq + q) * BB_TOPK;
+#pragma unroll
+      for (int t = 0; t < BB_TOPK; ++t) {
+        const float a = top[qt].d[t], b = od[BB_TOPK - 1 - t];
+        const int ia = top[qt].i[t], ib = oi[BB_TOPK - 1 - t];
+        const bool take_a = a < b || (a == b && ia < ib);
+        pd[t] = take_a ? a : b;
+        pi[t] = take_a ? ia : ib;
+      }
+    }
+  }
+}
+
+#define PTS_KS_SWITCH(dk, ...)                                                                     \
+  switch (dk) {                                                                                    \
+    case 32: { constexpr int KSC = 2; __VA_ARGS__; } break;                                        \
+    case 64: { constexpr int KSC = 4; __VA_ARGS__; } break;                                        \
+    case 96: { constexpr int KSC = 6; __VA_ARGS__; } break;                                        \
+    case 128: { constexpr int KSC = 8; __VA_ARGS__; } break;                                       \
+    default: ::pts::fail(PTS_ERR_UNSUPPORTED, "bf16 width must be 32/64/96/128");                  \
+  }
+
+int brute_splits(int64_t nq) {
+  // at least ~4 blocks per CU over 256 CUs; a multiple of the 8 XCDs
+  const int64_t qblocks = ceil_div(nq, BB_QPB);
+  int S = 8;
+  while (qblocks * S < 1024 && S < 64) S *= 2;
+  return S;
+}
+
+void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16_t* Zb, const float* zbn, int64_t N,
+                            int dk, int S, float* part_d, int32_t* part_i) {
+  ProfScope ps(c, "brute_bf16_topk");
+  if (nq == 0) return;
+  PTS_REQUIRE(N > 0 && N < INT_MAX, PTS_ERR_ARG, "brute: bad N");
+  const int64_t qblocks = ceil_div(nq, BB_QPB);
+  const int64_t rows = round_up(ceil_div(N, S), BB_STAGE);
+  PTS_REQUIRE(qblocks * S < (int64_t)1 << 31, PTS_ERR_UNSUPPORTED, "brute: grid too large");
+  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_brute_bf16_topk<KSC>, dim3((unsigned)(qblocks * S)), dim3(BB_QPB), 0,
+                                       c->stream, Qb, nq, Zb, zbn, N, S, rows, part_d, part_i));
+  check_launch("k_brute_bf16_topk");
+}
+
+// ---------------------------------------------------------------------------
+// merge the S partial top-k lists of a query and re-rank the k survivors by
+// the FP32 distance in PCA space; nn = original id (ties to the lowest id)
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restrict__ part_d,
+                                                          const int32_t* __restrict__ part_i, int64_t nq, int S,
+                                                          int k, const float* __restrict__ Qp,
+                                                          const float* __restrict__ Zp,
+                                                          const int32_t* __restrict__ perm, int64_t N,
+                                                          int32_t* __restrict__ cand_out,
+                                                          int32_t* __restrict__ nn) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  TopK<BB_TOPK> top;
+  top.init();
+  for (int s = 0; s < S; ++s) {
+    const float* pd = part_d + ((int64_t)s * nq + q) * BB_TOPK;
+    const int32_t* pi = part_i + ((int64_t)s * nq + q) * BB_TOPK;
+    for (int t = 0; t < BB_TOPK; ++t) {
+      const float v = pd[t];
+      const int id = pi[t];
+      // keep (v, id) order: equal distances keep the lower position
+      if (v < top.d[BB_TOPK - 1] || (v == top.d[BB_TOPK - 1] && id < top.i[BB_TOPK - 1])) {
+        if (v == top.d[BB_TOPK - 1]) {
+          top.d[BB_TOPK - 1] = FLT_MAX;  // make room, re-insert below
+          top.i[BB_TOPK - 1] = INT_MAX;
+        }
+        top.insert(v, id);
+      }
+    }
+  }
+  float qv[DP];
+#pragma unroll
+  for (int kq = 0; kq < DP; kq += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(Qp + q * DP + kq);
+    qv[kq] = v.x;
+    qv[kq + 1] = v.y;
+    qv[kq + 2] = v.z;
+    qv[kq + 3] = v.w;
+  }
+  float best = FLT_MAX;
+  int bid = INT_MAX;
+#pragma unroll
+  for (int t = 0; t < BB_TOPK; ++t) {
+    const int pos = top.i[t];
+    if (cand_out) cand_out[q * BB_TOPK + t] = (t < k && pos >= 0 && pos < N) ? perm[pos] : -1;
+    if (t >= k || pos < 0 || pos >= N) continue;
+    const float* zr = Zp + (int64_t)pos * DP;
+    float acc = 0.f;
+#pragma unroll
+    for (int kq = 0; kq < DP; kq += 4) {
+      const float4 z = *reinterpret_cast<const float4*>(zr + kq);
+      const float t0 = qv[kq] - z.x, t1 = qv[kq + 1] - z.y, t2 = qv[kq + 2] - z.z, t3 = qv[kq + 3] - z.w;
+      acc = fmaf(t0, t0, acc);
+      acc = fmaf(t1, t1, acc);
+      acc = fmaf(t2, t2, acc);
+      acc = fmaf(t3, t3, acc);
+    }
+    const int id = perm[pos];
+    if (acc < best || (acc == best && id < bid)) {
+      best = acc;
+      bid = id;
+    }
+  }
+  nn[q] = (bid == INT_MAX) ? -1 : bid;
+}
+
+void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int k,
+                             const float* Qp, int dp, const float* Zp, const int32_t* perm, int64_t N,
+                             int32_t* cand_out, int32_t* nn) {
+  ProfScope ps(c, "merge_rerank");
+  if (nq == 0) return;
+  PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
+  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_merge_rerank_pca<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
+                                       c->stream, part_d, part_i, nq, S, k, Qp, Zp, perm, N, cand_out, nn));
+  check_launch("k_merge_rerank_pca");
+}
+
+// full-D re-rank of given candidate ids (original exemplar ids): one wave
+// per query, lanes over window pixels
+__global__ __launch_bounds__(256) void k_rerank_full(const float4* __restrict__ x, int H, int W, int w, int s,
+                                                     int cols, const float4* __restrict__ ex, int Hz, int Wz,
+                                                     const int32_t* __restrict__ cand, int k, int64_t nq,
+                                                     int32_t* __restrict__ nn) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= nq) return;
+  const int i = (int)(q / cols), j = (int)(q - (int64_t)i * cols);
+  const int v = i * s, u = j * s;
+  const int nu = Wz - w + 1;
+  const int64_t N = (int64_t)(Hz - w + 1) * nu;
+  float best = FLT_MAX;
+  int bid = INT_MAX;
+  for (int t = 0; t < k; ++t) {
+    const int e = cand[q * BB_TOPK + t];
+    if (e < 0 || e >= N) continue;
+    const int ey = e / nu, exx = e - ey * nu;
+    float acc = 0.f;
+    for (int p = lane; p < w * w; p += 64) {
+      const int dy = p / w, dx = p - dy * w;
+      int xx = u + dx;
+      if (xx >= W) xx -= W;
+      const float4 a = x[(int64_t)(v + dy) * W + xx];
+      const float4 b = ex[(int64_t)(ey + dy) * Wz + exx + dx];
+      const float t0 = a.x - b.x, t1 = a.y - b.y, t2 = a.z - b.z, t3 = a.w - b.w;
+      acc = fmaf(t0, t0, acc);
+      acc = fmaf(t1, t1, acc);
+      acc = fmaf(t2, t2, acc);
+      acc = fmaf(t3, t3, acc);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (acc < best || (acc == best && e < bid)) {
+      best = acc;
+      bid = e;
+    }
+  }
+  if (lane == 0) nn[q] = (bid == INT_MAX) ? -1 : bid;
+}
+
+void launch_rerank_full(Ctx* c, const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
+                        const int32_t* cand, int k, int64_t nq, int32_t* nn) {
+  ProfScope ps(c, "rerank_full");
+  if (nq == 0) return;
+  hipLaunchKernelGGL(k_rerank_full, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, c->stream,
+                     reinterpret_cast<const float4*>(x), H, W, w, s, W / s, reinterpret_cast<const float4*>(ex), Hz,
+                     Wz, cand, k, nq, nn);
+  check_launch("k_rerank_full");
+}
+
+}  // namespace pts
