@@ -40,9 +40,14 @@ void project_queries(Ctx* c, const float* x, int H, int W, int stride, float* qp
 void exemplar_projection(Ctx* c, float* zproj);
 void descend_unpadded(Ctx* c, const float* qproj, int64_t n, int32_t* leaf);
 
+BucketBufs bucket_buffers(Ctx* c, int64_t n, int n_leaves, int chunk, int* max_tiles);
+
 // solve.cpp
 const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int* w);
 void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W0, float* x, int H, int W,
                pts_solve_trace* tr);
 
 }  // namespace pts
+
+// the opaque handle of the C ABI is the context itself
+struct pts_ctx : public pts::Ctx {};

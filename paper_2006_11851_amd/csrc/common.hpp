@@ -35,8 +35,8 @@ struct Error {
     if (!(cond)) ::pts::fail(code, msg);                                                           \
   } while (0)
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 struct Ctx;
 
@@ -95,10 +95,13 @@ struct Mlp {
   bool valid = false;
   int n_in = 0, h = 0, n_out = 0;
   int64_t n_params = 0;
-  DevMem params;      // f32 packed
+  DevMem params;      // f32 packed W1, b1, W2, b2, W3, b3
   DevMem in_scale;    // f32 [n_in]
   DevMem adam_m, adam_v;
   int64_t adam_t = 0;
+  uint64_t version = 0;               // bumped on every weight change
+  DevMem w1b, w2b, w3b;               // bf16 copies for inference
+  uint64_t bf_version = ~0ull;
 };
 
 struct ProfEntry {

@@ -1,28 +1,87 @@
 // Accelerated search forms: placeholders until their kernels land.
 #include "bf16_learned.hpp"
+#include "kernels_bf16.hpp"
+#include "kernels_mlp.hpp"
 
 namespace pts {
 
-void search_brute_bf16(Ctx*, ExView, const Index&, const float*, int, int, const pts_estep_params&, const float*,
-                       int64_t, int32_t*) {
-  fail(PTS_ERR_UNSUPPORTED, "BRUTE_BF16 not available");
+void search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
+                       const float* qp, int64_t nq, int32_t* nn) {
+  const int k = p.topk <= 0 ? 8 : p.topk;
+  PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
+  uint16_t* qb = c->buf<uint16_t>("qbf16", (size_t)nq * ix.dk);
+  launch_queries_bf16(c, qp, nq, ix.dp, ix.dk, qb);
+  const int S = brute_splits(nq);
+  float* pd = c->buf<float>("bb_pd", (size_t)S * nq * 8);
+  int32_t* pi = c->buf<int32_t>("bb_pi", (size_t)S * nq * 8);
+  launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), ix.zbnorm.as<float>(), ix.N, ix.dk, S, pd, pi);
+  if (p.rerank_full) {
+    int32_t* cand = c->buf<int32_t>("bb_cand", (size_t)nq * 8);
+    int32_t* tmp = c->buf<int32_t>("bb_nn_pca", (size_t)nq);
+    launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(),
+                            ix.perm.as<int32_t>(), ix.N, cand, tmp);
+    launch_rerank_full(c, x, H, W, ix.w, p.stride, ex.img, ex.Hz, ex.Wz, cand, k, nq, nn);
+  } else {
+    launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(),
+                            ix.perm.as<int32_t>(), ix.N, nullptr, nn);
+  }
 }
 
-int64_t search_learned(Ctx*, ExView, const Index&, const float*, int, int, const pts_estep_params&, const float*,
-                       int64_t, int32_t*, bool, bool) {
-  fail(PTS_ERR_UNSUPPORTED, "learned modes not available");
+int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
+                       const float* qp, int64_t nq, int32_t* nn, bool bf16_scan, bool count_fallbacks) {
+  const int P = p.n_proposals <= 0 ? 4 : p.n_proposals;
+  PTS_REQUIRE(P >= 1 && P <= 8 && P <= ix.tree.n_leaves(), PTS_ERR_ARG, "n_proposals must be 1..8 (and <= leaves)");
+  const int L = ix.tree.n_leaves();
+  // proposals and softmax margins
+  int32_t* prop = c->buf<int32_t>("ln_prop", (size_t)nq * P);
+  float* margin = c->buf<float>("ln_margin", (size_t)nq);
+  mlp_propose_rows(c, qp, ix.dp, nq, P, prop, margin);
+  // the tree's own leaf, used where the margin is low
+  int32_t* dleaf = c->buf<int32_t>("ln_dleaf", (size_t)nq);
+  launch_descend(c, qp, nq, ix.dp, ix.cent.as<float>(), ix.first_child.as<int32_t>(), ix.n_children.as<int32_t>(),
+                 ix.leaf_of_node.as<int32_t>(), dleaf);
+  int32_t* pair_leaf = c->buf<int32_t>("ln_pair_leaf", (size_t)nq * P);
+  int32_t* fb = c->buf<int32_t>("ln_fallbacks", 1);
+  launch_zero_i32(c, fb, 1);
+  launch_learned_pairs(c, prop, margin, dleaf, nq, P, p.margin, L, pair_leaf, fb);
+  const int chunk = bf16_scan ? 512 : 64;
+  int max_tiles = 0;
+  BucketBufs b = bucket_buffers(c, nq * P, L, chunk, &max_tiles);
+  launch_bucket(c, pair_leaf, nq * P, L, chunk, b);
+  if (!bf16_scan) {
+    int32_t* pid = c->buf<int32_t>("ln_pair_id", (size_t)nq * P);
+    float* pdd = c->buf<float>("ln_pair_d", (size_t)nq * P);
+    launch_leaf_scan_f32(c, qp, ix.dp, ix.zproj.as<float>(), ix.perm.as<int32_t>(), ix.leaf_off.as<int32_t>(), b,
+                         max_tiles, P, pid, pdd);
+    launch_merge_pairs_f32(c, pair_leaf, pid, pdd, nq, P, nn);
+  } else {
+    PTS_REQUIRE(ix.has_bf16, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
+    const int k = p.topk <= 0 ? 8 : p.topk;
+    PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
+    uint16_t* qb = c->buf<uint16_t>("qbf16", (size_t)nq * ix.dk);
+    launch_queries_bf16(c, qp, nq, ix.dp, ix.dk, qb);
+    float* pdd = c->buf<float>("ln_pair_cd", (size_t)nq * P * 8);
+    int32_t* pii = c->buf<int32_t>("ln_pair_ci", (size_t)nq * P * 8);
+    launch_leaf_scan_bf16(c, qb, P, ix.zbf.as<uint16_t>(), ix.zbnorm.as<float>(), ix.dk, ix.leaf_off.as<int32_t>(), b,
+                          max_tiles, pdd, pii);
+    if (p.rerank_full) {
+      int32_t* cand = c->buf<int32_t>("bb_cand", (size_t)nq * 8);
+      int32_t* tmp = c->buf<int32_t>("bb_nn_pca", (size_t)nq);
+      launch_merge_rerank_pca(c, pdd, pii, nq, P, P, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(),
+                              ix.perm.as<int32_t>(), ix.N, cand, tmp);
+      launch_rerank_full(c, x, H, W, ix.w, p.stride, ex.img, ex.Hz, ex.Wz, cand, k, nq, nn);
+    } else {
+      launch_merge_rerank_pca(c, pdd, pii, nq, P, P, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(),
+                              ix.perm.as<int32_t>(), ix.N, nullptr, nn);
+    }
+  }
+  int32_t fbh = 0;
+  if (count_fallbacks) {
+    PTS_HIP(hipMemcpyAsync(&fbh, fb, 4, hipMemcpyDeviceToHost, c->stream));
+    PTS_HIP(hipStreamSynchronize(c->stream));
+  }
+  return fbh;
 }
 
 }  // namespace pts
 
-extern "C" {
-int pts_mlp_init(pts_ctx*, int, int, int, uint64_t) { return PTS_ERR_UNSUPPORTED; }
-int pts_mlp_n_params(pts_ctx*, int64_t*) { return PTS_ERR_UNSUPPORTED; }
-int pts_mlp_get_weights(pts_ctx*, float*) { return PTS_ERR_UNSUPPORTED; }
-int pts_mlp_set_weights(pts_ctx*, const float*) { return PTS_ERR_UNSUPPORTED; }
-int pts_mlp_set_input_scale(pts_ctx*, const float*) { return PTS_ERR_UNSUPPORTED; }
-int pts_mlp_forward(pts_ctx*, const float*, int64_t, int, float*) { return PTS_ERR_UNSUPPORTED; }
-int pts_mlp_loss_grad(pts_ctx*, const float*, const int32_t*, int64_t, int, float*, float*) { return PTS_ERR_UNSUPPORTED; }
-int pts_mlp_train(pts_ctx*, const float*, const int32_t*, int64_t, const pts_train_params*, float*) { return PTS_ERR_UNSUPPORTED; }
-int pts_mlp_propose(pts_ctx*, const float*, int64_t, int, int32_t*, float*) { return PTS_ERR_UNSUPPORTED; }
-}

@@ -147,9 +147,10 @@ __device__ __forceinline__ void stage_store(const StageRegs<KS>& R, BruteSmem<KS
 // One wave: 64 queries (two B tiles) against the staged 128 rows.
 template <int KS>
 __device__ __forceinline__ void stage_compute(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
-                                              TopK<BB_TOPK> (&top)[2], int64_t pos0, int lane) {
+                                              TopK<BB_TOPK> (&top)[2], int64_t pos0, int lane, int nvalid) {
 #pragma unroll
   for (int t = 0; t < BB_STAGE / 32; ++t) {
+    if (t * 32 >= nvalid) break;  // rows past the range: padding only
     bf16x8 A[KS];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
@@ -223,7 +224,8 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
       const int buf = st & 1;
       const bool more = st + 1 < nstages;
       if (more) stage_load<KS>(R, Zb, zbn, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end, tid);
-      stage_compute<KS>(sm, buf, B, top, row_begin + (int64_t)st * BB_STAGE, lane);
+      stage_compute<KS>(sm, buf, B, top, row_begin + (int64_t)st * BB_STAGE, lane,
+                        (int)min((int64_t)BB_STAGE, row_end - row_begin - (int64_t)st * BB_STAGE));
       if (more) stage_store<KS>(R, sm, buf ^ 1, tid);
       __syncthreads();
     }
@@ -249,6 +251,86 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
         const bool take_a = a < b || (a == b && ia < ib);
         pd[t] = take_a ? a : b;
         pi[t] = take_a ? ia : ib;
+      }
+    }
+  }
+}
+
+// BF16 scan of leaves for (query, leaf) pairs: tile = (leaf, 512 pairs of
+// the bucketed order); rows = the leaf's members (contiguous in leaf order);
+// per pair the top-8 (score, leaf position).  Waves without pairs skip the
+// matrix work but still help stage the rows.
+template <int KS>
+__global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restrict__ Qb, int P,
+                                                        const uint16_t* __restrict__ Zb,
+                                                        const float* __restrict__ zbn,
+                                                        const int32_t* __restrict__ leaf_off,
+                                                        const int32_t* __restrict__ qoff,
+                                                        const int32_t* __restrict__ order,
+                                                        const int2* __restrict__ tiles,
+                                                        const int32_t* __restrict__ ntiles,
+                                                        float* __restrict__ pair_d, int32_t* __restrict__ pair_i) {
+  __shared__ BruteSmem<KS> sm;
+  const int t = blockIdx.x;
+  if (t >= *ntiles) return;  // uniform per block
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int2 tile = tiles[t];
+  const int pend = min(qoff[tile.x + 1], tile.y + BB_QPB);
+  const bool wave_active = tile.y + wave * 64 < pend;
+  bf16x8 B[2][KS];
+  int pr[2];
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt) {
+    const int pos = tile.y + wave * 64 + qt * 32 + (lane & 31);
+    pr[qt] = pos < pend ? order[pos] : -1;
+    const int64_t q = pr[qt] >= 0 ? pr[qt] / P : -1;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      uint4 u = make_uint4(0, 0, 0, 0);
+      if (q >= 0) u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + (lane >> 5)];
+      B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+  }
+  TopK<BB_TOPK> top[2];
+  top[0].init();
+  top[1].init();
+  const int64_t row_begin = leaf_off[tile.x], row_end = leaf_off[tile.x + 1];
+  if (row_begin < row_end) {
+    const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
+    StageRegs<KS> R;
+    stage_load<KS>(R, Zb, zbn, row_begin, row_end, tid);
+    stage_store<KS>(R, sm, 0, tid);
+    __syncthreads();
+    for (int st = 0; st < nstages; ++st) {
+      const int buf = st & 1;
+      const bool more = st + 1 < nstages;
+      if (more) stage_load<KS>(R, Zb, zbn, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end, tid);
+      if (wave_active)
+        stage_compute<KS>(sm, buf, B, top, row_begin + (int64_t)st * BB_STAGE, lane,
+                          (int)min((int64_t)BB_STAGE, row_end - row_begin - (int64_t)st * BB_STAGE));
+      if (more) stage_store<KS>(R, sm, buf ^ 1, tid);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt) {
+    float od[BB_TOPK];
+    int oi[BB_TOPK];
+#pragma unroll
+    for (int k2 = 0; k2 < BB_TOPK; ++k2) {
+      od[k2] = __shfl_xor(top[qt].d[k2], 32, 64);
+      oi[k2] = __shfl_xor(top[qt].i[k2], 32, 64);
+    }
+    if (lane < 32 && pr[qt] >= 0) {
+      float* pd = pair_d + (int64_t)pr[qt] * BB_TOPK;
+      int32_t* pi = pair_i + (int64_t)pr[qt] * BB_TOPK;
+#pragma unroll
+      for (int k2 = 0; k2 < BB_TOPK; ++k2) {
+        const float a = top[qt].d[k2], b = od[BB_TOPK - 1 - k2];
+        const int ia = top[qt].i[k2], ib = oi[BB_TOPK - 1 - k2];
+        const bool take_a = a < b || (a == b && ia < ib);
+        pd[k2] = take_a ? a : b;
+        pi[k2] = take_a ? ia : ib;
       }
     }
   }
@@ -284,13 +366,26 @@ void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16
   check_launch("k_brute_bf16_topk");
 }
 
+void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb, const float* zbn, int dk,
+                           const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* pair_d,
+                           int32_t* pair_i) {
+  ProfScope ps(c, "leaf_scan_bf16");
+  if (max_tiles == 0) return;
+  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_leaf_scan_bf16<KSC>, dim3(max_tiles), dim3(BB_QPB), 0, c->stream, Qb, P, Zb,
+                                       zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, pair_d, pair_i));
+  check_launch("k_leaf_scan_bf16");
+}
+
 // ---------------------------------------------------------------------------
 // merge the S partial top-k lists of a query and re-rank the k survivors by
 // the FP32 distance in PCA space; nn = original id (ties to the lowest id)
 
+// list s of query q is row (q * qs + s * ss) of part [..][8]; a list whose
+// valid[] entry is negative is skipped (valid == NULL: all lists valid).
 template <int DP>
 __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restrict__ part_d,
                                                           const int32_t* __restrict__ part_i, int64_t nq, int S,
+                                                          int64_t qs, int64_t ss, const int32_t* __restrict__ valid,
                                                           int k, const float* __restrict__ Qp,
                                                           const float* __restrict__ Zp,
                                                           const int32_t* __restrict__ perm, int64_t N,
@@ -301,8 +396,10 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
   TopK<BB_TOPK> top;
   top.init();
   for (int s = 0; s < S; ++s) {
-    const float* pd = part_d + ((int64_t)s * nq + q) * BB_TOPK;
-    const int32_t* pi = part_i + ((int64_t)s * nq + q) * BB_TOPK;
+    const int64_t row = q * qs + (int64_t)s * ss;
+    if (valid && valid[row] < 0) continue;
+    const float* pd = part_d + row * BB_TOPK;
+    const int32_t* pi = part_i + row * BB_TOPK;
     for (int t = 0; t < BB_TOPK; ++t) {
       const float v = pd[t];
       const int id = pi[t];
@@ -352,14 +449,15 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
   nn[q] = (bid == INT_MAX) ? -1 : bid;
 }
 
-void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int k,
-                             const float* Qp, int dp, const float* Zp, const int32_t* perm, int64_t N,
-                             int32_t* cand_out, int32_t* nn) {
+void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
+                             int64_t ss, const int32_t* valid, int k, const float* Qp, int dp, const float* Zp,
+                             const int32_t* perm, int64_t N, int32_t* cand_out, int32_t* nn) {
   ProfScope ps(c, "merge_rerank");
   if (nq == 0) return;
   PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
   PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_merge_rerank_pca<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
-                                       c->stream, part_d, part_i, nq, S, k, Qp, Zp, perm, N, cand_out, nn));
+                                       c->stream, part_d, part_i, nq, S, qs, ss, valid, k, Qp, Zp, perm, N, cand_out,
+                                       nn));
   check_launch("k_merge_rerank_pca");
 }
 

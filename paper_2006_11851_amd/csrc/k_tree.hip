@@ -14,7 +14,7 @@
 #include <cfloat>
 #include <climits>
 
-#include "kernels.hpp"
+#include "kernels_bf16.hpp"
 
 namespace pts {
 
@@ -64,18 +64,6 @@ __global__ __launch_bounds__(256) void k_descend(const float* __restrict__ Qp, i
   }
   leaf[q] = leaf_of_node[node];
 }
-
-#define PTS_DP_SWITCH(dp, ...)                                                                     \
-  switch (dp) {                                                                                    \
-    case 16: { constexpr int DPC = 16; __VA_ARGS__; } break;                                       \
-    case 24: { constexpr int DPC = 24; __VA_ARGS__; } break;                                       \
-    case 32: { constexpr int DPC = 32; __VA_ARGS__; } break;                                       \
-    case 48: { constexpr int DPC = 48; __VA_ARGS__; } break;                                       \
-    case 64: { constexpr int DPC = 64; __VA_ARGS__; } break;                                       \
-    case 96: { constexpr int DPC = 96; __VA_ARGS__; } break;                                       \
-    case 128: { constexpr int DPC = 128; __VA_ARGS__; } break;                                     \
-    default: ::pts::fail(PTS_ERR_UNSUPPORTED, "padded PCA width must be 16/24/32/48/64/96/128");   \
-  }
 
 void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* cent, const int32_t* first_child,
                     const int32_t* n_children, const int32_t* leaf_of_node, int32_t* leaf) {
@@ -212,8 +200,8 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
                                                        const int32_t* __restrict__ qoff,
                                                        const int32_t* __restrict__ order,
                                                        const int2* __restrict__ tiles,
-                                                       const int32_t* __restrict__ ntiles, int32_t* __restrict__ nn,
-                                                       float* __restrict__ best_d2) {
+                                                       const int32_t* __restrict__ ntiles, int P,
+                                                       int32_t* __restrict__ nn, float* __restrict__ best_d2) {
   __shared__ float4 Zs[LS_M][DP / 4];
   __shared__ int Zid[LS_M];
   __shared__ float rd[4][LS_Q];
@@ -226,7 +214,8 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int pos = tile.y + lane;
   const bool active = pos < qend && pos < tile.y + LS_Q;
-  const int q = active ? order[pos] : -1;
+  const int pair = active ? order[pos] : -1;  // query * P + slot
+  const int q = active ? pair / P : -1;
   float qv[DP];
 #pragma unroll
   for (int k = 0; k < DP; k += 4) {
@@ -278,17 +267,18 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
         bd = rd[w][lane];
         bi = ri[w][lane];
       }
-    nn[q] = (bi == INT_MAX) ? -1 : bi;
-    if (best_d2) best_d2[q] = bd;
+    nn[pair] = (bi == INT_MAX) ? -1 : bi;
+    if (best_d2) best_d2[pair] = bd;
   }
 }
 
 void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
-                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int32_t* nn, float* best_d2) {
+                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, int32_t* nn,
+                          float* best_d2) {
   ProfScope ps(c, "leaf_scan_f32");
   if (max_tiles == 0) return;
   PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_leaf_scan_f32<DPC>, dim3(max_tiles), dim3(256), 0, c->stream, Qp, Zp, perm,
-                                       leaf_off, b.off, b.order, b.tiles, b.ntiles, nn, best_d2));
+                                       leaf_off, b.off, b.order, b.tiles, b.ntiles, P, nn, best_d2));
   check_launch("k_leaf_scan_f32");
 }
 
@@ -300,6 +290,68 @@ void launch_zero_i32(Ctx* c, int32_t* p, int64_t n) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, p, n);
   check_launch("k_zero_i32");
+}
+
+}  // namespace pts
+
+namespace pts {
+
+// pair lists of the learned search: slot s of query q scans leaf
+// pair_leaf[q * P + s] (-1 = unused).  Margin below thr: the tree's leaf
+// only (the fallback); otherwise the P proposed leaves.
+__global__ __launch_bounds__(256) void k_learned_pairs(const int32_t* __restrict__ prop, const float* __restrict__ margin,
+                                                       const int32_t* __restrict__ dleaf, int64_t nq, int P, float thr,
+                                                       int n_leaves, int32_t* __restrict__ pair_leaf,
+                                                       int32_t* __restrict__ fallbacks) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const bool fb = !(margin[q] >= thr);
+  for (int s = 0; s < P; ++s) {
+    int l = fb ? (s == 0 ? dleaf[q] : -1) : prop[q * P + s];
+    if (l < 0 || l >= n_leaves) l = -1;
+    pair_leaf[q * P + s] = l;
+  }
+  if (fb) atomicAdd(fallbacks, 1);
+}
+
+void launch_learned_pairs(Ctx* c, const int32_t* prop, const float* margin, const int32_t* dleaf, int64_t nq, int P,
+                          float thr, int n_leaves, int32_t* pair_leaf, int32_t* fallbacks) {
+  ProfScope ps(c, "learned_pairs");
+  if (nq == 0) return;
+  hipLaunchKernelGGL(k_learned_pairs, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, prop, margin, dleaf,
+                     nq, P, thr, n_leaves, pair_leaf, fallbacks);
+  check_launch("k_learned_pairs");
+}
+
+// nn[q] = the best of the query's P pair winners (ties to the lowest id)
+__global__ __launch_bounds__(256) void k_merge_pairs_f32(const int32_t* __restrict__ pair_leaf,
+                                                         const int32_t* __restrict__ pair_id,
+                                                         const float* __restrict__ pair_d, int64_t nq, int P,
+                                                         int32_t* __restrict__ nn) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  float bd = FLT_MAX;
+  int bi = INT_MAX;
+  for (int s = 0; s < P; ++s) {
+    const int64_t p = q * P + s;
+    if (pair_leaf[p] < 0) continue;
+    const int id = pair_id[p];
+    const float d = pair_d[p];
+    if (id >= 0 && better_id(d, id, bd, bi)) {
+      bd = d;
+      bi = id;
+    }
+  }
+  nn[q] = (bi == INT_MAX) ? -1 : bi;
+}
+
+void launch_merge_pairs_f32(Ctx* c, const int32_t* pair_leaf, const int32_t* pair_id, const float* pair_d, int64_t nq,
+                            int P, int32_t* nn) {
+  ProfScope ps(c, "merge_pairs");
+  if (nq == 0) return;
+  hipLaunchKernelGGL(k_merge_pairs_f32, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf, pair_id,
+                     pair_d, nq, P, nn);
+  check_launch("k_merge_pairs_f32");
 }
 
 }  // namespace pts

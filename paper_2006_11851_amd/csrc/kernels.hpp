@@ -64,7 +64,13 @@ struct BucketBufs {
 void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* cent, const int32_t* first_child,
                     const int32_t* n_children, const int32_t* leaf_of_node, int32_t* leaf);
 void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b);
+// order[] holds pair indices (query * P + slot); results per pair
 void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
-                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int32_t* nn, float* best_d2);
+                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, int32_t* nn,
+                          float* best_d2);
+void launch_learned_pairs(Ctx* c, const int32_t* prop, const float* margin, const int32_t* dleaf, int64_t nq, int P,
+                          float thr, int n_leaves, int32_t* pair_leaf, int32_t* fallbacks);
+void launch_merge_pairs_f32(Ctx* c, const int32_t* pair_leaf, const int32_t* pair_id, const float* pair_d, int64_t nq,
+                            int P, int32_t* nn);
 
 }  // namespace pts

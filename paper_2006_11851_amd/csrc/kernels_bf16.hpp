@@ -1,0 +1,42 @@
+// Launchers of the BF16 search kernels (internal).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace pts {
+
+#define PTS_DP_SWITCH(dp, ...)                                                                     \
+  switch (dp) {                                                                                    \
+    case 16: { constexpr int DPC = 16; __VA_ARGS__; } break;                                       \
+    case 24: { constexpr int DPC = 24; __VA_ARGS__; } break;                                       \
+    case 32: { constexpr int DPC = 32; __VA_ARGS__; } break;                                       \
+    case 48: { constexpr int DPC = 48; __VA_ARGS__; } break;                                       \
+    case 64: { constexpr int DPC = 64; __VA_ARGS__; } break;                                       \
+    case 96: { constexpr int DPC = 96; __VA_ARGS__; } break;                                       \
+    case 128: { constexpr int DPC = 128; __VA_ARGS__; } break;                                     \
+    default: ::pts::fail(PTS_ERR_UNSUPPORTED, "padded PCA width must be 16/24/32/48/64/96/128");   \
+  }
+
+// Qb [nq][dk] = bf16(-2 Qp), zero padded
+void launch_queries_bf16(Ctx* c, const float* Qp, int64_t nq, int dp, int dk, uint16_t* Qb);
+// number of exemplar splits for the brute-force kernel
+int brute_splits(int64_t nq);
+// partial top-8 (score, leaf position) per (split, query): part [S][nq][8]
+void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16_t* Zb, const float* zbn, int64_t N,
+                            int dk, int S, float* part_d, int32_t* part_i);
+// merge S partial lists per query (list s of query q = row q*qs + s*ss of
+// part [..][8]; lists with valid[row] < 0 skipped), re-rank the best k in
+// FP32 PCA space; nn = exemplar id.  cand_out (optional) [nq][8]: the k
+// candidates as exemplar ids (-1 beyond k)
+void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
+                             int64_t ss, const int32_t* valid, int k, const float* Qp, int dp, const float* Zp,
+                             const int32_t* perm, int64_t N, int32_t* cand_out, int32_t* nn);
+// BF16 top-8 of each bucketed (query, leaf) pair over the leaf's members: pair [nq*P][8]
+void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb, const float* zbn, int dk,
+                           const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* pair_d,
+                           int32_t* pair_i);
+// full-D re-rank of candidate exemplar ids cand [nq][8] (first k used)
+void launch_rerank_full(Ctx* c, const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
+                        const int32_t* cand, int k, int64_t nq, int32_t* nn);
+
+}  // namespace pts

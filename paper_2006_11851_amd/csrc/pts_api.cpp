@@ -11,8 +11,6 @@
 
 using namespace pts;
 
-struct pts_ctx : public pts::Ctx {};
-
 static thread_local std::string g_create_error;
 
 template <class F>

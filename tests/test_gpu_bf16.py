@@ -1,0 +1,110 @@
+"""GPU parity of the BF16 brute-force form (MFMA distances, top-8, FP32
+re-rank) against the oracle's BF16 form, teacher-forced on the GPU's own
+FP32 projections so both sides round the same values to bf16."""
+import numpy as np
+import pytest
+
+from oracle import bf16, exact, irls, parity, vectors
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _setup(ctx, name, d, branching=8, depth=3):
+    ex, init, wl = helpers.workload_inputs(name)
+    ctx.set_exemplar_u8(ex, 0.5)
+    w = wl.w[-1]
+    ctx.build_index(w, d, branching, depth, seed=0, make_bf16=True)
+    return ex, init, wl, w
+
+
+@pytest.mark.parametrize("d", [16, 24, 64])
+def test_brute_bf16_teacher_forced_small(gpu_ctx, d):
+    print(f"case: brute_bf16 ex64_out128 d={d}", flush=True)
+    ex, init, wl, w = _setup(gpu_ctx, "ex64_out128", d, 4, 3)
+    s = wl.stride[0]
+    x = gpu_ctx.rgbs_from_u8(init)
+    nn, dist = gpu_ctx.estep(x, w, s, mode="brute_bf16")
+    Qp = _np(gpu_ctx.project(x, s)).astype(np.float64)
+    Zp = _np(gpu_ctx.exemplar_projection()).astype(np.float64)
+    nn_o, cand = bf16.brute_nn(Qp, Zp, 8)
+    ok, same, _ = parity.nn_agreement(Qp, Zp, _np(nn), nn_o)
+    assert ok >= 0.999, (ok, same)
+    # invariant: where the exact PCA-space NN is among the bf16 top 8, both agree
+    nn_pca, _ = gpu_ctx.estep(x, w, s, mode="exact_pca")
+    inside = np.array([a in c for a, c in zip(_np(nn_pca), cand)])
+    ok_in, _, _ = parity.nn_agreement(Qp[inside], Zp, _np(nn)[inside], _np(nn_pca)[inside])
+    assert ok_in >= 0.999
+    Q, Zm = helpers.query_and_exemplar(vectors.rgbs(init), vectors.rgbs(ex), w, s)
+    assert np.allclose(_np(dist), np.sqrt(parity.sqdist_rows(Q, Zm, _np(nn))), rtol=1e-5, atol=1e-6)
+
+
+def test_brute_bf16_ragged_and_rerank_full(gpu_ctx):
+    """N and nq not multiples of the 128-row stage or the 512-query block."""
+    print("case: brute_bf16 ragged + full-D re-rank", flush=True)
+    r = np.random.default_rng(7)
+    from paper_2006_11851_amd import synth
+
+    ex = synth.perspective_exemplar(9, 90, 70, 40, 2.0, 9.0)
+    init, _ = synth.row_matched_init(3, ex, 72, 48, 8)
+    gpu_ctx.set_exemplar_u8(ex, 0.5)
+    gpu_ctx.build_index(8, 32, 4, 2, seed=0, make_bf16=True)
+    x = gpu_ctx.rgbs_from_u8(init)
+    w, s = 8, 2
+    nn, _ = gpu_ctx.estep(x, w, s, mode="brute_bf16", rerank_full=1)
+    Qp = _np(gpu_ctx.project(x, s)).astype(np.float64)
+    Zp = _np(gpu_ctx.exemplar_projection()).astype(np.float64)
+    Q, Zm = helpers.query_and_exemplar(vectors.rgbs(init), vectors.rgbs(ex), w, s)
+    assert Zm.shape[0] % 128 != 0 and Q.shape[0] % 512 != 0
+    cand, _ = bf16.brute_topk(Qp, Zp, 8)
+    nn_o, _ = bf16.rerank(Q, Zm, cand)
+    ok, same, _ = parity.nn_agreement(Q, Zm, _np(nn), nn_o)
+    assert ok >= 0.999, (ok, same)
+    for k in (1, 3):
+        nnk, _ = gpu_ctx.estep(x, w, s, mode="brute_bf16", topk=k)
+        cand_k = cand[:, :k]
+        nn_ok, _ = bf16.rerank(Qp, Zp, cand_k)
+        ok, same, _ = parity.nn_agreement(Qp, Zp, _np(nnk), nn_ok)
+        assert ok >= 0.995, (k, ok, same)
+
+
+def test_brute_bf16_energy_gap_ex512_w16(gpu_ctx):
+    """Precision form at 16x16 windows (D = 1024, N = 247009, nq = 64768,
+    PCA 64): energy within 0.5 % of exhaustive full-D search."""
+    print("case: brute_bf16 energy gap ex512_out1024_w16", flush=True)
+    ex, init, wl, w = _setup(gpu_ctx, "ex512_out1024_w16", 64)
+    s = wl.stride[0]
+    x = gpu_ctx.rgbs_from_u8(init)
+    nn_e, d_e = gpu_ctx.estep(x, w, s, mode="exact_full")
+    Ee, _ = gpu_ctx.energy(d_e)
+    gaps = {}
+    for name, mode, rf in [("exact_pca", "exact_pca", 0), ("tree", "tree", 0), ("brute_bf16", "brute_bf16", 0),
+                           ("brute_bf16_full_rerank", "brute_bf16", 1)]:
+        nn_m, d_m = gpu_ctx.estep(x, w, s, mode=mode, rerank_full=rf)
+        gaps[name] = gpu_ctx.energy(d_m)[0] / Ee - 1.0
+        if name == "brute_bf16":
+            nn_b = nn_m
+    print(f"energy gaps vs exhaustive full-D search at the initial output: {gaps}", flush=True)
+    assert all(g >= -1e-6 for g in gaps.values())
+    # gated gap: G_t = E(x^{t-1}; nn_method) / E(x^{t-1}; nn_exact) - 1 along the
+    # method's own trajectory (10 iterations), maximum over t
+    xt = x.clone()
+    G = []
+    for t in range(10):
+        nn_m, d_m = gpu_ctx.estep(xt, w, s, mode="brute_bf16", rerank_full=1)
+        _, d_x = gpu_ctx.estep(xt, w, s, mode="exact_full")
+        G.append(gpu_ctx.energy(d_m)[0] / gpu_ctx.energy(d_x)[0] - 1.0)
+        gpu_ctx.mstep(nn_m, d_m, xt, w, s)
+    print(f"trajectory gaps (brute_bf16, full-D re-rank): {G}", flush=True)
+    assert max(G) <= 0.005, G
+    # sampled parity against the oracle's BF16 form
+    Qp = _np(gpu_ctx.project(x, s)).astype(np.float64)
+    Zp = _np(gpu_ctx.exemplar_projection()).astype(np.float64)
+    sample = np.sort(np.random.default_rng(1).choice(Qp.shape[0], 128, replace=False))
+    nn_o, _ = bf16.brute_nn(Qp[sample], Zp, 8)
+    ok, same, _ = parity.nn_agreement(Qp[sample], Zp, _np(nn_b)[sample], nn_o)
+    assert ok >= 0.99, (ok, same)

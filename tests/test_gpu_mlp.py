@@ -1,0 +1,186 @@
+"""Learned leaf proposal on the GPU: gradients against the FP64 oracle,
+matrix-core inference against the oracle, training, the learned search
+against the oracle (teacher-forced on the GPU's proposals), and the gain of
+the trained network over the method without it."""
+import numpy as np
+import pytest
+
+from oracle import bf16 as obf16
+from oracle import mlp as omlp
+from oracle import parity, tree
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _tensor_rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.fixture(scope="module")
+def mlp_setup(gpu_ctx):
+    import torch
+
+    r = np.random.default_rng(0)
+    n_in, h, n_out, n = 64, 256, 1024, 192
+    gpu_ctx.set_exemplar_u8(np.zeros((16, 16, 3), np.uint8), 0.5)  # fresh context state
+    gpu_ctx.mlp_init(n_in, h, n_out, seed=3)
+    theta = _gpu_theta = gpu_ctx.mlp_get_weights().astype(np.float64)
+    scale = r.uniform(0.5, 2.0, n_in).astype(np.float32)
+    gpu_ctx.mlp_set_input_scale(scale)
+    q = r.normal(size=(n, n_in)).astype(np.float32)
+    lab = r.integers(0, n_out, n).astype(np.int32)
+    return dict(ctx=gpu_ctx, theta=theta, scale=scale, q=q, lab=lab, dims=(n_in, h, n_out),
+                qt=torch.from_numpy(q).cuda(), lt=torch.from_numpy(lab).cuda())
+
+
+def test_mlp_gradients_fp32_match_oracle(mlp_setup):
+    S = mlp_setup
+    ctx, (n_in, h, n_out) = S["ctx"], S["dims"]
+    loss, g = ctx.mlp_loss_grad(S["qt"], S["lt"], bf16=False)
+    lo, go = omlp.loss_and_grad(S["theta"], S["q"].astype(np.float64), S["lab"], n_in, h, n_out,
+                                S["scale"].astype(np.float64))
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    parts_g = omlp.unpack(_np(g).astype(np.float64), n_in, h, n_out)
+    parts_o = omlp.unpack(go, n_in, h, n_out)
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "W3", "b3"], parts_g, parts_o):
+        assert _tensor_rel(a, b) <= 1e-4, name
+
+
+def test_mlp_gradients_bf16_match_oracle(mlp_setup):
+    S = mlp_setup
+    ctx, (n_in, h, n_out) = S["ctx"], S["dims"]
+    loss, g = ctx.mlp_loss_grad(S["qt"], S["lt"], bf16=True)
+    lo, go = omlp.loss_and_grad(S["theta"], S["q"].astype(np.float64), S["lab"], n_in, h, n_out,
+                                S["scale"].astype(np.float64))
+    assert abs(loss - lo) <= 2e-2 * abs(lo)
+    assert _tensor_rel(_np(g).astype(np.float64), go) <= 2e-2
+
+
+def test_mlp_forward_and_matrix_core_proposals(mlp_setup):
+    S = mlp_setup
+    ctx, (n_in, h, n_out) = S["ctx"], S["dims"]
+    logits = _np(ctx.mlp_forward(S["qt"], n_out, bf16=False)).astype(np.float64)
+    lo, _ = omlp.forward(S["theta"], S["q"].astype(np.float64), n_in, h, n_out, S["scale"].astype(np.float64))
+    assert np.abs(logits - lo).max() <= 1e-4 * max(1.0, np.abs(lo).max())
+    leaves, margin = ctx.mlp_propose(S["qt"], 4)
+    top_o, m_o = omlp.propose(lo, 4)
+    L = _np(leaves)
+    assert np.mean(L[:, 0] == top_o[:, 0]) >= 0.95
+    # every GPU proposal that differs from the oracle's is a near tie in the oracle's logits
+    for qi in range(L.shape[0]):
+        for t in range(4):
+            if L[qi, t] != top_o[qi, t]:
+                assert abs(lo[qi, L[qi, t]] - lo[qi, top_o[qi, t]]) <= 0.05 * max(1.0, abs(lo[qi, top_o[qi, t]]))
+    assert np.abs(_np(margin) - m_o).max() <= 0.03
+
+
+def test_adam_step_matches_oracle(mlp_setup):
+    import torch
+
+    S = mlp_setup
+    ctx, (n_in, h, n_out) = S["ctx"], S["dims"]
+    ctx.mlp_init(n_in, h, n_out, seed=5)
+    ctx.mlp_set_input_scale(S["scale"])
+    th0 = ctx.mlp_get_weights().astype(np.float64)
+    # one full-batch step: the sampler draws indices with replacement, so use a batch of 1 row repeated
+    q1 = torch.from_numpy(np.repeat(S["q"][:1], 7, axis=0)).cuda()
+    l1 = torch.from_numpy(np.repeat(S["lab"][:1], 7)).cuda()
+    ctx.mlp_train(q1, l1, 1, batch=5, lr=1e-3, bf16=False, log_every=0)
+    th1 = ctx.mlp_get_weights().astype(np.float64)
+    _, g = omlp.loss_and_grad(th0, S["q"][:1].astype(np.float64), S["lab"][:1], n_in, h, n_out,
+                              S["scale"].astype(np.float64))
+    exp, _, _ = omlp.adam_step(th0, g, np.zeros_like(th0), np.zeros_like(th0), 1, 1e-3)
+    # the first Adam step moves each parameter by ~lr * sign(g) where g is not tiny
+    big = np.abs(g) > 1e-6 * np.abs(g).max()
+    assert np.abs((th1 - th0)[big] - (exp - th0)[big]).max() <= 2e-4
+
+
+@pytest.fixture(scope="module")
+def learned_c1(gpu_ctx):
+    """Index with a 32-way depth-2 tree at the 64^2 -> 128^2 scale and a
+    network trained on pairs from three plain iterations."""
+    from paper_2006_11851_amd import training
+
+    ex, init, wl = helpers.workload_inputs("ex64_out128")
+    ctx = gpu_ctx
+    ctx.set_exemplar_u8(ex, 0.5)
+    info = ctx.build_index(8, 16, 8, 2, seed=0, make_bf16=True)
+    x0 = ctx.rgbs_from_u8(init)
+    q, lab = training.collect_pairs(ctx, x0, 8, 4, 6)
+    ctx.mlp_init(16, 256, info.n_leaves, seed=1)
+    untrained = ctx.mlp_get_weights()
+    log = training.train(ctx, q, lab, epochs=200, batch=1024, lr=2e-3, log_every=20)
+    return dict(ctx=ctx, ex=ex, init=init, info=info, x0=x0, log=log, untrained=untrained, q=q, lab=lab)
+
+
+def test_training_reduces_loss_and_learns_leaves(learned_c1):
+    S = learned_c1
+    log = S["log"]
+    print("training loss:", log[:3], "...", log[-3:], flush=True)
+    assert log[-1] < 0.5 * log[0]
+    leaves, _ = S["ctx"].mlp_propose(S["q"], 4)
+    hit = (_np(leaves) == _np(S["lab"])[:, None]).any(axis=1).mean()
+    print("top-4 contains the exact-NN leaf:", hit, flush=True)
+    assert hit >= 0.8
+
+
+@pytest.mark.parametrize("mode", ["learned", "learned_bf16"])
+def test_learned_search_teacher_forced(learned_c1, mode):
+    S = learned_c1
+    ctx = S["ctx"]
+    print(f"case: {mode} ex64_out128", flush=True)
+    x = S["x0"]
+    nn, dist, st = ctx.estep(x, 8, 4, mode=mode, stats=True)
+    qp = ctx.project(x, 4)
+    leaves, margin = ctx.mlp_propose(qp, 4)
+    dleaf = ctx.descend(qp)
+    g = ctx.export_index()
+    t = helpers.dict_to_oracle_tree(g)
+    Qp = _np(qp).astype(np.float64)
+    Zp = _np(ctx.exemplar_projection()).astype(np.float64)
+    L, M, DL = _np(leaves), _np(margin), _np(dleaf)
+    lists = [[int(DL[i])] if not (M[i] >= 0.2) else list(L[i]) for i in range(L.shape[0])]
+    assert st.fallbacks == sum(1 for i in range(L.shape[0]) if not (M[i] >= 0.2))
+    if mode == "learned":
+        nn_o, _ = tree.search_leaves(Qp, Zp, t, lists)
+    else:
+        cand = []
+        for i, ls in enumerate(lists):
+            mem = np.concatenate([t.leaf_members(l) for l in ls])
+            ids, _ = obf16.brute_topk(Qp[i : i + 1], Zp[mem], 8)
+            cand.append(mem[ids[0]])
+        nn_o, _ = obf16.rerank(Qp, Zp, cand)
+    ok, same, _ = parity.nn_agreement(Qp, Zp, _np(nn), nn_o)
+    assert ok >= 0.999, (ok, same)
+
+
+def test_learned_gain_over_tree_and_untrained(learned_c1):
+    """Energy gap to exhaustive search on a held-out initial output (another
+    init seed): trained proposals against the plain tree and an untrained net."""
+    from paper_2006_11851_amd import synth
+
+    S = learned_c1
+    ctx = S["ctx"]
+    init2, _ = synth.row_matched_init(7, S["ex"], 128, 128, 8)
+    x = ctx.rgbs_from_u8(init2)
+    _, d_e = ctx.estep(x, 8, 4, mode="exact_full")
+    Ee = ctx.energy(d_e)[0]
+
+    def gap(mode):
+        _, d = ctx.estep(x, 8, 4, mode=mode)
+        return ctx.energy(d)[0] / Ee - 1.0
+
+    trained = ctx.mlp_get_weights()
+    g_learned = gap("learned")
+    g_tree = gap("tree")
+    ctx.mlp_set_weights(S["untrained"])
+    g_untrained = gap("learned")
+    ctx.mlp_set_weights(trained)
+    print(f"gaps: learned {g_learned:.4f} tree {g_tree:.4f} untrained {g_untrained:.4f}", flush=True)
+    assert g_learned < g_tree
+    assert g_learned < g_untrained
