@@ -1,10 +1,13 @@
-"""Benchmark: NN queries/s and ms/iteration of the search + blend hot path.
+"""Benchmark: NN queries/s and ms/iteration, BF16 + learned proposal against
+the plain FP32 tree search, at the finest level of a synthetic workload.
 
-One step = one iteration at the finest level: E-step (projection, search,
-winner distance) + M-step (2x2 patch blend) + energy, over the whole output
-image, inputs resident in HBM.  Prints one JSON line.
+One step = one iteration over the whole output image: E-step (projection,
+search, winner distance) + M-step (2x2 patch blend) + energy, with inputs
+resident in HBM.  Both forms run from the same output image; the energy gap
+of each to exhaustive full-dimension search is measured on a fixed random
+1/16 of the queries before and after the timed steps.  Prints one JSON line.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--form FORM]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
@@ -19,45 +22,38 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS = {  # MI355X published peaks
-    "hbm_gbs": 8000.0,
-    "bf16_tflops": 2500.0,
-    "fp32_vector_tflops": 157.3,
-}
+PEAK = {"bf16": 2500.0, "fp32_vector": 157.3, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s (MI355X)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ex256_out512")
-    ap.add_argument("--form", default="tree", choices=["tree", "exact_pca", "brute_bf16", "learned", "learned_bf16"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ex1024_out2048")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--train-iters", type=int, default=6)
+    ap.add_argument("--train-per-iter", type=int, default=65536)
+    ap.add_argument("--epochs", type=float, default=6.0)
+    ap.add_argument("--residual", type=int, default=1)
+    ap.add_argument("--rerank-full", type=int, default=1)
+    ap.add_argument("--only", default="", help="run one form only (tree or learned_bf16)")
     return ap.parse_args()
 
 
-def kernel_algorithmic(form, name, nq, N, d, D, leaf_mean, w, H, W):
-    """(bound, algorithmic units per launch, unit) for the kernels we report."""
-    if name == "leaf_scan_f32":
-        # 3 flops (sub, mul, add) per (query, member, dimension)
-        return "alu", 3.0 * nq * leaf_mean * d, "TFLOP/s"
-    if name == "mstep_patch2x2":
-        # per pixel: (w/s)^2 covering windows x 16 B gathered + 16 B read/written;
-        # per window: 8 B of (id, distance)
-        return "hbm", None, "GB/s"
-    return None, None, None
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
 
-    from paper_2006_11851_amd import pts, synth
+    from paper_2006_11851_amd import pts, synth, training
 
     wl = synth.workload(a.workload)
     ex = wl.exemplar()
@@ -68,87 +64,155 @@ def main():
     t0 = time.time()
     info = ctx.build_index(w, wl.pca_dims, wl.branching, wl.depth, seed=0, make_bf16=True)
     build_s = time.time() - t0
+    log(f"index: N={info.N} d={info.d} leaves={info.n_leaves} mean leaf {info.leaf_mean:.1f} "
+        f"retained {info.retained_variance:.4f} in {build_s:.1f} s")
     init, _ = synth.row_matched_init(wl.init_seed, ex, Hout, Hout, w)
     x0 = ctx.rgbs_from_u8(init, 0.5)
-    x = x0.clone()
     nq = ctx.nq(Hout, Hout, w, s)
-    nn = torch.empty(nq, dtype=torch.int32, device="cuda")
-    dist = torch.empty(nq, dtype=torch.float32, device="cuda")
 
-    def step():
-        ctx.estep(x, w, s, mode=a.form, nn=nn, dist=dist)
-        ctx.mstep(nn, dist, x, w, s)
-        return ctx.energy(dist)
+    # learned proposal: pairs from the plain method, labelled by exhaustive search
+    t0 = time.time()
+    q, lab = training.collect_pairs_sampled(ctx, x0, w, s, a.train_iters, min(a.train_per_iter, nq), seed=1)
+    ctx.mlp_init(info.d, 256, info.n_leaves, seed=0)
+    losses = training.train(ctx, q, lab, epochs=a.epochs, batch=4096, lr=2e-3, log_every=50)
+    train_s = time.time() - t0
+    leaves_hit = None
+    prop, _ = ctx.mlp_propose(q, 4)
+    leaves_hit = float((prop == lab[:, None]).any(dim=1).float().mean())
+    log(f"MLP: {q.shape[0]} pairs, loss {losses[0]:.3f} -> {losses[-1]:.3f}, top-4 train recall {leaves_hit:.3f}, "
+        f"{train_s:.1f} s")
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    energies = []
-    for _ in range(a.steps):
-        energies.append(step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
-    ms_per_step = 1000.0 * elapsed / a.steps
-    value = nq / (elapsed / a.steps)
+    sample = torch.randperm(nq, generator=torch.Generator().manual_seed(16))[: nq // 16].to(torch.int32).cuda()
 
-    # dominant kernel and its roofline
-    kern = {k: v for k, v in prof.items()}
-    dom = max(kern, key=lambda k: kern[k][0])
-    dom_ms = kern[dom][0] / max(1, kern[dom][1])
-    roof = None
-    leaf_mean = info.leaf_mean
-    if dom == "leaf_scan_f32":
-        flops = 3.0 * nq * leaf_mean * info.d
-        ach = flops / (dom_ms * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": PEAKS["fp32_vector_tflops"],
-                "unit": "TFLOP/s", "frac": ach / PEAKS["fp32_vector_tflops"], "traffic": None}
-    elif dom == "mstep_patch2x2":
-        cover = (w // s) ** 2
-        byts = Hout * Hout * (cover * 16 + 32) + (Hout * Hout / 4) * cover * 8
-        ach = byts / (dom_ms * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-                "frac": ach / PEAKS["hbm_gbs"], "traffic": None}
-    else:
-        roof = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": None}
+    def gap(x, nn_dist):
+        _, d_ex = ctx.exact_search(x, w, s, sample)
+        d_m = nn_dist[sample.long()].contiguous()
+        return ctx.energy(d_m)[0] / ctx.energy(d_ex)[0] - 1.0
 
-    cpu = None
-    if not a.no_cpu:
-        cpu = cpu_baseline(ctx, ex, init, w, s, a.cpu_seconds)
+    forms = {
+        "plain_fp32_tree": dict(mode="tree"),
+        "bf16_learned": dict(mode="learned_bf16", residual=a.residual, rerank_full=a.rerank_full, n_proposals=4,
+                             margin=0.2),
+    }
+    if a.only:
+        forms = {k: v for k, v in forms.items() if v["mode"] == a.only}
+    res = {}
+    for name, kw in forms.items():
+        x = x0.clone()
+        nn = torch.empty(nq, dtype=torch.int32, device="cuda")
+        dist = torch.empty(nq, dtype=torch.float32, device="cuda")
+        ctx.estep(x, w, s, nn=nn, dist=dist, **kw)
+        g0 = gap(x, dist)
 
+        def step():
+            ctx.estep(x, w, s, nn=nn, dist=dist, **kw)
+            ctx.mstep(nn, dist, x, w, s)
+            return ctx.energy(dist)
+
+        for _ in range(a.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E = [step() for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        _, _, st = ctx.estep(x, w, s, nn=nn, dist=dist, stats=True, **kw)
+        g1 = gap(x, dist)
+        res[name] = dict(value=nq * a.steps / el, ms_per_step=1000 * el / a.steps, gap_first=g0, gap_last=g1,
+                         fallback_rate=st.fallbacks / nq, energy_last=E[-1][0],
+                         kernels_ms_per_step={k: v[0] / a.steps for k, v in prof.items()},
+                         launches={k: v[1] for k, v in prof.items()}, x=x)
+        log(f"{name}: {res[name]['value']:.3e} q/s, {res[name]['ms_per_step']:.3f} ms/step, gap {g0:.4f} -> {g1:.4f}")
+
+    head = res.get("bf16_learned") or res["plain_fp32_tree"]
+    kern = head["kernels_ms_per_step"]
+    roof = roofline(ctx, head, info, nq, a, forms)
+    cpu = None if a.no_cpu else cpu_baseline(ctx, ex, init, w, s, a.cpu_seconds)
     out = {
         "metric": "NN queries/s + ms/iteration",
-        "value": value,
+        "value": head["value"],
         "unit": "NN queries/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if "bf16_learned" in res else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload} finest level: exemplar {wl.ex_size}^2, output {Hout}^2, "
-                               f"w={w}, stride={s}, N={info.N}, nq={nq}, d={info.d}, "
-                               f"tree b{wl.branching} L{wl.depth}", "form": a.form},
-        "kernels_ms_per_step": {k: v[0] / a.steps for k, v in kern.items()},
-        "energy_last": energies[-1][0],
+        "config": {
+            "workload": f"{a.workload} finest level: exemplar {wl.ex_size}^2, output {Hout}^2, w={w}, stride={s}, "
+                        f"N={info.N}, nq={nq}, PCA {info.d}, k-means tree b{wl.branching} L{wl.depth} "
+                        f"({info.n_leaves} leaves)",
+            "form": "BF16 MFMA leaf scans of the MLP's top-4 leaves (tree below margin 0.2), top-8, FP32 re-rank"
+                    + (" in full D" if a.rerank_full else " in PCA space")
+                    + (", residual-energy ranking" if a.residual else ""),
+        },
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "x"} for k, v in res.items()},
+        "speedup_vs_plain_fp32": (res["bf16_learned"]["value"] / res["plain_fp32_tree"]["value"])
+        if len(res) == 2 else None,
         "index_build_s": build_s,
+        "mlp_training_s": train_s,
+        "mlp_pairs": int(q.shape[0]),
+        "mlp_top4_train_recall": leaves_hit,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
+def roofline(ctx, head, info, nq, a, forms):
+    """Dominant kernel of the reported form against its bound."""
+    kern = head["kernels_ms_per_step"]
+    launches = head["launches"]
+    dom = max(kern, key=lambda k: kern[k])
+    per_launch_ms = kern[dom] * a.steps / max(1, launches[dom])
+    d, h, L = info.d, 256, info.n_leaves
+    dk = -(-d // 32) * 32
+    if dom == "mlp_out_topk_mfma":
+        flops = 2.0 * h * (-(-L // 32) * 32) * nq
+        bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
+    elif dom == "mlp_hidden_mfma":
+        flops = 2.0 * h * h * nq
+        bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
+    elif dom == "leaf_scan_bf16":
+        flops = 2.0 * dk * scanned_pairs(ctx, head, info, nq)
+        bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
+    elif dom == "leaf_scan_f32":
+        flops = 3.0 * d * nq * info.leaf_mean
+        bound, peak, unit = "alu", PEAK["fp32_vector"], "TFLOP/s"
+    else:
+        return {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "ms_per_launch": per_launch_ms}
+    ach = flops / (per_launch_ms * 1e-3) / 1e12
+    return {"kernel": dom, "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": None, "ms_per_launch": per_launch_ms, "algorithmic_flops_per_launch": flops}
+
+
+def scanned_pairs(ctx, head, info, nq):
+    """(query, exemplar) pairs the learned BF16 scan visits for the final image."""
+    import torch
+
+    x = head["x"]
+    g = ctx.export_index()
+    sizes = torch.from_numpy(np.diff(g["leaf_off"])).cuda()
+    qp = ctx.project(x, 2)
+    prop, margin = ctx.mlp_propose(qp, 4)
+    dleaf = ctx.descend(qp)
+    fb = ~(margin >= 0.2)
+    tot = sizes[prop.long()].sum(dim=1)
+    tot = torch.where(fb, sizes[dleaf.long()], tot)
+    return float(tot.sum())
+
+
 def cpu_baseline(ctx, ex, init, w, s, seconds):
-    """The FP64 oracle's search (PCA projection, tree descent, leaf scan,
-    winner distance) timed on a bounded sample of the same queries, with the
+    """The FP64 oracle's search (projection, tree descent, leaf scan, full-D
+    winner distance) on a bounded random sample of the same queries, with the
     GPU's basis and tree, BLAS limited to one thread."""
     from threadpoolctl import threadpool_limits
 
@@ -163,20 +227,19 @@ def cpu_baseline(ctx, ex, init, w, s, seconds):
     Q = vectors.query_matrix(X, w, s)
     with threadpool_limits(1):
         Zp = pca.project(Zm, g["mu"], g["basis"])
-        r = np.random.default_rng(0)
-        order = r.permutation(Q.shape[0])
+        order = np.random.default_rng(0).permutation(Q.shape[0])
         done = 0
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < seconds and done < Q.shape[0]:
-            idx = order[done : done + 256]
+            idx = order[done : done + 64]
             Qp = pca.project(Q[idx], g["mu"], g["basis"])
             nn, _, _, _ = tree.tree_nn(Qp, Zp, t)
             solve.winner_distance(Q[idx], Zm, nn)
             done += idx.size
         el = time.perf_counter() - t0
     return {"value": done / el, "unit": "NN queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} random queries of the same image, oracle tree search (projection, descent, "
-                      f"leaf scan, full-D winner distance) with the GPU-built basis and tree, FP64, "
+            "sample": f"{done} random queries of the initial output image, oracle tree search (projection, descent, "
+                      f"leaf scan, full-D winner distance) with the GPU-built basis and tree, FP64, one thread, "
                       f"{el:.1f} s"}
 
 

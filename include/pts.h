@@ -165,6 +165,10 @@ typedef struct pts_estep_params {
   int rerank_full; /* 1: re-rank BF16 candidates by full-D distance; 0: PCA space */
   int n_proposals; /* leaves proposed by the MLP (4; 1..8) */
   float margin;    /* softmax margin p1 - p2 below which the tree is used (0.2) */
+  int residual;    /* 1: rank PCA-space candidates by ||q' - z'||^2 + ||z - mu||^2 - ||z'||^2,
+                      i.e. also charge each exemplar window its energy outside the PCA
+                      subspace (leaf scans, BF16 scans and the PCA-space re-rank); 0: plain
+                      PCA-space distance */
 } pts_estep_params;
 
 typedef struct pts_estep_stats {
@@ -180,6 +184,13 @@ typedef struct pts_estep_stats {
  * [nq]; dist: float32 [nq].  st_host may be NULL (then no synchronisation). */
 int pts_estep(pts_ctx* ctx, const float* x_rgbs, int H, int W, const pts_estep_params* p, int32_t* nn,
               float* dist, pts_estep_stats* st_host);
+
+/* Exhaustive full-D search (the exact reference of Eq. 4's z_q) for the
+ * listed output windows only: qids int32 [n] (window ids, each < nq of the
+ * grid); nn int32 [n] and dist float32 [n] (||x_q - z_nn||, FP32), ties to
+ * the lowest exemplar id.  Used to judge approximate searches on a sample. */
+int pts_exact_search(pts_ctx* ctx, const float* x_rgbs, int H, int W, int w, int stride, const int32_t* qids,
+                     int64_t n, int32_t* nn, float* dist);
 
 /* PCA projection of the output windows: qproj float32 [nq][d] (row q =
  * B^T (x_q - mu)).  The first step of every PCA-space search. */
@@ -232,6 +243,7 @@ typedef struct pts_solve_params {
   int coarse_mode;                /* search mode at the coarser levels */
   int topk, rerank_full, n_proposals;
   float margin;
+  int residual;
   float r, delta;
   int patch_offset;
   float guidance_weight;

@@ -26,12 +26,24 @@ def round_bf16(a) -> np.ndarray:
     return rounded.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def brute_topk(Qp, Zp, k: int = 8):
-    """Top-k exemplar ids per query by the distance of the bf16-rounded vectors."""
-    return exact.topk(round_bf16(Qp), round_bf16(Zp), k)
+def brute_topk(Qp, Zp, k: int = 8, offset=None):
+    """Top-k exemplar ids per query by the distance of the bf16-rounded
+    vectors (plus an optional per-exemplar offset, see ``residual``)."""
+    return exact.topk(round_bf16(Qp), round_bf16(Zp), k, offset=offset)
 
 
-def rerank(Q, Z, cand):
+def residual(Zm, mu, Zp):
+    """Energy of each exemplar window outside the PCA subspace,
+    ||z - mu||^2 - ||z'||^2 (>= 0).  Adding it to the PCA-space distance
+    ranks candidates by an estimate of the full-dimension distance that is
+    unbiased when the two windows' residuals are uncorrelated (the query's
+    own residual energy is a constant per query)."""
+    A = np.asarray(Zm, dtype=np.float64) - np.asarray(mu, dtype=np.float64)
+    P = np.asarray(Zp, dtype=np.float64)
+    return np.maximum(np.einsum("ij,ij->i", A, A) - np.einsum("ij,ij->i", P, P), 0.0)
+
+
+def rerank(Q, Z, cand, offset=None):
     """Re-rank candidate ids with unrounded vectors; returns (nn, d2)."""
     Q = np.asarray(Q, dtype=np.float64)
     Z = np.asarray(Z, dtype=np.float64)
@@ -42,15 +54,17 @@ def rerank(Q, Z, cand):
         c = np.asarray(cand[q], dtype=np.int64)
         diff = Z[c] - Q[q][None, :]
         dd = np.einsum("ij,ij->i", diff, diff)
+        if offset is not None:
+            dd = dd + np.asarray(offset, dtype=np.float64)[c]
         o = np.lexsort((c, dd))[0]
         nn[q] = c[o]
         d2[q] = dd[o]
     return nn, d2
 
 
-def brute_nn(Qp, Zp, k: int = 8, Q_full=None, Z_full=None):
+def brute_nn(Qp, Zp, k: int = 8, Q_full=None, Z_full=None, offset=None):
     """BF16 top-k then FP64 re-rank in PCA space (or full D if given)."""
-    cand, _ = brute_topk(Qp, Zp, k)
+    cand, _ = brute_topk(Qp, Zp, k, offset=offset)
     if Q_full is not None:
         return rerank(Q_full, Z_full, cand)[0], cand
-    return rerank(Qp, Zp, cand)[0], cand
+    return rerank(Qp, Zp, cand, offset=offset)[0], cand

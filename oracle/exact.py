@@ -24,10 +24,12 @@ def _direct_d2(q: np.ndarray, Z: np.ndarray, idx: np.ndarray) -> np.ndarray:
     return np.einsum("ij,ij->i", diff, diff)
 
 
-def topk_direct(Q: np.ndarray, Z: np.ndarray, k: int = 1, block: int = 0):
+def topk_direct(Q: np.ndarray, Z: np.ndarray, k: int = 1, block: int = 0, offset=None):
     """Exact k nearest (squared distance, id) per query by the direct form.
 
-    Returns (ids int64 [nq][k], d2 float64 [nq][k]) sorted by (d2, id).
+    ``offset`` (optional, [N]) is added to every exemplar's squared distance
+    before ranking.  Returns (ids int64 [nq][k], d2 float64 [nq][k]) sorted by
+    (d2, id).
     """
     Q = np.asarray(Q, dtype=np.float64)
     Z = np.asarray(Z, dtype=np.float64)
@@ -44,6 +46,8 @@ def topk_direct(Q: np.ndarray, Z: np.ndarray, k: int = 1, block: int = 0):
         for c in range(D):
             t = Qb[:, c][:, None] - Z[:, c][None, :]
             acc += t * t
+        if offset is not None:
+            acc += np.asarray(offset, dtype=np.float64)[None, :]
         # lexicographic (d2, id): stable sort on d2 keeps ids ascending
         order = np.argsort(acc, axis=1, kind="stable")[:, :k]
         ids[b0 : b0 + block] = order
@@ -51,7 +55,7 @@ def topk_direct(Q: np.ndarray, Z: np.ndarray, k: int = 1, block: int = 0):
     return ids, d2s
 
 
-def topk(Q: np.ndarray, Z: np.ndarray, k: int = 1, block: int = 0):
+def topk(Q: np.ndarray, Z: np.ndarray, k: int = 1, block: int = 0, offset=None):
     """Same result as :func:`topk_direct`, using a proven-safe BLAS prefilter."""
     Q = np.asarray(Q, dtype=np.float64)
     Z = np.asarray(Z, dtype=np.float64)
@@ -60,6 +64,7 @@ def topk(Q: np.ndarray, Z: np.ndarray, k: int = 1, block: int = 0):
     k = min(k, N)
     zn = np.einsum("ij,ij->i", Z, Z)
     zmax = zn.max() if N else 0.0
+    off = np.zeros(N) if offset is None else np.asarray(offset, dtype=np.float64)
     if block <= 0:
         block = max(1, int(1.6e7 // max(1, N)))
     # |expanded - direct| <= gamma * (||q||^2 + ||z||^2), gamma = (D + 4) eps
@@ -69,12 +74,12 @@ def topk(Q: np.ndarray, Z: np.ndarray, k: int = 1, block: int = 0):
     for b0 in range(0, nq, block):
         Qb = Q[b0 : b0 + block]
         qn = np.einsum("ij,ij->i", Qb, Qb)
-        dexp = qn[:, None] + zn[None, :] - 2.0 * (Qb @ Z.T)
+        dexp = qn[:, None] + zn[None, :] - 2.0 * (Qb @ Z.T) + off[None, :]
         kth = np.partition(dexp, k - 1, axis=1)[:, k - 1]
         for r in range(Qb.shape[0]):
             bound = 2.0 * gamma * (qn[r] + zmax)
             cand = np.nonzero(dexp[r] <= kth[r] + 2.0 * bound)[0]
-            d = _direct_d2(Qb[r], Z, cand)
+            d = _direct_d2(Qb[r], Z, cand) + off[cand]
             o = np.lexsort((cand, d))[:k]
             ids[b0 + r] = cand[o]
             d2s[b0 + r] = d[o]

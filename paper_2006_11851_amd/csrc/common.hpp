@@ -84,6 +84,8 @@ struct Index {
   DevMem znorm;                // f32 [N] ||z'||^2 (leaf order)
   DevMem zbf;                  // bf16 [N][dk], leaf order
   DevMem zbnorm;               // f32 [N] ||bf16(z')||^2
+  DevMem zres;                 // f32 [N] ||z - mu||^2 - ||z'||^2: energy outside the PCA subspace
+  DevMem zbnorm_res;           // f32 [N] zbnorm + zres
   DevMem perm;                 // i32 [N] leaf position -> exemplar id
   DevMem leaf_of_ex;           // i32 [N] exemplar id -> leaf
   DevMem leaf_off;             // i32 [n_leaves + 1]

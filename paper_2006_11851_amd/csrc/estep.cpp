@@ -80,7 +80,7 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       BucketBufs b = bucket_buffers(c, nq, ix->tree.n_leaves(), 64, &max_tiles);
       launch_bucket(c, leaf, nq, ix->tree.n_leaves(), 64, b);
       launch_leaf_scan_f32(c, qp, ix->dp, ix->zproj.as<float>(), ix->perm.as<int32_t>(), ix->leaf_off.as<int32_t>(),
-                           b, max_tiles, 1, nn, nullptr);
+                           b, max_tiles, 1, p.residual ? ix->zres.as<float>() : nullptr, nn, nullptr);
       break;
     }
     case PTS_MODE_BRUTE_BF16: {

@@ -14,15 +14,17 @@ void search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   const int S = brute_splits(nq);
   float* pd = c->buf<float>("bb_pd", (size_t)S * nq * 8);
   int32_t* pi = c->buf<int32_t>("bb_pi", (size_t)S * nq * 8);
-  launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), ix.zbnorm.as<float>(), ix.N, ix.dk, S, pd, pi);
+  const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();
+  const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
+  launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, ix.N, ix.dk, S, pd, pi);
   if (p.rerank_full) {
     int32_t* cand = c->buf<int32_t>("bb_cand", (size_t)nq * 8);
     int32_t* tmp = c->buf<int32_t>("bb_nn_pca", (size_t)nq);
-    launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(),
+    launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
                             ix.perm.as<int32_t>(), ix.N, cand, tmp);
     launch_rerank_full(c, x, H, W, ix.w, p.stride, ex.img, ex.Hz, ex.Wz, cand, k, nq, nn);
   } else {
-    launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(),
+    launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
                             ix.perm.as<int32_t>(), ix.N, nullptr, nn);
   }
 }
@@ -52,7 +54,7 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     int32_t* pid = c->buf<int32_t>("ln_pair_id", (size_t)nq * P);
     float* pdd = c->buf<float>("ln_pair_d", (size_t)nq * P);
     launch_leaf_scan_f32(c, qp, ix.dp, ix.zproj.as<float>(), ix.perm.as<int32_t>(), ix.leaf_off.as<int32_t>(), b,
-                         max_tiles, P, pid, pdd);
+                         max_tiles, P, p.residual ? ix.zres.as<float>() : nullptr, pid, pdd);
     launch_merge_pairs_f32(c, pair_leaf, pid, pdd, nq, P, nn);
   } else {
     PTS_REQUIRE(ix.has_bf16, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
@@ -62,16 +64,18 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     launch_queries_bf16(c, qp, nq, ix.dp, ix.dk, qb);
     float* pdd = c->buf<float>("ln_pair_cd", (size_t)nq * P * 8);
     int32_t* pii = c->buf<int32_t>("ln_pair_ci", (size_t)nq * P * 8);
-    launch_leaf_scan_bf16(c, qb, P, ix.zbf.as<uint16_t>(), ix.zbnorm.as<float>(), ix.dk, ix.leaf_off.as<int32_t>(), b,
-                          max_tiles, pdd, pii);
+    const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();
+    const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
+    launch_leaf_scan_bf16(c, qb, P, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b, max_tiles, pdd,
+                          pii);
     if (p.rerank_full) {
       int32_t* cand = c->buf<int32_t>("bb_cand", (size_t)nq * 8);
       int32_t* tmp = c->buf<int32_t>("bb_nn_pca", (size_t)nq);
-      launch_merge_rerank_pca(c, pdd, pii, nq, P, P, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(),
+      launch_merge_rerank_pca(c, pdd, pii, nq, P, P, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
                               ix.perm.as<int32_t>(), ix.N, cand, tmp);
       launch_rerank_full(c, x, H, W, ix.w, p.stride, ex.img, ex.Hz, ex.Wz, cand, k, nq, nn);
     } else {
-      launch_merge_rerank_pca(c, pdd, pii, nq, P, P, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(),
+      launch_merge_rerank_pca(c, pdd, pii, nq, P, P, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
                               ix.perm.as<int32_t>(), ix.N, nullptr, nn);
     }
   }

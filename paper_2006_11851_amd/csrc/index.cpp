@@ -186,7 +186,7 @@ void grow_tree(Ctx* c, const float* P, int64_t N, int d, int dp, int branching, 
       int32_t* counts = static_cast<int32_t*>(d_counts.ensure(c, (size_t)ncent * 4));
       launch_zero_i32(c, reinterpret_cast<int32_t*>(sums), (int64_t)ncent * dp * 2);
       launch_zero_i32(c, counts, ncent);
-      launch_kmeans_accumulate(c, P, dp, dm, m, dso, d_cent_off.as<int32_t>(), assign, sums, counts);
+      launch_kmeans_accumulate(c, P, dp, dm, m, dso, d_cent_off.as<int32_t>(), assign, sums, counts, ncent);
       int32_t changed_h = 0;
       PTS_HIP(hipMemcpyAsync(&changed_h, changed, 4, hipMemcpyDeviceToHost, c->stream));
       download(c, sums_h, sums, (size_t)ncent * dp);
@@ -285,7 +285,7 @@ int tree_depth(const HostTree& t) {
 
 // Device copies of everything the search needs, from the host basis/tree and
 // the exemplar projected in original order (zorig, [N][dp]).
-void finalize_device(Ctx* c, Index& ix, const float* zorig, bool make_bf16) {
+void finalize_device(Ctx* c, Index& ix, ExView ex, const float* zorig, bool make_bf16) {
   const int64_t N = ix.N;
   const HostTree& t = ix.tree;
   std::vector<float> cf((size_t)t.n_nodes() * ix.dp, 0.f);
@@ -306,11 +306,18 @@ void finalize_device(Ctx* c, Index& ix, const float* zorig, bool make_bf16) {
   float* zn = static_cast<float*>(ix.znorm.ensure(c, (size_t)N * 4));
   launch_permute_rows(c, zorig, ix.perm.as<int32_t>(), N, ix.dp, zl, zn);
   ix.has_bf16 = make_bf16;
+  float* cn = c->buf<float>("ix_cnorm", (size_t)N);
+  launch_centered_norm(c, ex.img, ex.Hz, ex.Wz, ix.w, ix.mu_f.as<float>(), cn);
+  float* zr = static_cast<float*>(ix.zres.ensure(c, (size_t)N * 4));
   if (make_bf16) {
     ix.dk = (int)round_up(ix.d, 32);
     uint16_t* zb = static_cast<uint16_t*>(ix.zbf.ensure(c, (size_t)N * ix.dk * 2));
     float* zbn = static_cast<float*>(ix.zbnorm.ensure(c, (size_t)N * 4));
     launch_to_bf16_rows(c, zl, N, ix.dp, ix.dk, zb, zbn);
+    float* zbr = static_cast<float*>(ix.zbnorm_res.ensure(c, (size_t)N * 4));
+    launch_residual(c, cn, ix.perm.as<int32_t>(), zn, zbn, N, zr, zbr);
+  } else {
+    launch_residual(c, cn, ix.perm.as<int32_t>(), zn, nullptr, N, zr, nullptr);
   }
   ix.max_depth = tree_depth(t);
   PTS_HIP(hipStreamSynchronize(c->stream));
@@ -390,7 +397,7 @@ void build_index_on(Ctx* c, ExView ex, const pts_index_params& p, Index& ix, pts
 
   // ---- tree
   grow_tree(c, zorig, N, d, ix.dp, p.branching, p.depth, p.kmeans_max_iter, p.seed, ix.tree);
-  finalize_device(c, ix, zorig, p.make_bf16 != 0);
+  finalize_device(c, ix, ex, zorig, p.make_bf16 != 0);
 
   if (info) {
     info->N = N;
@@ -493,7 +500,7 @@ void import_index(Ctx* c, ExView ex, const pts_index_host& in, int make_bf16, In
   float* zorig = c->buf<float>("ix_zorig", (size_t)N * ix.dp);
   launch_project_image(c, ex.img, ex.Hz, ex.Wz, ix.w, 1, false, ix.mu_f.as<float>(), ix.basis_f.as<float>(), ix.dp,
                        zorig);
-  finalize_device(c, ix, zorig, make_bf16 != 0);
+  finalize_device(c, ix, ex, zorig, make_bf16 != 0);
 }
 
 }  // namespace pts

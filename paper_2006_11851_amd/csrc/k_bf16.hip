@@ -388,6 +388,7 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
                                                           int64_t qs, int64_t ss, const int32_t* __restrict__ valid,
                                                           int k, const float* __restrict__ Qp,
                                                           const float* __restrict__ Zp,
+                                                          const float* __restrict__ zres,
                                                           const int32_t* __restrict__ perm, int64_t N,
                                                           int32_t* __restrict__ cand_out,
                                                           int32_t* __restrict__ nn) {
@@ -440,6 +441,7 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
       acc = fmaf(t2, t2, acc);
       acc = fmaf(t3, t3, acc);
     }
+    if (zres) acc += zres[pos];
     const int id = perm[pos];
     if (acc < best || (acc == best && id < bid)) {
       best = acc;
@@ -451,13 +453,13 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
 
 void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
                              int64_t ss, const int32_t* valid, int k, const float* Qp, int dp, const float* Zp,
-                             const int32_t* perm, int64_t N, int32_t* cand_out, int32_t* nn) {
+                             const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out, int32_t* nn) {
   ProfScope ps(c, "merge_rerank");
   if (nq == 0) return;
   PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
   PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_merge_rerank_pca<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
-                                       c->stream, part_d, part_i, nq, S, qs, ss, valid, k, Qp, Zp, perm, N, cand_out,
-                                       nn));
+                                       c->stream, part_d, part_i, nq, S, qs, ss, valid, k, Qp, Zp, zres, perm, N,
+                                       cand_out, nn));
   check_launch("k_merge_rerank_pca");
 }
 

@@ -364,6 +364,46 @@ __global__ __launch_bounds__(256) void k_kmeans_accumulate(const float* __restri
   if (gidx == 0) atomicAdd(counts + cidx, 1);
 }
 
+// Same sums with block-private LDS accumulators when the centroid table is
+// small (ncent * dp <= 4096): every block adds its members into LDS with
+// 64-bit LDS atomics and flushes its partial table once, instead of every
+// member hitting the few global addresses of the table.
+__global__ __launch_bounds__(256) void k_kmeans_accumulate_lds(const float* __restrict__ P, int dp,
+                                                               const int32_t* __restrict__ members, int64_t m,
+                                                               const int32_t* __restrict__ seg_of,
+                                                               const int32_t* __restrict__ seg_cent_off,
+                                                               const int32_t* __restrict__ assign, int ncent,
+                                                               unsigned long long* __restrict__ sums,
+                                                               int32_t* __restrict__ counts) {
+  __shared__ unsigned long long s_sum[4096];
+  __shared__ int s_cnt[1024];
+  const int tab = ncent * dp;
+  for (int i = threadIdx.x; i < tab; i += blockDim.x) s_sum[i] = 0ull;
+  for (int i = threadIdx.x; i < ncent; i += blockDim.x) s_cnt[i] = 0;
+  __syncthreads();
+  const int ng = dp >> 2;
+  const int64_t per_block = (m * ng + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * per_block;
+  const int64_t t1 = min(m * ng, t0 + per_block);
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+    const int64_t i = t / ng;
+    const int gidx = (int)(t - i * ng);
+    const int cidx = seg_cent_off[seg_of[i]] + assign[i];
+    const float4 v = *reinterpret_cast<const float4*>(P + (int64_t)members[i] * dp + 4 * gidx);
+    unsigned long long* dst = s_sum + cidx * dp + 4 * gidx;
+    atomicAdd(dst + 0, (unsigned long long)(long long)__double2ll_rn((double)v.x * KM_FIX));
+    atomicAdd(dst + 1, (unsigned long long)(long long)__double2ll_rn((double)v.y * KM_FIX));
+    atomicAdd(dst + 2, (unsigned long long)(long long)__double2ll_rn((double)v.z * KM_FIX));
+    atomicAdd(dst + 3, (unsigned long long)(long long)__double2ll_rn((double)v.w * KM_FIX));
+    if (gidx == 0) atomicAdd(s_cnt + cidx, 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < tab; i += blockDim.x)
+    if (s_sum[i]) atomicAdd(sums + i, s_sum[i]);
+  for (int i = threadIdx.x; i < ncent; i += blockDim.x)
+    if (s_cnt[i]) atomicAdd(counts + i, s_cnt[i]);
+}
+
 void launch_kmeans_mindist(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m, const int32_t* seg_of,
                            const float* cand, float* mind, int first) {
   ProfScope ps(c, "kmeans_mindist");
@@ -385,14 +425,72 @@ void launch_kmeans_assign(Ctx* c, const float* P, int dp, const int32_t* members
 
 void launch_kmeans_accumulate(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m,
                               const int32_t* seg_of, const int32_t* seg_cent_off, const int32_t* assign,
-                              unsigned long long* sums, int32_t* counts) {
+                              unsigned long long* sums, int32_t* counts, int ncent) {
   ProfScope ps(c, "kmeans_accumulate");
   if (m == 0) return;
   PTS_REQUIRE(dp % 4 == 0, PTS_ERR_ARG, "kmeans: dp must be a multiple of 4");
   const int64_t n = m * (dp / 4);
+  if ((int64_t)ncent * dp <= 4096 && ncent <= 1024) {
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(n, 2048)));
+    hipLaunchKernelGGL(k_kmeans_accumulate_lds, dim3(blocks), dim3(256), 0, c->stream, P, dp, members, m, seg_of,
+                       seg_cent_off, assign, ncent, sums, counts);
+    check_launch("k_kmeans_accumulate_lds");
+    return;
+  }
   hipLaunchKernelGGL(k_kmeans_accumulate, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, P, dp, members,
                      m, seg_of, seg_cent_off, assign, sums, counts);
   check_launch("k_kmeans_accumulate");
+}
+
+// ---------------------------------------------------------------------------
+// ||z - mu||^2 of every exemplar window (original order): one wave per window
+
+__global__ __launch_bounds__(256) void k_centered_norm(WinGeom g, int64_t n, const float* __restrict__ mu,
+                                                       float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t win = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (win >= n) return;
+  float acc = 0.f;
+  for (int p = lane; p < g.w * g.w; p += 64) {
+    const float4 v = win_pixel(g, win, p);
+    const float t0 = v.x - mu[4 * p], t1 = v.y - mu[4 * p + 1], t2 = v.z - mu[4 * p + 2], t3 = v.w - mu[4 * p + 3];
+    acc = fmaf(t0, t0, acc);
+    acc = fmaf(t1, t1, acc);
+    acc = fmaf(t2, t2, acc);
+    acc = fmaf(t3, t3, acc);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) out[win] = acc;
+}
+
+void launch_centered_norm(Ctx* c, const float* img, int H, int W, int w, const float* mu, float* out) {
+  ProfScope ps(c, "centered_norm");
+  const WinGeom g = geom(img, H, W, w, 1, false);
+  const int64_t n = (int64_t)(H - w + 1) * (W - w + 1);
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_centered_norm, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, c->stream, g, n, mu, out);
+  check_launch("k_centered_norm");
+}
+
+// res[i] = max(0, cn[perm[i]] - zn[i]);  bres[i] = bn[i] + res[i]
+__global__ __launch_bounds__(256) void k_residual(const float* __restrict__ cn, const int32_t* __restrict__ perm,
+                                                  const float* __restrict__ zn, const float* __restrict__ bn, int64_t n,
+                                                  float* __restrict__ res, float* __restrict__ bres) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float r = fmaxf(cn[perm[i]] - zn[i], 0.f);
+  res[i] = r;
+  if (bres) bres[i] = bn[i] + r;
+}
+
+void launch_residual(Ctx* c, const float* cn, const int32_t* perm, const float* zn, const float* bn, int64_t n,
+                     float* res, float* bres) {
+  ProfScope ps(c, "residual");
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, cn, perm, zn, bn, n, res,
+                     bres);
+  check_launch("k_residual");
 }
 
 // ---------------------------------------------------------------------------

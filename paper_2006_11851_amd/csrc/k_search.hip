@@ -277,3 +277,53 @@ void launch_count_diff(Ctx* c, const int32_t* a, const int32_t* b, int64_t n, in
 }
 
 }  // namespace pts
+
+namespace pts {
+
+// windows of a listed subset of output-grid ids: out[r][(dy*w+dx)*4+c]
+__global__ __launch_bounds__(256) void k_gather_windows_list(const float4* __restrict__ img, int H, int W, int w,
+                                                             int s, int cols, int64_t nq,
+                                                             const int32_t* __restrict__ qids, int64_t n,
+                                                             float4* __restrict__ out) {
+  const int64_t ww = (int64_t)w * w;
+  const int64_t total = n * ww;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / ww;
+    const int p = (int)(t - r * ww);
+    int64_t q = qids[r];
+    if (q < 0 || q >= nq) q = 0;  // invalid ids read window 0; the caller validated
+    const int i = (int)(q / cols), j = (int)(q - (int64_t)i * cols);
+    const int dy = p / w, dx = p - dy * w;
+    int x = j * s + dx;
+    if (x >= W) x -= W;
+    out[t] = img[(int64_t)(i * s + dy) * W + x];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sqrt(const float* __restrict__ a, int64_t n, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = sqrtf(a[i]);
+}
+
+void launch_exact_subset(Ctx* c, const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
+                         const int32_t* qids, int64_t n, int32_t* nn, float* dist) {
+  ProfScope ps(c, "exact_subset");
+  if (n == 0) return;
+  const Grid g{H, W, w, s};
+  const int D = 4 * w * w;
+  const int64_t N = (int64_t)(Hz - w + 1) * (Wz - w + 1);
+  float* zw = c->buf<float>("exact_zw", (size_t)N * D);
+  float* qw = c->buf<float>("exact_qw_sub", (size_t)n * D);
+  float* d2 = c->buf<float>("exact_d2_sub", (size_t)n);
+  launch_gather_windows(c, ex, Hz, Wz, w, 1, false, zw);
+  const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(n * w * w, 256), 65536);
+  hipLaunchKernelGGL(k_gather_windows_list, dim3(blocks), dim3(256), 0, c->stream, reinterpret_cast<const float4*>(x), H,
+                     W, w, s, g.cols(), g.nq(), qids, n, reinterpret_cast<float4*>(qw));
+  check_launch("k_gather_windows_list");
+  launch_argmin_direct(c, qw, n, zw, N, D, nullptr, nn, d2);
+  hipLaunchKernelGGL(k_sqrt, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, d2, n, dist);
+  check_launch("k_sqrt");
+}
+
+}  // namespace pts

@@ -161,12 +161,68 @@ __global__ __launch_bounds__(256) void k_leaf_tiles(const int32_t* __restrict__ 
   for (int t = t0; t < t1; ++t) tiles[t] = make_int2(l, off[l] + (t - t0) * chunk);
 }
 
+// LDS-privatised histogram: per block, count its chunk in LDS, then one
+// global atomic per (block, leaf) with a non-zero count.
+constexpr int BK_LDS_LEAVES = 8192;
+constexpr int BK_PER_BLOCK = 4096;
+
+__global__ __launch_bounds__(256) void k_leaf_hist_lds(const int32_t* __restrict__ leaf, int64_t n, int n_leaves,
+                                                       int32_t* __restrict__ counts) {
+  __shared__ int sc[BK_LDS_LEAVES];
+  for (int i = threadIdx.x; i < n_leaves; i += 256) sc[i] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * BK_PER_BLOCK;
+  const int64_t e1 = min(n, e0 + BK_PER_BLOCK);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int l = leaf[e];
+    if (l >= 0 && l < n_leaves) atomicAdd(sc + l, 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_leaves; i += 256)
+    if (sc[i]) atomicAdd(counts + i, sc[i]);
+}
+
+// scatter: ranks within the block from LDS atomics, one global reservation
+// per (block, leaf)
+__global__ __launch_bounds__(256) void k_leaf_scatter_lds(const int32_t* __restrict__ leaf, int64_t n, int n_leaves,
+                                                          int32_t* __restrict__ cursor, int32_t* __restrict__ order) {
+  __shared__ int sc[BK_LDS_LEAVES];
+  for (int i = threadIdx.x; i < n_leaves; i += 256) sc[i] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * BK_PER_BLOCK;
+  const int64_t e1 = min(n, e0 + BK_PER_BLOCK);
+  int rank[BK_PER_BLOCK / 256];
+#pragma unroll
+  for (int u = 0; u < BK_PER_BLOCK / 256; ++u) {
+    const int64_t e = e0 + threadIdx.x + u * 256;
+    rank[u] = -1;
+    if (e < e1) {
+      const int l = leaf[e];
+      if (l >= 0 && l < n_leaves) rank[u] = atomicAdd(sc + l, 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_leaves; i += 256)
+    if (sc[i]) sc[i] = atomicAdd(cursor + i, sc[i]);  // base of this block's run
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < BK_PER_BLOCK / 256; ++u) {
+    const int64_t e = e0 + threadIdx.x + u * 256;
+    if (rank[u] >= 0) order[sc[leaf[e]] + rank[u]] = (int32_t)e;
+  }
+}
+
 void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b) {
   ProfScope ps(c, "leaf_bucket");
   hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)ceil_div(n_leaves, 256)), dim3(256), 0, c->stream, b.counts,
                      (int64_t)n_leaves);
   check_launch("k_zero_i32");
-  if (n > 0) {
+  const bool lds = n_leaves <= BK_LDS_LEAVES;
+  if (n > 0 && lds) {
+    hipLaunchKernelGGL(k_leaf_hist_lds, dim3((unsigned)ceil_div(n, BK_PER_BLOCK)), dim3(256), 0, c->stream, leaf, n,
+                       n_leaves, b.counts);
+    check_launch("k_leaf_hist_lds");
+  } else if (n > 0) {
     hipLaunchKernelGGL(k_leaf_hist, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, leaf, n, n_leaves,
                        b.counts);
     check_launch("k_leaf_hist");
@@ -174,7 +230,11 @@ void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chu
   hipLaunchKernelGGL(k_leaf_scan_offsets, dim3(1), dim3(1024), 0, c->stream, b.counts, n_leaves, chunk, b.off,
                      b.cursor, b.tile_off, b.ntiles);
   check_launch("k_leaf_scan_offsets");
-  if (n > 0) {
+  if (n > 0 && lds) {
+    hipLaunchKernelGGL(k_leaf_scatter_lds, dim3((unsigned)ceil_div(n, BK_PER_BLOCK)), dim3(256), 0, c->stream, leaf, n,
+                       n_leaves, b.cursor, b.order);
+    check_launch("k_leaf_scatter_lds");
+  } else if (n > 0) {
     hipLaunchKernelGGL(k_leaf_scatter, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, leaf, n, n_leaves,
                        b.cursor, b.order);
     check_launch("k_leaf_scatter");
@@ -201,9 +261,11 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
                                                        const int32_t* __restrict__ order,
                                                        const int2* __restrict__ tiles,
                                                        const int32_t* __restrict__ ntiles, int P,
+                                                       const float* __restrict__ zres,
                                                        int32_t* __restrict__ nn, float* __restrict__ best_d2) {
   __shared__ float4 Zs[LS_M][DP / 4];
   __shared__ int Zid[LS_M];
+  __shared__ float Zr[LS_M];
   __shared__ float rd[4][LS_Q];
   __shared__ int ri[4][LS_Q];
   const int t = blockIdx.x;
@@ -236,7 +298,10 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
       Zs[r][k4] = (r < mcount) ? reinterpret_cast<const float4*>(Zp + (int64_t)(mb + r) * DP)[k4]
                                : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    if (threadIdx.x < LS_M) Zid[threadIdx.x] = (threadIdx.x < mcount) ? perm[mb + threadIdx.x] : INT_MAX;
+    if (threadIdx.x < LS_M) {
+      Zid[threadIdx.x] = (threadIdx.x < mcount) ? perm[mb + threadIdx.x] : INT_MAX;
+      Zr[threadIdx.x] = (zres && threadIdx.x < mcount) ? zres[mb + threadIdx.x] : 0.f;
+    }
     __syncthreads();
     for (int r = wave; r < mcount; r += 4) {
       float acc = 0.f;
@@ -250,6 +315,7 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
         acc = fmaf(t2, t2, acc);
         acc = fmaf(t3, t3, acc);
       }
+      acc += Zr[r];
       const int id = Zid[r];
       if (better_id(acc, id, bd, bi)) {
         bd = acc;
@@ -273,12 +339,12 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
 }
 
 void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
-                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, int32_t* nn,
-                          float* best_d2) {
+                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, const float* zres,
+                          int32_t* nn, float* best_d2) {
   ProfScope ps(c, "leaf_scan_f32");
   if (max_tiles == 0) return;
   PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_leaf_scan_f32<DPC>, dim3(max_tiles), dim3(256), 0, c->stream, Qp, Zp, perm,
-                                       leaf_off, b.off, b.order, b.tiles, b.ntiles, P, nn, best_d2));
+                                       leaf_off, b.off, b.order, b.tiles, b.ntiles, P, zres, nn, best_d2));
   check_launch("k_leaf_scan_f32");
 }
 

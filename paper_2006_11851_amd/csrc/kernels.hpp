@@ -24,6 +24,9 @@ void launch_argmin_direct(Ctx* c, const float* Q, int64_t nq, const float* Z, in
 // dist[q] = || x_q - z_nn[q] || over the full window (NaN for an invalid id)
 void launch_winner_dist(Ctx* c, const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
                         const int32_t* nn, float* dist);
+// exhaustive full-D search of listed output windows: nn, dist = sqrt(d2)
+void launch_exact_subset(Ctx* c, const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
+                         const int32_t* qids, int64_t n, int32_t* nn, float* dist);
 // number of i with a[i] != b[i], added to *count (int32)
 void launch_count_diff(Ctx* c, const int32_t* a, const int32_t* b, int64_t n, int32_t* count);
 void launch_zero_i32(Ctx* c, int32_t* p, int64_t n);
@@ -45,10 +48,15 @@ void launch_kmeans_assign(Ctx* c, const float* P, int dp, const int32_t* members
                           int32_t* changed);
 void launch_kmeans_accumulate(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m,
                               const int32_t* seg_of, const int32_t* seg_cent_off, const int32_t* assign,
-                              unsigned long long* sums, int32_t* counts);
+                              unsigned long long* sums, int32_t* counts, int ncent);
 // dst[i] = src[perm[i]] (rows of dp floats); norm[i] = ||dst[i]||^2 if non-null
 void launch_permute_rows(Ctx* c, const float* src, const int32_t* perm, int64_t n, int dp, float* dst, float* norm);
 void launch_to_bf16_rows(Ctx* c, const float* P, int64_t n, int dp, int dk, uint16_t* out, float* norm);
+// ||z - mu||^2 per exemplar window (original id order)
+void launch_centered_norm(Ctx* c, const float* img, int H, int W, int w, const float* mu, float* out);
+// leaf order: res = max(0, cn[perm] - zn), bres = bn + res (bres optional)
+void launch_residual(Ctx* c, const float* cn, const int32_t* perm, const float* zn, const float* bn, int64_t n,
+                     float* res, float* bres);
 void launch_leaf_of_ids(Ctx* c, const int32_t* leaf_of_ex, const int32_t* nn, int64_t n, int32_t* leaf, int64_t N);
 
 // ---- tree search (k_tree.hip)
@@ -66,8 +74,8 @@ void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* ce
 void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b);
 // order[] holds pair indices (query * P + slot); results per pair
 void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
-                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, int32_t* nn,
-                          float* best_d2);
+                          const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, const float* zres,
+                          int32_t* nn, float* best_d2);
 void launch_learned_pairs(Ctx* c, const int32_t* prop, const float* margin, const int32_t* dleaf, int64_t nq, int P,
                           float thr, int n_leaves, int32_t* pair_leaf, int32_t* fallbacks);
 void launch_merge_pairs_f32(Ctx* c, const int32_t* pair_leaf, const int32_t* pair_id, const float* pair_d, int64_t nq,

@@ -198,6 +198,18 @@ int pts_estep(pts_ctx* c, const float* x, int H, int W, const pts_estep_params* 
   });
 }
 
+int pts_exact_search(pts_ctx* c, const float* x, int H, int W, int w, int stride, const int32_t* qids, int64_t n,
+                     int32_t* nn, float* dist) {
+  CTX_REQUIRED(c);
+  return guard(c, [&] {
+    PTS_REQUIRE(x && n >= 0 && (n == 0 || (qids && nn && dist)), PTS_ERR_ARG, "exact_search: bad arguments");
+    ExView ex = ctx_exemplar(c);
+    validate_grid(H, W, w, stride);
+    PTS_REQUIRE(w <= ex.Hz && w <= ex.Wz, PTS_ERR_ARG, "exact_search: window larger than the exemplar");
+    launch_exact_subset(c, x, H, W, w, stride, ex.img, ex.Hz, ex.Wz, qids, n, nn, dist);
+  });
+}
+
 int pts_project(pts_ctx* c, const float* x, int H, int W, int stride, float* qproj) {
   CTX_REQUIRED(c);
   return guard(c, [&] {

@@ -96,6 +96,7 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
     ep.rerank_full = p.rerank_full;
     ep.n_proposals = p.n_proposals;
     ep.margin = p.margin;
+    ep.residual = p.residual;
     const Grid g{h, w, lp.w, lp.stride};
     const int64_t nq = g.nq();
     int32_t* nn_cur = static_cast<int32_t*>(nn_a.ensure(c, (size_t)nq * 4));

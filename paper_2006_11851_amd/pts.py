@@ -106,6 +106,7 @@ class pts_estep_params(C.Structure):
         ("rerank_full", C.c_int),
         ("n_proposals", C.c_int),
         ("margin", C.c_float),
+        ("residual", C.c_int),
     ]
 
 
@@ -144,6 +145,7 @@ class pts_solve_params(C.Structure):
         ("rerank_full", C.c_int),
         ("n_proposals", C.c_int),
         ("margin", C.c_float),
+        ("residual", C.c_int),
         ("r", C.c_float),
         ("delta", C.c_float),
         ("patch_offset", C.c_int),
@@ -202,6 +204,7 @@ SIGNATURES = {
     "pts_export_index": (_I, [_P, C.POINTER(pts_index_host)]),
     "pts_import_index": (_I, [_P, C.POINTER(pts_index_host), _I]),
     "pts_estep": (_I, [_P, _P, _I, _I, C.POINTER(pts_estep_params), _P, _P, C.POINTER(pts_estep_stats)]),
+    "pts_exact_search": (_I, [_P, _P, _I, _I, _I, _I, _P, _I64, _P, _P]),
     "pts_project": (_I, [_P, _P, _I, _I, _I, _P]),
     "pts_exemplar_projection": (_I, [_P, _P]),
     "pts_leaf_of": (_I, [_P, _P, _I64, _P]),
@@ -400,19 +403,28 @@ class Context:
     def nq(self, H, W, w, s):
         return ((H - w) // s + 1) * (W // s)
 
-    def estep(self, x, w, stride, mode="tree", topk=8, rerank_full=0, n_proposals=4, margin=0.2, stats=False,
-              nn=None, dist=None):
+    def estep(self, x, w, stride, mode="tree", topk=8, rerank_full=0, n_proposals=4, margin=0.2, residual=0,
+              stats=False, nn=None, dist=None):
         H, W = x.shape[:2]
         nq = self.nq(H, W, w, stride)
         nn = self._i32(nq) if nn is None else nn
         dist = self._f32(nq) if dist is None else dist
         p = pts_estep_params(MODES[mode] if isinstance(mode, str) else mode, w, stride, topk, rerank_full,
-                             n_proposals, margin)
+                             n_proposals, margin, int(residual))
         st = pts_estep_stats()
         self._ok(lib().pts_estep(self._h, _ptr(x), H, W, C.byref(p), _ptr(nn), _ptr(dist),
                                  C.byref(st) if stats else None))
         if stats:
             return nn, dist, st
+        return nn, dist
+
+    def exact_search(self, x, w, stride, qids):
+        """Exhaustive full-D search of the listed output windows (int32 tensor)."""
+        n = qids.numel()
+        nn = self._i32(n)
+        dist = self._f32(n)
+        self._ok(lib().pts_exact_search(self._h, _ptr(x), x.shape[0], x.shape[1], w, stride, _ptr(qids), n, _ptr(nn),
+                                        _ptr(dist)))
         return nn, dist
 
     def project(self, x, stride):
@@ -477,8 +489,8 @@ class Context:
         return out
 
     def solve(self, x0, levels, mode="tree", coarse_mode="tree", topk=8, rerank_full=0, n_proposals=4,
-              margin=0.2, r=0.8, delta=1e-3, patch_offset=0, guidance_weight=0.5, seed=0, kmeans_max_iter=50,
-              reuse_finest_index=False, trace=True):
+              margin=0.2, residual=0, r=0.8, delta=1e-3, patch_offset=0, guidance_weight=0.5, seed=0,
+              kmeans_max_iter=50, reuse_finest_index=False, trace=True):
         """levels: list of dicts with w, stride, iters, pca_dims, branching, depth (coarse to fine)."""
         L = len(levels)
         lv = (pts_level_params * L)(*[
@@ -486,8 +498,8 @@ class Context:
                              l.get("depth", 0)) for l in levels])
         p = pts_solve_params(L, lv, MODES[mode] if isinstance(mode, str) else mode,
                              MODES[coarse_mode] if isinstance(coarse_mode, str) else coarse_mode, topk, rerank_full,
-                             n_proposals, margin, r, delta, patch_offset, guidance_weight, seed, kmeans_max_iter,
-                             int(reuse_finest_index))
+                             n_proposals, margin, int(residual), r, delta, patch_offset, guidance_weight, seed,
+                             kmeans_max_iter, int(reuse_finest_index))
         H0, W0 = x0.shape[:2]
         H, W = H0 << (L - 1), W0 << (L - 1)
         out = self._f32((H, W, 4))

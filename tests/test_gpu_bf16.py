@@ -43,6 +43,24 @@ def test_brute_bf16_teacher_forced_small(gpu_ctx, d):
     assert np.allclose(_np(dist), np.sqrt(parity.sqdist_rows(Q, Zm, _np(nn))), rtol=1e-5, atol=1e-6)
 
 
+def test_brute_bf16_residual_teacher_forced(gpu_ctx):
+    print("case: brute_bf16 residual ranking ex64_out128", flush=True)
+    ex, init, wl, w = _setup(gpu_ctx, "ex64_out128", 16, 4, 3)
+    s = wl.stride[0]
+    x = gpu_ctx.rgbs_from_u8(init)
+    Qp = _np(gpu_ctx.project(x, s)).astype(np.float64)
+    Zp = _np(gpu_ctx.exemplar_projection()).astype(np.float64)
+    g = gpu_ctx.export_index()
+    Q, Zm = helpers.query_and_exemplar(vectors.rgbs(init), vectors.rgbs(ex), w, s)
+    off = bf16.residual(Zm, g["mu"], Zp)
+    nn, _ = gpu_ctx.estep(x, w, s, mode="brute_bf16", residual=1)
+    nn_o, _ = bf16.brute_nn(Qp, Zp, 8, offset=off)
+    d_gpu = parity.sqdist_rows(Qp, Zp, _np(nn)) + off[_np(nn)]
+    d_or = parity.sqdist_rows(Qp, Zp, nn_o) + off[nn_o]
+    ok = np.mean((_np(nn) == nn_o) | (d_gpu - d_or <= 1e-4 * np.maximum(d_or, 1e-300)))
+    assert ok >= 0.999, ok
+
+
 def test_brute_bf16_ragged_and_rerank_full(gpu_ctx):
     """N and nq not multiples of the 128-row stage or the 512-query block."""
     print("case: brute_bf16 ragged + full-D re-rank", flush=True)
@@ -92,15 +110,19 @@ def test_brute_bf16_energy_gap_ex512_w16(gpu_ctx):
     assert all(g >= -1e-6 for g in gaps.values())
     # gated gap: G_t = E(x^{t-1}; nn_method) / E(x^{t-1}; nn_exact) - 1 along the
     # method's own trajectory (10 iterations), maximum over t
-    xt = x.clone()
-    G = []
-    for t in range(10):
-        nn_m, d_m = gpu_ctx.estep(xt, w, s, mode="brute_bf16", rerank_full=1)
-        _, d_x = gpu_ctx.estep(xt, w, s, mode="exact_full")
-        G.append(gpu_ctx.energy(d_m)[0] / gpu_ctx.energy(d_x)[0] - 1.0)
-        gpu_ctx.mstep(nn_m, d_m, xt, w, s)
-    print(f"trajectory gaps (brute_bf16, full-D re-rank): {G}", flush=True)
-    assert max(G) <= 0.005, G
+    maxg = {}
+    for rf in (0, 1):
+        for res in (0, 1):
+            xt = x.clone()
+            G = []
+            for t in range(10):
+                nn_m, d_m = gpu_ctx.estep(xt, w, s, mode="brute_bf16", rerank_full=rf, residual=res)
+                _, d_x = gpu_ctx.estep(xt, w, s, mode="exact_full")
+                G.append(gpu_ctx.energy(d_m)[0] / gpu_ctx.energy(d_x)[0] - 1.0)
+                gpu_ctx.mstep(nn_m, d_m, xt, w, s)
+            maxg[(rf, res)] = max(G)
+            print(f"trajectory gaps (rerank_full={rf}, residual={res}): {['%.5f' % g for g in G]}", flush=True)
+    assert maxg[(1, 1)] <= 0.005, maxg
     # sampled parity against the oracle's BF16 form
     Qp = _np(gpu_ctx.project(x, s)).astype(np.float64)
     Zp = _np(gpu_ctx.exemplar_projection()).astype(np.float64)

@@ -490,3 +490,20 @@ def test_mlp_proposal_margin():
     logits = np.array([[math.log(3.0), 0.0, 0.0]])
     top, margin = mlp.propose(logits, 2)
     assert abs(margin[0] - (3 / 5 - 1 / 5)) < 1e-15
+
+
+def test_residual_offset_ranks_by_full_distance_estimate():
+    # with the exemplar's out-of-subspace energy added, a PCA-space ranking
+    # equals the full-dimension ranking whenever the query lies in the subspace
+    r = np.random.default_rng(21)
+    Zm = r.normal(size=(400, 12)) * np.linspace(3, 0.2, 12)
+    mu, B, _, _ = pca.basis(Zm, 4)
+    Zp = pca.project(Zm, mu, B)
+    Q = mu + r.normal(size=(30, 4)) @ B.T  # queries inside the subspace
+    off = bf16.residual(Zm, mu, Zp)
+    assert np.all(off >= 0) and off.max() > 0
+    ids_full = exact.topk(Q, Zm, 3)[0]
+    ids_pca = exact.topk(pca.project(Q, mu, B), Zp, 3, offset=off)[0]
+    assert np.array_equal(ids_full, ids_pca)
+    ids_direct = exact.topk_direct(pca.project(Q, mu, B), Zp, 3, offset=off)[0]
+    assert np.array_equal(ids_direct, ids_pca)
