@@ -149,7 +149,8 @@ def main():
             "workload": f"{a.workload} finest level: exemplar {wl.ex_size}^2, output {Hout}^2, w={w}, stride={s}, "
                         f"N={info.N}, nq={nq}, PCA {info.d}, k-means tree b{wl.branching} L{wl.depth} "
                         f"({info.n_leaves} leaves)",
-            "form": "BF16 MFMA leaf scans of the MLP's top-4 leaves (tree below margin 0.2), top-8, FP32 re-rank"
+            "form": "BF16 MFMA leaf scans of the MLP's top-4 leaves (plus the tree's leaf below margin 0.2), "
+                    "8 class-minimum candidates, FP32 re-rank"
                     + (" in full D" if a.rerank_full else " in PCA space")
                     + (", residual-energy ranking" if a.residual else ""),
         },
@@ -205,8 +206,8 @@ def scanned_pairs(ctx, head, info, nq):
     prop, margin = ctx.mlp_propose(qp, 4)
     dleaf = ctx.descend(qp)
     fb = ~(margin >= 0.2)
-    tot = sizes[prop.long()].sum(dim=1)
-    tot = torch.where(fb, sizes[dleaf.long()], tot)
+    dup = (prop == dleaf[:, None]).any(dim=1)
+    tot = sizes[prop.long()].sum(dim=1) + torch.where(fb & ~dup, sizes[dleaf.long()], torch.zeros_like(dleaf))
     return float(tot.sum())
 
 

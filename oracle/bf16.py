@@ -68,3 +68,42 @@ def brute_nn(Qp, Zp, k: int = 8, Q_full=None, Z_full=None, offset=None):
     if Q_full is not None:
         return rerank(Q_full, Z_full, cand)[0], cand
     return rerank(Qp, Zp, cand, offset=offset)[0], cand
+
+
+def class_candidates(q, Zrows, offset=None):
+    """Candidate rule of a BF16 scan over an ordered list of rows (a leaf's
+    members in leaf order): with i the position of a row in the scan, the
+    rows fall into 16 classes by i % 16 and into 32-row tiles by i // 32;
+    each class's score is its minimum over the rows (ties to the earliest
+    tile), the 4 classes with the smallest scores are kept, and each
+    contributes the two rows of its tile in that class (i and i + 16 within
+    the tile).  Scores are exact distances of the bf16-rounded vectors (plus
+    the optional per-row offset).  Returns (positions into Zrows [<=8],
+    scores [<=8]) with both rows of a class sharing the class score.
+    """
+    qb = round_bf16(np.asarray(q)[None, :])[0]
+    Zb = round_bf16(Zrows)
+    d = np.einsum("ij,ij->i", Zb - qb[None, :], Zb - qb[None, :])
+    if offset is not None:
+        d = d + np.asarray(offset, dtype=np.float64)
+    m = d.size
+    best = []
+    for b in range(16):
+        bv, bt = np.inf, -1
+        for t in range((m + 31) // 32):
+            rows = [i for i in (32 * t + b, 32 * t + b + 16) if i < m]
+            if not rows:
+                continue
+            v = min(d[i] for i in rows)
+            if v < bv:
+                bv, bt = v, t
+        if bt >= 0:
+            best.append((bv, b, bt))
+    best.sort(key=lambda e: (e[0], e[1]))
+    pos, sc = [], []
+    for v, b, t in best[:4]:
+        for i in (32 * t + b, 32 * t + b + 16):
+            if i < m:
+                pos.append(i)
+                sc.append(v)
+    return np.asarray(pos, dtype=np.int64), np.asarray(sc)

@@ -19,9 +19,8 @@ void search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, ix.N, ix.dk, S, pd, pi);
   if (p.rerank_full) {
     int32_t* cand = c->buf<int32_t>("bb_cand", (size_t)nq * 8);
-    int32_t* tmp = c->buf<int32_t>("bb_nn_pca", (size_t)nq);
     launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
-                            ix.perm.as<int32_t>(), ix.N, cand, tmp);
+                            ix.perm.as<int32_t>(), ix.N, cand, nullptr);
     launch_rerank_full(c, x, H, W, ix.w, p.stride, ex.img, ex.Hz, ex.Wz, cand, k, nq, nn);
   } else {
     launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
@@ -38,44 +37,47 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   int32_t* prop = c->buf<int32_t>("ln_prop", (size_t)nq * P);
   float* margin = c->buf<float>("ln_margin", (size_t)nq);
   mlp_propose_rows(c, qp, ix.dp, nq, P, prop, margin);
-  // the tree's own leaf, used where the margin is low
+  // the tree's own leaf, needed only where the margin is low
   int32_t* dleaf = c->buf<int32_t>("ln_dleaf", (size_t)nq);
-  launch_descend(c, qp, nq, ix.dp, ix.cent.as<float>(), ix.first_child.as<int32_t>(), ix.n_children.as<int32_t>(),
-                 ix.leaf_of_node.as<int32_t>(), dleaf);
-  int32_t* pair_leaf = c->buf<int32_t>("ln_pair_leaf", (size_t)nq * P);
+  int32_t* lowq = c->buf<int32_t>("ln_lowq", (size_t)nq);
+  int32_t* nlow = c->buf<int32_t>("ln_nlow", 1);
+  launch_zero_i32(c, nlow, 1);
+  launch_descend_low_margin(c, qp, nq, ix.dp, margin, p.margin, ix.cent.as<float>(), ix.first_child.as<int32_t>(),
+                            ix.n_children.as<int32_t>(), ix.leaf_of_node.as<int32_t>(), lowq, nlow, dleaf);
+  const int P1 = P + 1;  // proposals + the tree's leaf for low-margin queries
+  int32_t* pair_leaf = c->buf<int32_t>("ln_pair_leaf", (size_t)nq * P1);
   int32_t* fb = c->buf<int32_t>("ln_fallbacks", 1);
   launch_zero_i32(c, fb, 1);
   launch_learned_pairs(c, prop, margin, dleaf, nq, P, p.margin, L, pair_leaf, fb);
   const int chunk = bf16_scan ? 512 : 64;
   int max_tiles = 0;
-  BucketBufs b = bucket_buffers(c, nq * P, L, chunk, &max_tiles);
-  launch_bucket(c, pair_leaf, nq * P, L, chunk, b);
+  BucketBufs b = bucket_buffers(c, nq * P1, L, chunk, &max_tiles);
+  launch_bucket(c, pair_leaf, nq * P1, L, chunk, b);
   if (!bf16_scan) {
-    int32_t* pid = c->buf<int32_t>("ln_pair_id", (size_t)nq * P);
-    float* pdd = c->buf<float>("ln_pair_d", (size_t)nq * P);
+    int32_t* pid = c->buf<int32_t>("ln_pair_id", (size_t)nq * P1);
+    float* pdd = c->buf<float>("ln_pair_d", (size_t)nq * P1);
     launch_leaf_scan_f32(c, qp, ix.dp, ix.zproj.as<float>(), ix.perm.as<int32_t>(), ix.leaf_off.as<int32_t>(), b,
-                         max_tiles, P, p.residual ? ix.zres.as<float>() : nullptr, pid, pdd);
-    launch_merge_pairs_f32(c, pair_leaf, pid, pdd, nq, P, nn);
+                         max_tiles, P1, p.residual ? ix.zres.as<float>() : nullptr, pid, pdd);
+    launch_merge_pairs_f32(c, pair_leaf, pid, pdd, nq, P1, nn);
   } else {
     PTS_REQUIRE(ix.has_bf16, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
     const int k = p.topk <= 0 ? 8 : p.topk;
     PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
     uint16_t* qb = c->buf<uint16_t>("qbf16", (size_t)nq * ix.dk);
     launch_queries_bf16(c, qp, nq, ix.dp, ix.dk, qb);
-    float* pdd = c->buf<float>("ln_pair_cd", (size_t)nq * P * 8);
-    int32_t* pii = c->buf<int32_t>("ln_pair_ci", (size_t)nq * P * 8);
+    float* pdd = c->buf<float>("ln_pair_cd", (size_t)nq * P1 * 8);
+    int32_t* pii = c->buf<int32_t>("ln_pair_ci", (size_t)nq * P1 * 8);
     const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();
     const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
-    launch_leaf_scan_bf16(c, qb, P, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b, max_tiles, pdd,
-                          pii);
+    launch_leaf_scan_bf16(c, qb, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b, max_tiles,
+                          pdd, pii);
     if (p.rerank_full) {
       int32_t* cand = c->buf<int32_t>("bb_cand", (size_t)nq * 8);
-      int32_t* tmp = c->buf<int32_t>("bb_nn_pca", (size_t)nq);
-      launch_merge_rerank_pca(c, pdd, pii, nq, P, P, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
-                              ix.perm.as<int32_t>(), ix.N, cand, tmp);
+      launch_merge_rerank_pca(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
+                              ix.perm.as<int32_t>(), ix.N, cand, nullptr);
       launch_rerank_full(c, x, H, W, ix.w, p.stride, ex.img, ex.Hz, ex.Wz, cand, k, nq, nn);
     } else {
-      launch_merge_rerank_pca(c, pdd, pii, nq, P, P, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
+      launch_merge_rerank_pca(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
                               ix.perm.as<int32_t>(), ix.N, nullptr, nn);
     }
   }

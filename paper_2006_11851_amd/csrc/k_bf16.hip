@@ -256,6 +256,54 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
   }
 }
 
+// Class-minimum candidate rule for scans where most rows are near the
+// query (a leaf's members): a sorted per-lane top-k would insert on a large
+// share of rows, and under SIMT every value slot would pay for it.  Instead
+// each lane keeps, for each of its 8 classes (value slots r and r + 8 of the
+// 32x32 output, i.e. scan rows i with i % 16 fixed), the minimum score over
+// the scan and the 32-row tile holding it: v_min3 + compare + select per
+// class and tile.  The 16 classes of a query (two half-lanes) are ranked by
+// their minima and the best 4 contribute both rows of their tile (rows
+// i % 32 == b and b + 16): 8 candidates that always include the minimum.
+template <int KS>
+__device__ __forceinline__ void stage_compute_cls(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
+                                                  float (&cm)[2][8], int (&ct)[2][8], int pos0, int lane,
+                                                  int nvalid) {
+#pragma unroll
+  for (int t = 0; t < BB_STAGE / 32; ++t) {
+    if (t * 32 >= nvalid) break;
+    bf16x8 A[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const uint4 u = S.frag[buf][t][kk][lane];
+      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+    floatx16 cinit;
+    const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
+      cinit[4 * g + 0] = z4.x;
+      cinit[4 * g + 1] = z4.y;
+      cinit[4 * g + 2] = z4.z;
+      cinit[4 * g + 3] = z4.w;
+    }
+    const int tbase = pos0 + t * 32;
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt) {
+      floatx16 acc = cinit;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc, 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float m3 = __builtin_fminf(cm[qt][c], __builtin_fminf(acc[c], acc[c + 8]));
+        ct[qt][c] = (m3 < cm[qt][c]) ? tbase : ct[qt][c];
+        cm[qt][c] = m3;
+      }
+    }
+  }
+}
+
 // BF16 scan of leaves for (query, leaf) pairs: tile = (leaf, 512 pairs of
 // the bucketed order); rows = the leaf's members (contiguous in leaf order);
 // per pair the top-8 (score, leaf position).  Waves without pairs skip the
@@ -291,10 +339,16 @@ __global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restri
       B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
   }
-  TopK<BB_TOPK> top[2];
-  top[0].init();
-  top[1].init();
-  const int64_t row_begin = leaf_off[tile.x], row_end = leaf_off[tile.x + 1];
+  float cm[2][8];
+  int ct[2][8];
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      cm[qt][c] = FLT_MAX;
+      ct[qt][c] = -1;
+    }
+  const int row_begin = leaf_off[tile.x], row_end = leaf_off[tile.x + 1];
   if (row_begin < row_end) {
     const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
     StageRegs<KS> R;
@@ -306,31 +360,82 @@ __global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restri
       const bool more = st + 1 < nstages;
       if (more) stage_load<KS>(R, Zb, zbn, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end, tid);
       if (wave_active)
-        stage_compute<KS>(sm, buf, B, top, row_begin + (int64_t)st * BB_STAGE, lane,
-                          (int)min((int64_t)BB_STAGE, row_end - row_begin - (int64_t)st * BB_STAGE));
+        stage_compute_cls<KS>(sm, buf, B, cm, ct, row_begin + st * BB_STAGE, lane,
+                              min(BB_STAGE, row_end - row_begin - st * BB_STAGE));
       if (more) stage_store<KS>(R, sm, buf ^ 1, tid);
       __syncthreads();
     }
   }
+  // rows of class c in half h of a tile: i = 8 (c / 4) + 4 h + (c % 4), and i + 16
+  const int h = lane >> 5;
 #pragma unroll
   for (int qt = 0; qt < 2; ++qt) {
-    float od[BB_TOPK];
-    int oi[BB_TOPK];
+    // the 4 best of this lane's 8 classes, then the 4 best of the two halves
+    float bv[4];
+    int bt[4], bc[4];
 #pragma unroll
-    for (int k2 = 0; k2 < BB_TOPK; ++k2) {
-      od[k2] = __shfl_xor(top[qt].d[k2], 32, 64);
-      oi[k2] = __shfl_xor(top[qt].i[k2], 32, 64);
+    for (int k2 = 0; k2 < 4; ++k2) {
+      bv[k2] = FLT_MAX;
+      bt[k2] = -1;
+      bc[k2] = 0;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      float v = cm[qt][c];
+      int tt = ct[qt][c], cc = c;
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) {  // insertion into a sorted list of 4
+        const bool sw = v < bv[k2];
+        const float fv = sw ? bv[k2] : v;
+        const int ft = sw ? bt[k2] : tt, fc = sw ? bc[k2] : cc;
+        bv[k2] = sw ? v : bv[k2];
+        bt[k2] = sw ? tt : bt[k2];
+        bc[k2] = sw ? cc : bc[k2];
+        v = fv;
+        tt = ft;
+        cc = fc;
+      }
+    }
+    int rowa[4];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) rowa[k2] = bt[k2] < 0 ? -1 : bt[k2] + 8 * (bc[k2] >> 2) + 4 * h + (bc[k2] & 3);
+    float ov[4];
+    int orow[4];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      ov[k2] = __shfl_xor(bv[k2], 32, 64);
+      orow[k2] = __shfl_xor(rowa[k2], 32, 64);
     }
     if (lane < 32 && pr[qt] >= 0) {
       float* pd = pair_d + (int64_t)pr[qt] * BB_TOPK;
       int32_t* pi = pair_i + (int64_t)pr[qt] * BB_TOPK;
+      int a = 0, b = 0;
 #pragma unroll
-      for (int k2 = 0; k2 < BB_TOPK; ++k2) {
-        const float a = top[qt].d[k2], b = od[BB_TOPK - 1 - k2];
-        const int ia = top[qt].i[k2], ib = oi[BB_TOPK - 1 - k2];
-        const bool take_a = a < b || (a == b && ia < ib);
-        pd[k2] = take_a ? a : b;
-        pi[k2] = take_a ? ia : ib;
+      for (int k2 = 0; k2 < 4; ++k2) {  // merge two sorted lists of 4, keep 4
+        float va = FLT_MAX, vb = FLT_MAX;
+        int ra = -1, rb = -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u == a) {
+            va = bv[u];
+            ra = rowa[u];
+          }
+          if (u == b) {
+            vb = ov[u];
+            rb = orow[u];
+          }
+        }
+        const bool take_a = va < vb || (va == vb && ra < rb);
+        const float v = take_a ? va : vb;
+        const int r = take_a ? ra : rb;
+        if (take_a) ++a;
+        else ++b;
+        const bool ok = r >= 0;
+        const bool ok2 = ok && r + 16 < row_end;
+        pd[2 * k2] = ok ? v : FLT_MAX;
+        pi[2 * k2] = ok ? r : INT_MAX;
+        pd[2 * k2 + 1] = ok2 ? v : FLT_MAX;
+        pi[2 * k2 + 1] = ok2 ? r + 16 : INT_MAX;
       }
     }
   }
@@ -413,6 +518,14 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
         top.insert(v, id);
       }
     }
+  }
+  if (!nn) {  // candidates only (a full-D re-rank follows)
+#pragma unroll
+    for (int t = 0; t < BB_TOPK; ++t) {
+      const int pos = top.i[t];
+      cand_out[q * BB_TOPK + t] = (t < k && pos >= 0 && pos < N) ? perm[pos] : -1;
+    }
+    return;
   }
   float qv[DP];
 #pragma unroll

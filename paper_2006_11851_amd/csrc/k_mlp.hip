@@ -322,8 +322,9 @@ void launch_mlp_inputs(Ctx* c, const float* Qp, int ld, int64_t nq, const float*
 // ---------------------------------------------------------------------------
 // matrix-core inference layers
 
-constexpr int ML_WAVES = 4;
-constexpr int ML_QPB = ML_WAVES * 64;  // queries per block (two 32-query tiles per wave)
+constexpr int ML_WAVES = 8;
+constexpr int ML_THREADS = ML_WAVES * 64;
+constexpr int ML_QPB = ML_WAVES * 32;  // queries per block (one 32-query tile per wave)
 
 template <int KS>
 struct MlpSmem {
@@ -332,13 +333,13 @@ struct MlpSmem {
 };
 
 template <int KS>
-__device__ __forceinline__ void wtile_load(uint4 (&R)[(32 * KS * 2 + ML_QPB - 1) / ML_QPB], float& rb,
+__device__ __forceinline__ void wtile_load(uint4 (&R)[(32 * KS * 2 + ML_THREADS - 1) / ML_THREADS], float& rb,
                                            const uint16_t* __restrict__ Wb, const float* __restrict__ bias, int n0,
                                            int N, int tid) {
-  constexpr int CH = KS * 2, NCH = 32 * CH, PER = (NCH + ML_QPB - 1) / ML_QPB;
+  constexpr int CH = KS * 2, NCH = 32 * CH, PER = (NCH + ML_THREADS - 1) / ML_THREADS;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int cidx = tid + u * ML_QPB;
+    const int cidx = tid + u * ML_THREADS;
     uint4 v = make_uint4(0, 0, 0, 0);
     if (cidx < NCH) {
       const int row = cidx / CH, ch = cidx - row * CH;
@@ -350,12 +351,12 @@ __device__ __forceinline__ void wtile_load(uint4 (&R)[(32 * KS * 2 + ML_QPB - 1)
 }
 
 template <int KS>
-__device__ __forceinline__ void wtile_store(const uint4 (&R)[(32 * KS * 2 + ML_QPB - 1) / ML_QPB], float rb,
+__device__ __forceinline__ void wtile_store(const uint4 (&R)[(32 * KS * 2 + ML_THREADS - 1) / ML_THREADS], float rb,
                                             MlpSmem<KS>& S, int buf, int tid) {
-  constexpr int CH = KS * 2, NCH = 32 * CH, PER = (NCH + ML_QPB - 1) / ML_QPB;
+  constexpr int CH = KS * 2, NCH = 32 * CH, PER = (NCH + ML_THREADS - 1) / ML_THREADS;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int cidx = tid + u * ML_QPB;
+    const int cidx = tid + u * ML_THREADS;
     if (cidx < NCH) {
       const int row = cidx / CH, ch = cidx - row * CH;
       S.frag[buf][ch >> 1][(ch & 1) * 32 + row] = R[u];
@@ -390,20 +391,21 @@ struct TopP {
   }
 };
 
-constexpr int ML_P = 8;  // proposals kept per query (callers use the first k <= 8)
+constexpr int ML_P = 8;
+constexpr int ML_QT = 1;  // 32-query tiles per wave
 
 // MODE 0: Y[q][n] = bf16(GELU(X W^T + b)); MODE 1: top-P leaves + margin.
 template <int KS, int MODE>
-__global__ __launch_bounds__(256) void k_mlp_layer(const uint16_t* __restrict__ X, int64_t nq,
+__global__ __launch_bounds__(512) void k_mlp_layer(const uint16_t* __restrict__ X, int64_t nq,
                                                    const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
                                                    int N, uint16_t* __restrict__ Y, int kout,
                                                    int32_t* __restrict__ leaves, float* __restrict__ margin) {
   __shared__ MlpSmem<KS> sm;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t qbase = (int64_t)blockIdx.x * ML_QPB + wave * 64;
-  bf16x8 B[2][KS];
+  const int64_t qbase = (int64_t)blockIdx.x * ML_QPB + wave * 32;
+  bf16x8 B[ML_QT][KS];
 #pragma unroll
-  for (int qt = 0; qt < 2; ++qt) {
+  for (int qt = 0; qt < ML_QT; ++qt) {
     const int64_t q = qbase + qt * 32 + (lane & 31);
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
@@ -412,18 +414,18 @@ __global__ __launch_bounds__(256) void k_mlp_layer(const uint16_t* __restrict__ 
       B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
   }
-  TopP<ML_P> top[2];
-  float smax[2], ssum[2];
+  TopP<ML_P> top[ML_QT];
+  float smax[ML_QT], ssum[ML_QT];
   if (MODE == 1) {
 #pragma unroll
-    for (int qt = 0; qt < 2; ++qt) {
+    for (int qt = 0; qt < ML_QT; ++qt) {
       top[qt].init();
       smax[qt] = -FLT_MAX;
       ssum[qt] = 0.f;
     }
   }
   const int ntiles = (N + 31) / 32;
-  uint4 R[(32 * KS * 2 + ML_QPB - 1) / ML_QPB];
+  uint4 R[(32 * KS * 2 + ML_THREADS - 1) / ML_THREADS];
   float rb = 0.f;
   wtile_load<KS>(R, rb, Wb, bias, 0, N, tid);
   wtile_store<KS>(R, rb, sm, 0, tid);
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(256) void k_mlp_layer(const uint16_t* __restrict__ 
     }
     const int nbase = t * 32 + 4 * (lane >> 5);
 #pragma unroll
-    for (int qt = 0; qt < 2; ++qt) {
+    for (int qt = 0; qt < ML_QT; ++qt) {
       floatx16 acc = cinit;
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc, 0, 0, 0);
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(256) void k_mlp_layer(const uint16_t* __restrict__ 
   }
   if (MODE == 1) {
 #pragma unroll
-    for (int qt = 0; qt < 2; ++qt) {
+    for (int qt = 0; qt < ML_QT; ++qt) {
       // merge with the partner lane (same query, other 16 rows of each tile)
       const float om = __shfl_xor(smax[qt], 32, 64);
       const float os = __shfl_xor(ssum[qt], 32, 64);
@@ -543,6 +545,162 @@ __global__ __launch_bounds__(256) void k_mlp_layer(const uint16_t* __restrict__ 
   }
 }
 
+// Output layer, exact top-P in two passes over the weight tiles.  Pass 1
+// keeps, per value slot, the running maximum of the logits (one max per
+// logit, no ids).  After it the query's largest logit m is known, and the
+// P-th largest of its 32 slot maxima (two half-lanes x 16 slots) is at most
+// its P-th largest logit.  Pass 2 recomputes the logits on the matrix cores,
+// inserts only logits at or above that bound into the sorted top-P, and sums
+// exp(l - m) for the softmax normaliser, skipping tiles whose logits are all
+// below m - 30 (their terms are below 1e-13 of the largest).
+template <int KS, int PP>
+__global__ __launch_bounds__(512) void k_mlp_out_topk(const uint16_t* __restrict__ X, int64_t nq,
+                                                      const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
+                                                      int N, int kout, int32_t* __restrict__ leaves,
+                                                      float* __restrict__ margin) {
+  __shared__ MlpSmem<KS> sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t qbase = (int64_t)blockIdx.x * ML_QPB + wave * 32;
+  bf16x8 B[ML_QT][KS];
+#pragma unroll
+  for (int qt = 0; qt < ML_QT; ++qt) {
+    const int64_t q = qbase + qt * 32 + (lane & 31);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      uint4 u = make_uint4(0, 0, 0, 0);
+      if (q < nq) u = reinterpret_cast<const uint4*>(X + q * (KS * 16))[2 * kk + (lane >> 5)];
+      B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+  }
+  float slot[ML_QT][16], tau[ML_QT], mx[ML_QT], ssum[ML_QT];
+  TopP<PP> top[ML_QT];
+#pragma unroll
+  for (int qt = 0; qt < ML_QT; ++qt) {
+    ssum[qt] = 0.f;
+    top[qt].init();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) slot[qt][r] = -FLT_MAX;
+  }
+  const int ntiles = (N + 31) / 32;
+  uint4 R[(32 * KS * 2 + ML_THREADS - 1) / ML_THREADS];
+  float rb = 0.f;
+  for (int pass = 0; pass < 2; ++pass) {
+    wtile_load<KS>(R, rb, Wb, bias, 0, N, tid);
+    __syncthreads();  // the previous pass has finished reading the buffers
+    wtile_store<KS>(R, rb, sm, 0, tid);
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+      const int buf = t & 1;
+      const bool more = t + 1 < ntiles;
+      if (more) wtile_load<KS>(R, rb, Wb, bias, (t + 1) * 32, N, tid);
+      bf16x8 A[KS];
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        const uint4 u = sm.frag[buf][kk][lane];
+        A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+      }
+      floatx16 cinit;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 b4 = *reinterpret_cast<const float4*>(&sm.bias[buf][8 * g + 4 * (lane >> 5)]);
+        cinit[4 * g + 0] = b4.x;
+        cinit[4 * g + 1] = b4.y;
+        cinit[4 * g + 2] = b4.z;
+        cinit[4 * g + 3] = b4.w;
+      }
+      const int nbase = t * 32 + 4 * (lane >> 5);
+#pragma unroll
+      for (int qt = 0; qt < ML_QT; ++qt) {
+        floatx16 acc = cinit;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc, 0, 0, 0);
+        // rows past N carry bias -FLT_MAX and zero weights: acc = -FLT_MAX, never selected
+        if (pass == 0) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) slot[qt][r] = fmaxf(slot[qt][r], acc[r]);
+        } else {
+          float mloc = acc[0];
+#pragma unroll
+          for (int r = 1; r < 16; ++r) mloc = fmaxf(mloc, acc[r]);
+          if (__any(mloc >= tau[qt])) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int n = nbase + 8 * (r >> 2) + (r & 3);
+              if (acc[r] >= tau[qt] && acc[r] > top[qt].v[PP - 1]) top[qt].insert(acc[r], n);
+            }
+          }
+          if (__any(mloc >= mx[qt] - 30.0f)) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) ssum[qt] += __expf(acc[r] - mx[qt]);
+          }
+        }
+      }
+      if (more) wtile_store<KS>(R, rb, sm, buf ^ 1, tid);
+      __syncthreads();
+    }
+    if (pass == 0) {
+      // m = largest logit; tau = kout-th largest of the 32 slot maxima
+#pragma unroll
+      for (int qt = 0; qt < ML_QT; ++qt) {
+        TopP<ML_P> s8;
+        s8.init();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          s8.insert(slot[qt][r], r);
+          s8.insert(__shfl_xor(slot[qt][r], 32, 64), 16 + r);
+        }
+        float tk = s8.v[0];
+#pragma unroll
+        for (int u = 1; u < ML_P; ++u)
+          if (u < kout) tk = s8.v[u];
+        tau[qt] = tk;
+        mx[qt] = s8.v[0];
+      }
+    }
+  }
+#pragma unroll
+  for (int qt = 0; qt < ML_QT; ++qt) {
+    const float s = ssum[qt] + __shfl_xor(ssum[qt], 32, 64);  // both halves share mx
+    float ov[PP];
+    int oi[PP];
+#pragma unroll
+    for (int t = 0; t < PP; ++t) {
+      ov[t] = __shfl_xor(top[qt].v[t], 32, 64);
+      oi[t] = __shfl_xor(top[qt].i[t], 32, 64);
+    }
+    const int64_t q = qbase + qt * 32 + (lane & 31);
+    if (lane < 32 && q < nq) {
+      int a = 0, b = 0;
+      float best[2] = {-FLT_MAX, -FLT_MAX};
+#pragma unroll
+      for (int t = 0; t < PP; ++t) {
+        float va = -FLT_MAX, vb = -FLT_MAX;
+        int ia = INT_MAX, ib = INT_MAX;
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+          if (u == a) {
+            va = top[qt].v[u];
+            ia = top[qt].i[u];
+          }
+          if (u == b) {
+            vb = ov[u];
+            ib = oi[u];
+          }
+        }
+        const bool take_a = (va > vb) || (va == vb && ia < ib);
+        const int id = take_a ? ia : ib;
+        const float vv = take_a ? va : vb;
+        if (take_a) ++a;
+        else ++b;
+        if (t < kout) leaves[q * kout + t] = (id == INT_MAX) ? -1 : id;
+        if (t < 2) best[t] = vv;
+      }
+      // p1 - p2 = (1 - exp(l2 - l1)) / sum_j exp(l_j - l1), with l1 = mx
+      margin[q] = (best[1] == -FLT_MAX) ? 1.0f : (1.0f - __expf(best[1] - best[0])) / s;
+    }
+  }
+}
+
 #define PTS_MLP_KS_SWITCH(K, ...)                                                                  \
   switch (K) {                                                                                     \
     case 32: { constexpr int KSC = 2; __VA_ARGS__; } break;                                        \
@@ -558,7 +716,7 @@ void launch_mlp_hidden(Ctx* c, const uint16_t* X, int64_t nq, int K, const uint1
   ProfScope ps(c, "mlp_hidden_mfma");
   if (nq == 0) return;
   PTS_REQUIRE(N % 4 == 0, PTS_ERR_UNSUPPORTED, "MLP hidden width must be a multiple of 4");
-  PTS_MLP_KS_SWITCH(K, hipLaunchKernelGGL((k_mlp_layer<KSC, 0>), dim3((unsigned)ceil_div(nq, ML_QPB)), dim3(256), 0,
+  PTS_MLP_KS_SWITCH(K, hipLaunchKernelGGL((k_mlp_layer<KSC, 0>), dim3((unsigned)ceil_div(nq, ML_QPB)), dim3(ML_THREADS), 0,
                                           c->stream, X, nq, Wb, bias, N, Y, N, nullptr, nullptr));
   check_launch("k_mlp_layer<hidden>");
 }
@@ -568,9 +726,14 @@ void launch_mlp_out_topk(Ctx* c, const uint16_t* X, int64_t nq, int K, const uin
   ProfScope ps(c, "mlp_out_topk_mfma");
   if (nq == 0) return;
   PTS_REQUIRE(k >= 1 && k <= ML_P, PTS_ERR_ARG, "proposals must be 1..8");
-  PTS_MLP_KS_SWITCH(K, hipLaunchKernelGGL((k_mlp_layer<KSC, 1>), dim3((unsigned)ceil_div(nq, ML_QPB)), dim3(256), 0,
-                                          c->stream, X, nq, Wb, bias, N, nullptr, k, leaves, margin));
-  check_launch("k_mlp_layer<out>");
+  if (k <= 4) {
+    PTS_MLP_KS_SWITCH(K, hipLaunchKernelGGL((k_mlp_out_topk<KSC, 4>), dim3((unsigned)ceil_div(nq, ML_QPB)), dim3(ML_THREADS),
+                                            0, c->stream, X, nq, Wb, bias, N, k, leaves, margin));
+  } else {
+    PTS_MLP_KS_SWITCH(K, hipLaunchKernelGGL((k_mlp_out_topk<KSC, 8>), dim3((unsigned)ceil_div(nq, ML_QPB)), dim3(ML_THREADS),
+                                            0, c->stream, X, nq, Wb, bias, N, k, leaves, margin));
+  }
+  check_launch("k_mlp_out_topk");
 }
 
 }  // namespace pts

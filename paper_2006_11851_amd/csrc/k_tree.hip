@@ -65,6 +65,79 @@ __global__ __launch_bounds__(256) void k_descend(const float* __restrict__ Qp, i
   leaf[q] = leaf_of_node[node];
 }
 
+// Descent restricted to queries whose margin is below thr: a compaction
+// pass lists them, the descent runs over the list (its length read on the
+// device), and every other query gets leaf -1.
+__global__ __launch_bounds__(256) void k_compact_low(const float* __restrict__ margin, int64_t nq, float thr,
+                                                     int32_t* __restrict__ list, int32_t* __restrict__ n,
+                                                     int32_t* __restrict__ leaf) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  leaf[q] = -1;
+  if (!(margin[q] >= thr)) list[atomicAdd(n, 1)] = (int32_t)q;
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_descend_list(const float* __restrict__ Qp, const int32_t* __restrict__ list,
+                                                      const int32_t* __restrict__ n, const float* __restrict__ cent,
+                                                      const int32_t* __restrict__ first_child,
+                                                      const int32_t* __restrict__ n_children,
+                                                      const int32_t* __restrict__ leaf_of_node,
+                                                      int32_t* __restrict__ leaf) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= *n) return;
+  const int64_t q = list[t];
+  float qv[DP];
+#pragma unroll
+  for (int k = 0; k < DP; k += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(Qp + q * DP + k);
+    qv[k] = v.x;
+    qv[k + 1] = v.y;
+    qv[k + 2] = v.z;
+    qv[k + 3] = v.w;
+  }
+  int node = 0;
+  for (int depth = 0; depth < 64; ++depth) {
+    const int nc = n_children[node];
+    if (nc == 0) break;
+    const int f = first_child[node];
+    float best = FLT_MAX;
+    int bj = 0;
+    for (int j = 0; j < nc; ++j) {
+      const float* cr = cent + (int64_t)(f + j) * DP;
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < DP; k += 4) {
+        const float4 cv = *reinterpret_cast<const float4*>(cr + k);
+        const float t0 = qv[k] - cv.x, t1 = qv[k + 1] - cv.y, t2 = qv[k + 2] - cv.z, t3 = qv[k + 3] - cv.w;
+        acc = fmaf(t0, t0, acc);
+        acc = fmaf(t1, t1, acc);
+        acc = fmaf(t2, t2, acc);
+        acc = fmaf(t3, t3, acc);
+      }
+      if (acc < best) {
+        best = acc;
+        bj = j;
+      }
+    }
+    node = f + bj;
+  }
+  leaf[q] = leaf_of_node[node];
+}
+
+void launch_descend_low_margin(Ctx* c, const float* Qp, int64_t nq, int dp, const float* margin, float thr,
+                               const float* cent, const int32_t* first_child, const int32_t* n_children,
+                               const int32_t* leaf_of_node, int32_t* list, int32_t* n, int32_t* leaf) {
+  ProfScope ps(c, "tree_descend_low");
+  if (nq == 0) return;
+  hipLaunchKernelGGL(k_compact_low, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, margin, nq, thr, list, n,
+                     leaf);
+  check_launch("k_compact_low");
+  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_descend_list<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
+                                       c->stream, Qp, list, n, cent, first_child, n_children, leaf_of_node, leaf));
+  check_launch("k_descend_list");
+}
+
 void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* cent, const int32_t* first_child,
                     const int32_t* n_children, const int32_t* leaf_of_node, int32_t* leaf) {
   ProfScope ps(c, "tree_descend");
@@ -363,8 +436,9 @@ void launch_zero_i32(Ctx* c, int32_t* p, int64_t n) {
 namespace pts {
 
 // pair lists of the learned search: slot s of query q scans leaf
-// pair_leaf[q * P + s] (-1 = unused).  Margin below thr: the tree's leaf
-// only (the fallback); otherwise the P proposed leaves.
+// pair_leaf[q * (P + 1) + s] (-1 = unused): slots 0..P-1 the P proposed
+// leaves; slot P the tree's own leaf when the margin is below thr (the
+// fallback) and that leaf is not already proposed.
 __global__ __launch_bounds__(256) void k_learned_pairs(const int32_t* __restrict__ prop, const float* __restrict__ margin,
                                                        const int32_t* __restrict__ dleaf, int64_t nq, int P, float thr,
                                                        int n_leaves, int32_t* __restrict__ pair_leaf,
@@ -372,11 +446,15 @@ __global__ __launch_bounds__(256) void k_learned_pairs(const int32_t* __restrict
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   const bool fb = !(margin[q] >= thr);
+  const int dl = dleaf[q];
+  bool dup = false;
   for (int s = 0; s < P; ++s) {
-    int l = fb ? (s == 0 ? dleaf[q] : -1) : prop[q * P + s];
+    int l = prop[q * P + s];
     if (l < 0 || l >= n_leaves) l = -1;
-    pair_leaf[q * P + s] = l;
+    dup = dup || (l == dl);
+    pair_leaf[q * (P + 1) + s] = l;
   }
+  pair_leaf[q * (P + 1) + P] = (fb && !dup && dl >= 0 && dl < n_leaves) ? dl : -1;
   if (fb) atomicAdd(fallbacks, 1);
 }
 

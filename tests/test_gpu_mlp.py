@@ -144,16 +144,24 @@ def test_learned_search_teacher_forced(learned_c1, mode):
     Qp = _np(qp).astype(np.float64)
     Zp = _np(ctx.exemplar_projection()).astype(np.float64)
     L, M, DL = _np(leaves), _np(margin), _np(dleaf)
-    lists = [[int(DL[i])] if not (M[i] >= 0.2) else list(L[i]) for i in range(L.shape[0])]
+    # proposals, plus the tree's leaf for low-margin queries
+    lists = [list(L[i]) + ([int(DL[i])] if not (M[i] >= 0.2) and DL[i] not in L[i] else [])
+             for i in range(L.shape[0])]
     assert st.fallbacks == sum(1 for i in range(L.shape[0]) if not (M[i] >= 0.2))
     if mode == "learned":
         nn_o, _ = tree.search_leaves(Qp, Zp, t, lists)
     else:
         cand = []
         for i, ls in enumerate(lists):
-            mem = np.concatenate([t.leaf_members(l) for l in ls])
-            ids, _ = obf16.brute_topk(Qp[i : i + 1], Zp[mem], 8)
-            cand.append(mem[ids[0]])
+            pos, sc = [], []
+            for l in ls:
+                mem = t.leaf_members(l)
+                p_, s_ = obf16.class_candidates(Qp[i], Zp[mem])
+                pos.append(mem[p_])
+                sc.append(s_)
+            pos, sc = np.concatenate(pos), np.concatenate(sc)
+            o = np.lexsort((pos, sc))[:8]
+            cand.append(pos[o])
         nn_o, _ = obf16.rerank(Qp, Zp, cand)
     ok, same, _ = parity.nn_agreement(Qp, Zp, _np(nn), nn_o)
     assert ok >= 0.999, (ok, same)

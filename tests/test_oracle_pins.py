@@ -507,3 +507,23 @@ def test_residual_offset_ranks_by_full_distance_estimate():
     assert np.array_equal(ids_full, ids_pca)
     ids_direct = exact.topk_direct(pca.project(Q, mu, B), Zp, 3, offset=off)[0]
     assert np.array_equal(ids_direct, ids_pca)
+
+
+def test_class_candidates_contain_the_minimum_and_follow_the_layout():
+    r = np.random.default_rng(22)
+    for m in (1, 7, 16, 33, 100, 257):
+        Z = r.normal(size=(m, 8)).astype(np.float32).astype(np.float64)
+        q = r.normal(size=8).astype(np.float32).astype(np.float64)
+        pos, sc = bf16.class_candidates(q, Z)
+        d = ((bf16.round_bf16(Z) - bf16.round_bf16(q[None]))**2).sum(1)
+        assert int(np.argmin(d)) in set(pos.tolist())
+        assert len(pos) <= 8 and len(pos) == len(set(pos.tolist()))
+        # pairs: every kept row's partner (i +- 16 inside its 32-row tile) is kept when it exists
+        for i in pos:
+            j = i + 16 if (i % 32) < 16 else i - 16
+            if j < m:
+                assert j in set(pos.tolist())
+        # scores are class minima: no row of a kept class beats its score
+        for i, v in zip(pos, sc):
+            cls = [k for k in range(m) if k % 16 == i % 16]
+            assert v == min(d[k] for k in cls)
