@@ -46,6 +46,7 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
   const int64_t N = (int64_t)(ex.Hz - w + 1) * (ex.Wz - w + 1);
   EstepStats st;
   st.nq = nq;
+  bool dist_done = false;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timing) {
     PTS_HIP(hipEventCreate(&e0));
@@ -88,7 +89,7 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       PTS_REQUIRE(ix->has_bf16, PTS_ERR_STATE, "BRUTE_BF16 needs an index built with make_bf16");
       float* qp = c->buf<float>("qproj", (size_t)nq * ix->dp);
       project_on(c, *ix, x, H, W, p.stride, qp);
-      search_brute_bf16(c, ex, *ix, x, H, W, p, qp, nq, nn);
+      dist_done = search_brute_bf16(c, ex, *ix, x, H, W, p, qp, nq, nn, dist);
       break;
     }
     case PTS_MODE_LEARNED:
@@ -99,13 +100,14 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
                   "MLP shape does not match the index (n_in = d, n_out = leaves)");
       float* qp = c->buf<float>("qproj", (size_t)nq * ix->dp);
       project_on(c, *ix, x, H, W, p.stride, qp);
-      st.fallbacks = search_learned(c, ex, *ix, x, H, W, p, qp, nq, nn, p.mode == PTS_MODE_LEARNED_BF16, timing);
+      st.fallbacks = search_learned(c, ex, *ix, x, H, W, p, qp, nq, nn, dist, &dist_done,
+                                    p.mode == PTS_MODE_LEARNED_BF16, timing);
       break;
     }
     default:
       fail(PTS_ERR_ARG, "unknown search mode");
   }
-  launch_winner_dist(c, x, H, W, w, p.stride, ex.img, ex.Hz, ex.Wz, nn, dist);
+  if (!dist_done) launch_winner_dist(c, x, H, W, w, p.stride, ex.img, ex.Hz, ex.Wz, nn, dist);
   if (timing) {
     PTS_HIP(hipEventRecord(e1, c->stream));
     PTS_HIP(hipEventSynchronize(e1));

@@ -1,12 +1,13 @@
-// Accelerated search forms: placeholders until their kernels land.
+// The accelerated search forms: BF16 brute force and the learned leaf
+// proposal, each ending in an FP32 re-rank.
 #include "bf16_learned.hpp"
 #include "kernels_bf16.hpp"
 #include "kernels_mlp.hpp"
 
 namespace pts {
 
-void search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
-                       const float* qp, int64_t nq, int32_t* nn) {
+bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
+                       const float* qp, int64_t nq, int32_t* nn, float* dist) {
   const int k = p.topk <= 0 ? 8 : p.topk;
   PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
   uint16_t* qb = c->buf<uint16_t>("qbf16", (size_t)nq * ix.dk);
@@ -18,18 +19,19 @@ void search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
   launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, ix.N, ix.dk, S, pd, pi);
   if (p.rerank_full) {
-    int32_t* cand = c->buf<int32_t>("bb_cand", (size_t)nq * 8);
-    launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
-                            ix.perm.as<int32_t>(), ix.N, cand, nullptr);
-    launch_rerank_full(c, x, H, W, ix.w, p.stride, ex.img, ex.Hz, ex.Wz, cand, k, nq, nn);
-  } else {
-    launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
-                            ix.perm.as<int32_t>(), ix.N, nullptr, nn);
+    launch_select_rerank_full(c, pd, pi, nq, S, 1, nq, nullptr, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
+                              p.stride, ex.img, ex.Hz, ex.Wz, nn, dist);
+    return dist != nullptr;
   }
+  launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
+                          ix.perm.as<int32_t>(), ix.N, nullptr, nn);
+  return false;
 }
 
 int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
-                       const float* qp, int64_t nq, int32_t* nn, bool bf16_scan, bool count_fallbacks) {
+                       const float* qp, int64_t nq, int32_t* nn, float* dist, bool* dist_done, bool bf16_scan,
+                       bool count_fallbacks) {
+  *dist_done = false;
   const int P = p.n_proposals <= 0 ? 4 : p.n_proposals;
   PTS_REQUIRE(P >= 1 && P <= 8 && P <= ix.tree.n_leaves(), PTS_ERR_ARG, "n_proposals must be 1..8 (and <= leaves)");
   const int L = ix.tree.n_leaves();
@@ -72,10 +74,9 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     launch_leaf_scan_bf16(c, qb, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b, max_tiles,
                           pdd, pii);
     if (p.rerank_full) {
-      int32_t* cand = c->buf<int32_t>("bb_cand", (size_t)nq * 8);
-      launch_merge_rerank_pca(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
-                              ix.perm.as<int32_t>(), ix.N, cand, nullptr);
-      launch_rerank_full(c, x, H, W, ix.w, p.stride, ex.img, ex.Hz, ex.Wz, cand, k, nq, nn);
+      launch_select_rerank_full(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
+                                p.stride, ex.img, ex.Hz, ex.Wz, nn, dist);
+      *dist_done = dist != nullptr;
     } else {
       launch_merge_rerank_pca(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
                               ix.perm.as<int32_t>(), ix.N, nullptr, nn);

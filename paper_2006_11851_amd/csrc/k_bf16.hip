@@ -576,56 +576,182 @@ void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i,
   check_launch("k_merge_rerank_pca");
 }
 
-// full-D re-rank of given candidate ids (original exemplar ids): one wave
-// per query, lanes over window pixels
-__global__ __launch_bounds__(256) void k_rerank_full(const float4* __restrict__ x, int H, int W, int w, int s,
-                                                     int cols, const float4* __restrict__ ex, int Hz, int Wz,
-                                                     const int32_t* __restrict__ cand, int k, int64_t nq,
-                                                     int32_t* __restrict__ nn) {
-  const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= nq) return;
-  const int i = (int)(q / cols), j = (int)(q - (int64_t)i * cols);
-  const int v = i * s, u = j * s;
+// Merge of the partial candidate lists of a query followed by the re-rank of
+// the best k in full dimension, fused.  Phase 1: one thread per query merges
+// its lists (each sorted by (score, position)) into the 8 best by (score,
+// position) and maps positions to exemplar ids in LDS.  Phase 2: 16 lanes
+// per query (4 queries per wave at a time) gather the query window and the k
+// candidate windows pixel by pixel from the two images, reduce the 8
+// squared distances with a halving butterfly, and keep the smallest (ties:
+// lower exemplar id).  Writes nn and, if dist is given, the full-D distance
+// of the winner.
+
+__device__ __forceinline__ bool lex_lt(float a, int ia, float b, int ib) { return a < b || (a == b && ia < ib); }
+
+struct Top8Lex {
+  float d[8];
+  int i[8];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      d[t] = FLT_MAX;
+      i[t] = INT_MAX;
+    }
+  }
+  __device__ __forceinline__ void insert(float v, int id) {
+    bool lt[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) lt[t] = lex_lt(v, id, d[t], i[t]);
+#pragma unroll
+    for (int t = 7; t > 0; --t) {
+      d[t] = lt[t - 1] ? d[t - 1] : (lt[t] ? v : d[t]);
+      i[t] = lt[t - 1] ? i[t - 1] : (lt[t] ? id : i[t]);
+    }
+    d[0] = lt[0] ? v : d[0];
+    i[0] = lt[0] ? id : i[0];
+  }
+};
+
+constexpr int SR_QPB = 256;
+
+__global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
+    const float* __restrict__ part_d, const int32_t* __restrict__ part_i, int64_t nq, int S, int64_t qs, int64_t ss,
+    const int32_t* __restrict__ valid, int k, const int32_t* __restrict__ perm, int64_t npos,
+    const float4* __restrict__ x, int W, int w, int s, int cols, const float4* __restrict__ ex, int Hz, int Wz,
+    int32_t* __restrict__ nn, float* __restrict__ dist) {
+  __shared__ int32_t cand[BB_TOPK][SR_QPB];
+  const int tid = threadIdx.x;
+  const int64_t q0 = (int64_t)blockIdx.x * SR_QPB;
+  {
+    const int64_t q = q0 + tid;
+    Top8Lex top;
+    top.init();
+    if (q < nq) {
+      for (int li = 0; li < S; ++li) {
+        const int64_t row = q * qs + (int64_t)li * ss;
+        if (valid && valid[row] < 0) continue;
+        const float4 da = reinterpret_cast<const float4*>(part_d + row * BB_TOPK)[0];
+        const float4 db = reinterpret_cast<const float4*>(part_d + row * BB_TOPK)[1];
+        const int4 ia = reinterpret_cast<const int4*>(part_i + row * BB_TOPK)[0];
+        const int4 ib = reinterpret_cast<const int4*>(part_i + row * BB_TOPK)[1];
+        const float dv[8] = {da.x, da.y, da.z, da.w, db.x, db.y, db.z, db.w};
+        const int iv[8] = {ia.x, ia.y, ia.z, ia.w, ib.x, ib.y, ib.z, ib.w};
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          // lists are sorted: once nothing in the wave improves, skip the insertion network
+          if (__any(lex_lt(dv[t], iv[t], top.d[7], top.i[7]))) top.insert(dv[t], iv[t]);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < BB_TOPK; ++t) {
+      const int pos = top.i[t];
+      cand[t][tid] = (t < k && pos >= 0 && pos < npos) ? perm[pos] : -1;
+    }
+  }
+  __syncthreads();
+  const int lane = tid & 63, g = lane & 15, grp = lane >> 4;
   const int nu = Wz - w + 1;
   const int64_t N = (int64_t)(Hz - w + 1) * nu;
-  float best = FLT_MAX;
-  int bid = INT_MAX;
-  for (int t = 0; t < k; ++t) {
-    const int e = cand[q * BB_TOPK + t];
-    if (e < 0 || e >= N) continue;
-    const int ey = e / nu, exx = e - ey * nu;
-    float acc = 0.f;
-    for (int p = lane; p < w * w; p += 64) {
-      const int dy = p / w, dx = p - dy * w;
+  const int npx = w * w;
+  const int ci = ((g >> 3) & 1) * 4 + ((g >> 2) & 1) * 2 + ((g >> 1) & 1);  // candidate held after the butterfly
+  for (int it = 0; it < SR_QPB / 16; ++it) {
+    const int ql = (tid >> 6) * 64 + it * 4 + grp;
+    const int64_t q = q0 + ql;
+    if (q >= nq) continue;  // uniform per 16-lane group; shuffles stay inside the group
+    const int qi = (int)(q / cols), qj = (int)(q - (int64_t)qi * cols);
+    const int v = qi * s, u = qj * s;
+    int64_t eb[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      int e = cand[c][ql];
+      if (e < 0 || e >= N) e = 0;  // read an in-bounds window, result discarded below
+      const int ey = e / nu;
+      eb[c] = (int64_t)ey * Wz + (e - ey * nu);
+    }
+    float acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    int dy = 0, dx = g;
+    while (dx >= w) {
+      dx -= w;
+      ++dy;
+    }
+    for (int p = g; p < npx; p += 16) {
       int xx = u + dx;
       if (xx >= W) xx -= W;
       const float4 a = x[(int64_t)(v + dy) * W + xx];
-      const float4 b = ex[(int64_t)(ey + dy) * Wz + exx + dx];
-      const float t0 = a.x - b.x, t1 = a.y - b.y, t2 = a.z - b.z, t3 = a.w - b.w;
-      acc = fmaf(t0, t0, acc);
-      acc = fmaf(t1, t1, acc);
-      acc = fmaf(t2, t2, acc);
-      acc = fmaf(t3, t3, acc);
-    }
+      const int64_t eo = (int64_t)dy * Wz + dx;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (acc < best || (acc == best && e < bid)) {
-      best = acc;
-      bid = e;
+      for (int c = 0; c < 8; ++c) {
+        const float4 b = ex[eb[c] + eo];
+        const float t0 = a.x - b.x, t1 = a.y - b.y, t2 = a.z - b.z, t3 = a.w - b.w;
+        acc[c] = fmaf(t0, t0, acc[c]);
+        acc[c] = fmaf(t1, t1, acc[c]);
+        acc[c] = fmaf(t2, t2, acc[c]);
+        acc[c] = fmaf(t3, t3, acc[c]);
+      }
+      dx += 16;
+      while (dx >= w) {
+        dx -= w;
+        ++dy;
+      }
+    }
+    // halving butterfly over the 16 lanes: after it, lane g holds the full
+    // sum of candidate ci(g) (lanes g and g^1 hold the same one)
+    float b4[4];
+    const bool h8 = g & 8, h4 = g & 4, h2 = g & 2;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float keep = h8 ? acc[t + 4] : acc[t];
+      const float send = h8 ? acc[t] : acc[t + 4];
+      b4[t] = keep + __shfl_xor(send, 8, 64);
+    }
+    float b2[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const float keep = h4 ? b4[t + 2] : b4[t];
+      const float send = h4 ? b4[t] : b4[t + 2];
+      b2[t] = keep + __shfl_xor(send, 4, 64);
+    }
+    float tot;
+    {
+      const float keep = h2 ? b2[1] : b2[0];
+      const float send = h2 ? b2[0] : b2[1];
+      tot = keep + __shfl_xor(send, 2, 64);
+    }
+    tot += __shfl_xor(tot, 1, 64);
+    const int e = cand[ci][ql];
+    float bd = (ci < k && e >= 0 && e < N) ? tot : FLT_MAX;
+    int bi = (ci < k && e >= 0 && e < N) ? e : INT_MAX;
+#pragma unroll
+    for (int off = 2; off <= 8; off <<= 1) {
+      const float od = __shfl_xor(bd, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (lex_lt(od, oi, bd, bi)) {
+        bd = od;
+        bi = oi;
+      }
+    }
+    if (g == 0) {
+      nn[q] = (bi == INT_MAX) ? -1 : bi;
+      if (dist) dist[q] = (bi == INT_MAX) ? __int_as_float(0x7fc00000) : sqrtf(bd);
     }
   }
-  if (lane == 0) nn[q] = (bid == INT_MAX) ? -1 : bid;
 }
 
-void launch_rerank_full(Ctx* c, const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
-                        const int32_t* cand, int k, int64_t nq, int32_t* nn) {
-  ProfScope ps(c, "rerank_full");
+void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
+                               int64_t ss, const int32_t* valid, int k, const int32_t* perm, int64_t npos,
+                               const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
+                               int32_t* nn, float* dist) {
+  ProfScope ps(c, "select_rerank_full");
   if (nq == 0) return;
-  hipLaunchKernelGGL(k_rerank_full, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, c->stream,
-                     reinterpret_cast<const float4*>(x), H, W, w, s, W / s, reinterpret_cast<const float4*>(ex), Hz,
-                     Wz, cand, k, nq, nn);
-  check_launch("k_rerank_full");
+  PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
+  PTS_REQUIRE(w >= 1 && w <= Hz && w <= Wz && w <= H && W % s == 0, PTS_ERR_ARG, "select_rerank_full: bad geometry");
+  hipLaunchKernelGGL(k_select_rerank_full, dim3((unsigned)ceil_div(nq, SR_QPB)), dim3(SR_QPB), 0, c->stream, part_d,
+                     part_i, nq, S, qs, ss, valid, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
+                     reinterpret_cast<const float4*>(ex), Hz, Wz, nn, dist);
+  check_launch("k_select_rerank_full");
 }
 
 }  // namespace pts

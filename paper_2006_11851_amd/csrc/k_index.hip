@@ -3,7 +3,8 @@
 //  * mean and covariance of all exemplar windows, gathered straight from the
 //    exemplar image, accumulated in FP64 (the covariance feeds the FP64
 //    eigensolve; centred products avoid the cancellation of E[zz^T]-mu mu^T);
-//  * projection of windows onto the basis, P = (x - mu) B, FP32, gathered
+//  * projection of windows onto the basis, P = (x - mu) B, FP32 on the
+//    matrix cores, gathered
 //    from an image on either window grid (exemplar: all corners; output:
 //    stride s with the x wrap) - used for the index and for every query;
 //  * k-means helpers: nearest-centre assignment (ties to the lowest centre),
@@ -198,72 +199,94 @@ void launch_mean_cov_image(Ctx* c, const float* img, int H, int W, int w, double
 }
 
 // ---------------------------------------------------------------------------
-// projection P[win][k] = sum_j (x_win[j] - mu[j]) B[j][k], FP32.
-// 256 threads, 64 windows per block; D in chunks of 8 pixels (32 elements)
-// staged through LDS together with the matching 32 rows of B.
+// projection P[win][k] = sum_j (x_win[j] - mu[j]) B[j][k], FP32, on the
+// matrix cores (v_mfma_f32_16x16x4_f32: FP32 operands, FP32 accumulation).
+// One MFMA step covers one pixel of the window (its 4 channels are the 4
+// k-slices of the instruction): A = 16 basis columns of those 4 rows (from
+// LDS), B = that pixel of 16 windows (read straight from the image: windows
+// overlap, so the reads hit in cache).  The output tile is 16 basis columns
+// x 16 windows; lane l holds window l % 16, columns 4 (l / 16) + 0..3.
+// Each wave owns 2 tiles of 16 windows; the basis goes through LDS in
+// chunks of 16 pixels (64 rows), shared by the 4 waves of the block.
 
-constexpr int PJ_T = 64, PJ_K = 32, PJ_MAXDP = 128;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_project(WinGeom g, int64_t n, int D, const float* __restrict__ mu,
-                                                 const float* __restrict__ B, int dp, float* __restrict__ P) {
-  __shared__ float Xs[PJ_T][PJ_K + 1];
-  __shared__ float Bs[PJ_K][PJ_MAXDP];
-  const int tid = threadIdx.x, tq = tid & 15, tk = tid >> 4;
-  const int64_t w0 = (int64_t)blockIdx.x * PJ_T;
-  const int nk = (dp + 15) / 16;  // outputs per thread along k (<= 8)
-  float acc[4][8];
+constexpr int PM_WT = 2;              // 16-window tiles per wave
+constexpr int PM_WPB = 4 * 16 * PM_WT;  // windows per block (4 waves)
+constexpr int PM_CP = 16;             // pixels per basis chunk
+
+template <int NKT>
+__global__ __launch_bounds__(256) void k_project_mfma(WinGeom g, int64_t n, int D, const float* __restrict__ mu,
+                                                      const float* __restrict__ B, int dp, float* __restrict__ P) {
+  constexpr int DPAD = 16 * NKT;
+  constexpr int LS = DPAD + ((DPAD % 32 == 0) ? 16 : 0);  // row stride: the two half-waves hit disjoint banks
+  __shared__ float Bs[PM_CP * 4][LS];
+  __shared__ float mus[PM_CP * 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const float* img = reinterpret_cast<const float*>(g.img);
+  int64_t win[PM_WT];
+  int vrow[PM_WT], ucol[PM_WT];
+  bool ok[PM_WT];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int wt = 0; wt < PM_WT; ++wt) {
+    win[wt] = (int64_t)blockIdx.x * PM_WPB + wave * (16 * PM_WT) + wt * 16 + col;
+    ok[wt] = win[wt] < n;
+    const int64_t wc = ok[wt] ? win[wt] : 0;
+    const int i = (int)(wc / g.cols), j = (int)(wc - (int64_t)i * g.cols);
+    vrow[wt] = i * g.s;
+    ucol[wt] = j * g.s;
+  }
+  floatx4 acc[PM_WT][NKT];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.f;
-  for (int j0 = 0; j0 < D; j0 += PJ_K) {
-    // 64 windows x 8 pixels: 512 pixel loads, 2 per thread
-    for (int t = tid; t < PJ_T * (PJ_K / 4); t += 256) {
-      const int r = t >> 3, pp = t & 7;
-      const int64_t win = w0 + r;
-      const int j = j0 + 4 * pp;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (win < n && j < D) {
-        v = win_pixel(g, win, j >> 2);
-        v.x -= mu[j];
-        v.y -= mu[j + 1];
-        v.z -= mu[j + 2];
-        v.w -= mu[j + 3];
-      }
-      Xs[r][4 * pp + 0] = v.x;
-      Xs[r][4 * pp + 1] = v.y;
-      Xs[r][4 * pp + 2] = v.z;
-      Xs[r][4 * pp + 3] = v.w;
+  for (int wt = 0; wt < PM_WT; ++wt)
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) acc[wt][kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int npx = D / 4;
+  for (int p0 = 0; p0 < npx; p0 += PM_CP) {
+    __syncthreads();  // the previous chunk has been consumed
+    for (int t = tid; t < PM_CP * 4 * DPAD; t += 256) {
+      const int r = t / DPAD, k = t - r * DPAD;
+      const int d = 4 * p0 + r;
+      Bs[r][k] = (d < D && k < dp) ? B[(int64_t)d * dp + k] : 0.f;
     }
-    for (int t = tid; t < PJ_K * dp; t += 256) {
-      const int r = t / dp, k = t - r * dp;
-      Bs[r][k] = (j0 + r < D) ? B[(int64_t)(j0 + r) * dp + k] : 0.f;
-    }
+    if (tid < PM_CP * 4) mus[tid] = (4 * p0 + tid < D) ? mu[4 * p0 + tid] : 0.f;
     __syncthreads();
-    for (int r = 0; r < PJ_K; ++r) {
-      float xv[4];
+    const int pend = min(PM_CP, npx - p0);
+    int dy = p0 / g.w, dx = p0 - dy * g.w;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) xv[a] = Xs[tq + 16 * a][r];
+    for (int pp = 0; pp < PM_CP; ++pp) {
+      if (pp < pend) {  // uniform
+        float xv[PM_WT];
+        const float m = mus[pp * 4 + kq];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        if (b < nk) {
-          const int k = tk + 16 * b;
-          const float bv = (k < dp) ? Bs[r][k] : 0.f;
+        for (int wt = 0; wt < PM_WT; ++wt) {
+          int xx = ucol[wt] + dx;
+          if (g.wrap && xx >= g.W) xx -= g.W;
+          xv[wt] = ok[wt] ? img[((int64_t)(vrow[wt] + dy) * g.W + xx) * 4 + kq] - m : 0.f;
+        }
 #pragma unroll
-          for (int a = 0; a < 4; ++a) acc[a][b] = fmaf(xv[a], bv, acc[a][b]);
+        for (int kt = 0; kt < NKT; ++kt) {
+          const float a = Bs[pp * 4 + kq][kt * 16 + col];
+#pragma unroll
+          for (int wt = 0; wt < PM_WT; ++wt)
+            acc[wt][kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xv[wt], acc[wt][kt], 0, 0, 0);
+        }
+        if (++dx == g.w) {
+          dx = 0;
+          ++dy;
         }
       }
     }
-    __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t win = w0 + tq + 16 * a;
-    if (win >= n) continue;
+  for (int wt = 0; wt < PM_WT; ++wt) {
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int k = tk + 16 * b;
-      if (b < nk && k < dp) P[win * dp + k] = acc[a][b];
+    for (int kt = 0; kt < NKT; ++kt) {
+      const int k = kt * 16 + 4 * kq;  // dp is a multiple of 8: a group of 4 is all in or all out
+      if (ok[wt] && k < dp)
+        *reinterpret_cast<float4*>(P + win[wt] * dp + k) =
+            make_float4(acc[wt][kt][0], acc[wt][kt][1], acc[wt][kt][2], acc[wt][kt][3]);
     }
   }
 }
@@ -271,14 +294,24 @@ __global__ __launch_bounds__(256) void k_project(WinGeom g, int64_t n, int D, co
 void launch_project_image(Ctx* c, const float* img, int H, int W, int w, int s, bool wrap, const float* mu,
                           const float* B, int dp, float* P) {
   ProfScope ps(c, wrap ? "project_queries" : "project_exemplar");
-  PTS_REQUIRE(dp >= 1 && dp <= PJ_MAXDP, PTS_ERR_UNSUPPORTED, "projection: d must be <= 128");
+  PTS_REQUIRE(dp >= 8 && dp <= 128 && dp % 8 == 0, PTS_ERR_UNSUPPORTED, "projection: padded width must be 8..128, /8");
   const WinGeom g = geom(img, H, W, w, s, wrap);
   const int64_t rows = (H - w) / s + 1;
   const int64_t n = rows * g.cols;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)ceil_div(n, PJ_T)), dim3(256), 0, c->stream, g, n, 4 * w * w, mu, B,
-                     dp, P);
-  check_launch("k_project");
+  const dim3 grid((unsigned)ceil_div(n, PM_WPB));
+  const int D = 4 * w * w;
+  switch ((dp + 15) / 16) {
+    case 1: hipLaunchKernelGGL(k_project_mfma<1>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+    case 2: hipLaunchKernelGGL(k_project_mfma<2>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+    case 3: hipLaunchKernelGGL(k_project_mfma<3>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+    case 4: hipLaunchKernelGGL(k_project_mfma<4>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+    case 5: hipLaunchKernelGGL(k_project_mfma<5>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+    case 6: hipLaunchKernelGGL(k_project_mfma<6>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+    case 7: hipLaunchKernelGGL(k_project_mfma<7>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+    default: hipLaunchKernelGGL(k_project_mfma<8>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+  }
+  check_launch("k_project_mfma");
 }
 
 // ---------------------------------------------------------------------------

@@ -35,8 +35,12 @@ void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i,
 void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb, const float* zbn, int dk,
                            const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* pair_d,
                            int32_t* pair_i);
-// full-D re-rank of candidate exemplar ids cand [nq][8] (first k used)
-void launch_rerank_full(Ctx* c, const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
-                        const int32_t* cand, int k, int64_t nq, int32_t* nn);
+// merge S partial lists per query as above and re-rank the best k by the
+// full-D FP32 distance gathered from the images x [H][W][4] and ex
+// [Hz][Wz][4]; nn = exemplar id, dist (optional) = its full-D distance
+void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
+                               int64_t ss, const int32_t* valid, int k, const int32_t* perm, int64_t npos,
+                               const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
+                               int32_t* nn, float* dist);
 
 }  // namespace pts
