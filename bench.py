@@ -22,7 +22,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"bf16": 2500.0, "fp32_vector": 157.3, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s (MI355X)
+# MI355X: dense bf16 MFMA, FP32 matrix (MFMA), FP32 vector (TFLOP/s); HBM (GB/s)
+PEAK = {"bf16": 2500.0, "fp32_matrix": 157.3, "fp32_vector": 157.3, "hbm": 8000.0}
 
 
 def parse():
@@ -39,6 +40,10 @@ def parse():
     ap.add_argument("--residual", type=int, default=1)
     ap.add_argument("--rerank-full", type=int, default=1)
     ap.add_argument("--only", default="", help="run one form only (tree or learned_bf16)")
+    ap.add_argument("--suite", default="", help="learned_c4: the learned form over the 16 seeded 256^2 exemplars")
+    ap.add_argument("--suite-seeds", type=int, default=16)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB tensor 3 times (the HBM-counter scale for rocprofv3 --pmc) and exit")
     return ap.parse_args()
 
 
@@ -53,8 +58,20 @@ def main():
         sys.exit(2)
     import torch
 
+    if a.calibrate_copy:
+        n = a.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "launches": 3}))
+        return
+
     from paper_2006_11851_amd import pts, synth, training
 
+    if a.suite == "learned_c4":
+        return learned_suite(a)
     wl = synth.workload(a.workload)
     ex = wl.exemplar()
     w, s = wl.w[-1], wl.stride[-1]
@@ -167,6 +184,36 @@ def main():
     print(json.dumps(out))
 
 
+def learned_suite(a):
+    """The learned form (FP32 scan of the proposed leaves) over seeded
+    exemplars at the 256^2 -> 512^2 workload's finest level; one JSON line."""
+    from paper_2006_11851_amd import learned_suite as ls
+    from paper_2006_11851_amd import pts, synth
+
+    ctx = pts.Context(0)
+    wl = synth.workload("ex256_out512_learned")
+    seeds = list(wl.extra["exemplar_seeds"])[: a.suite_seeds]
+    t0 = time.time()
+    rows = ls.run(ctx, seeds, log=log)
+    lg = np.array([r["learned"]["max_gap"] for r in rows])
+    ll = np.array([r["learned"]["last_gap"] for r in rows])
+    bg = np.array([r["learned_bf16"]["max_gap"] for r in rows])
+    bl = np.array([r["learned_bf16"]["last_gap"] for r in rows])
+    tg = np.array([r["tree"]["max_gap"] for r in rows])
+    print(json.dumps({
+        "suite": "learned_c4", "exemplars": len(rows), "pairs_total": int(sum(r["pairs"] for r in rows)),
+        "config": "exemplar 256^2, output 512^2 finest level, w=8, stride 2, PCA 64, tree b32 L2 (1024 leaves), "
+                  "MLP 64-256-256-1024, top-4 leaves scanned in FP32, tree leaf added below margin 0.2",
+        "learned_max_gap_mean": float(lg.mean()), "learned_max_gap_max": float(lg.max()),
+        "learned_last_gap_mean": float(ll.mean()), "learned_last_gap_max": float(ll.max()),
+        "learned_bf16_full_rerank_max_gap_mean": float(bg.mean()), "learned_bf16_full_rerank_max_gap_max": float(bg.max()),
+        "learned_bf16_full_rerank_last_gap_mean": float(bl.mean()),
+        "tree_max_gap_mean": float(tg.mean()),
+        "fallback_rate_mean": float(np.mean([r["learned"]["fallback_rate"] for r in rows])),
+        "top4_train_recall_mean": float(np.mean([r["top4_train_recall"] for r in rows])),
+        "seconds": time.time() - t0, "per_exemplar": rows}))
+
+
 def roofline(ctx, head, info, nq, a, forms):
     """Dominant kernel of the reported form against its bound."""
     kern = head["kernels_ms_per_step"]
@@ -175,15 +222,19 @@ def roofline(ctx, head, info, nq, a, forms):
     per_launch_ms = kern[dom] * a.steps / max(1, launches[dom])
     d, h, L = info.d, 256, info.n_leaves
     dk = -(-d // 32) * 32
+    K1 = -(-d // 32) * 32
     if dom == "mlp_out_topk_mfma":
         flops = 2.0 * h * (-(-L // 32) * 32) * nq
         bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
     elif dom == "mlp_hidden_mfma":
-        flops = 2.0 * h * h * nq
+        flops = 2.0 * (K1 * h + h * h) * nq
         bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
     elif dom == "leaf_scan_bf16":
         flops = 2.0 * dk * scanned_pairs(ctx, head, info, nq)
         bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
+    elif dom == "project_queries":
+        flops = 2.0 * info.D * d * nq
+        bound, peak, unit = "mfma", PEAK["fp32_matrix"], "TFLOP/s"
     elif dom == "leaf_scan_f32":
         flops = 3.0 * d * nq * info.leaf_mean
         bound, peak, unit = "alu", PEAK["fp32_vector"], "TFLOP/s"

@@ -127,7 +127,7 @@ typedef struct pts_index_info {
  * eigensolve, basis B = the d leading eigenvectors (largest-|entry| made
  * positive), projection z' = B^T (z - mu), and the k-means tree over z'
  * (nodes split while depth < `depth` and the node holds >= branching
- * members - the paper's "fewer than k" stop rule).  Synchronous. */
+ * members - the paper's stop rule for small clusters).  Synchronous. */
 int pts_build_index(pts_ctx* ctx, const pts_index_params* p, pts_index_info* info_host);
 
 /* Host form of an index, for export/import (parity tests share a basis and
@@ -281,7 +281,9 @@ int pts_upsample2(pts_ctx* ctx, const float* x_rgbs, int H, int W, float guidanc
 
 /* ---- learned leaf proposal ----------------------------------------------- */
 
-/* MLP n_in -> hidden -> hidden -> n_out, GELU (exact erf), input scaled per
+/* MLP n_in -> hidden -> hidden -> n_out, GELU (exact erf; the matrix-core
+ * inference of pts_mlp_propose and the learned modes evaluates it within 3e-6
+ * of that, below the bf16 rounding of the activations), input scaled per
  * feature by a fixed vector (default 1 / sqrt(eigenvalue) of the index).
  * Parameters packed W1 [h][n_in], b1 [h], W2 [h][h], b2 [h], W3 [n_out][h],
  * b3 [n_out], float32.  n_out must equal the index's leaf count to be used

@@ -26,6 +26,9 @@ HIP_FLAGS = [
 ]
 
 
+COMPILE_TIMEOUT_S = 600
+
+
 def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
@@ -33,7 +36,12 @@ def sources():
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
     cmd = ["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    try:
+        # a source normally compiles in well under a minute; a compiler that
+        # runs away ends the build with an error instead of hanging it
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=COMPILE_TIMEOUT_S)
+    except subprocess.TimeoutExpired:
+        raise RuntimeError(f"hipcc did not finish {src} within {COMPILE_TIMEOUT_S} s")
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
     warn = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())

@@ -6,15 +6,15 @@
 
 namespace pts {
 
-// nn[q] for projected queries qp [nq][ix.dp].  When the form re-ranks in full
+// nn[q] for projected queries qp [nq][ix.dp] (qb: their bf16(-2 q') [nq][ix.dk]).  When the form re-ranks in full
 // dimension it also writes the winner distance to dist (if non-null) and
 // returns true; otherwise the caller computes it.
 bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
-                       const float* qp, int64_t nq, int32_t* nn, float* dist);
+                       const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist);
 // returns the number of queries that fell back to the tree; *dist_done as
 // the return value above
 int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
-                       const float* qp, int64_t nq, int32_t* nn, float* dist, bool* dist_done, bool bf16_scan,
-                       bool count_fallbacks);
+                       const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist, bool* dist_done,
+                       bool bf16_scan, bool count_fallbacks);
 
 }  // namespace pts

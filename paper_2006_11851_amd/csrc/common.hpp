@@ -103,6 +103,7 @@ struct Mlp {
   int64_t adam_t = 0;
   uint64_t version = 0;               // bumped on every weight change
   DevMem w1b, w2b, w3b;               // bf16 copies for inference
+  DevMem b3p;                         // output bias padded to 32 rows (-FLT_MAX)
   uint64_t bf_version = ~0ull;
 };
 

@@ -32,8 +32,9 @@ BucketBufs bucket_buffers(Ctx* c, int64_t n, int n_leaves, int chunk, int* max_t
   return b;
 }
 
-void project_on(Ctx* c, const Index& ix, const float* x, int H, int W, int stride, float* qp) {
-  launch_project_image(c, x, H, W, ix.w, stride, true, ix.mu_f.as<float>(), ix.basis_f.as<float>(), ix.dp, qp);
+void project_on(Ctx* c, const Index& ix, const float* x, int H, int W, int stride, float* qp, uint16_t* qb = nullptr) {
+  launch_project_image(c, x, H, W, ix.w, stride, true, ix.mu_f.as<float>(), ix.basis_f.as<float>(), ix.dp, qp, qb,
+                       ix.dk);
 }
 
 EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, const pts_estep_params& p,
@@ -78,8 +79,9 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       launch_descend(c, qp, nq, ix->dp, ix->cent.as<float>(), ix->first_child.as<int32_t>(),
                      ix->n_children.as<int32_t>(), ix->leaf_of_node.as<int32_t>(), leaf);
       int max_tiles = 0;
-      BucketBufs b = bucket_buffers(c, nq, ix->tree.n_leaves(), 64, &max_tiles);
-      launch_bucket(c, leaf, nq, ix->tree.n_leaves(), 64, b);
+      const int chunk = leaf_scan_f32_chunk(ix->dp);
+      BucketBufs b = bucket_buffers(c, nq, ix->tree.n_leaves(), chunk, &max_tiles);
+      launch_bucket(c, leaf, nq, ix->tree.n_leaves(), chunk, b);
       launch_leaf_scan_f32(c, qp, ix->dp, ix->zproj.as<float>(), ix->perm.as<int32_t>(), ix->leaf_off.as<int32_t>(),
                            b, max_tiles, 1, p.residual ? ix->zres.as<float>() : nullptr, nn, nullptr);
       break;
@@ -88,8 +90,9 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       require_index(c, ix, w);
       PTS_REQUIRE(ix->has_bf16, PTS_ERR_STATE, "BRUTE_BF16 needs an index built with make_bf16");
       float* qp = c->buf<float>("qproj", (size_t)nq * ix->dp);
-      project_on(c, *ix, x, H, W, p.stride, qp);
-      dist_done = search_brute_bf16(c, ex, *ix, x, H, W, p, qp, nq, nn, dist);
+      uint16_t* qb = c->buf<uint16_t>("qbf16", (size_t)nq * ix->dk);
+      project_on(c, *ix, x, H, W, p.stride, qp, qb);
+      dist_done = search_brute_bf16(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist);
       break;
     }
     case PTS_MODE_LEARNED:
@@ -99,9 +102,11 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       PTS_REQUIRE(c->mlp.n_in == ix->d && c->mlp.n_out == ix->tree.n_leaves(), PTS_ERR_STATE,
                   "MLP shape does not match the index (n_in = d, n_out = leaves)");
       float* qp = c->buf<float>("qproj", (size_t)nq * ix->dp);
-      project_on(c, *ix, x, H, W, p.stride, qp);
-      st.fallbacks = search_learned(c, ex, *ix, x, H, W, p, qp, nq, nn, dist, &dist_done,
-                                    p.mode == PTS_MODE_LEARNED_BF16, timing);
+      const bool bf = p.mode == PTS_MODE_LEARNED_BF16;
+      PTS_REQUIRE(!bf || ix->has_bf16, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
+      uint16_t* qb = bf ? c->buf<uint16_t>("qbf16", (size_t)nq * ix->dk) : nullptr;
+      project_on(c, *ix, x, H, W, p.stride, qp, qb);
+      st.fallbacks = search_learned(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist, &dist_done, bf, timing);
       break;
     }
     default:

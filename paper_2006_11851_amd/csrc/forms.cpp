@@ -7,11 +7,9 @@
 namespace pts {
 
 bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
-                       const float* qp, int64_t nq, int32_t* nn, float* dist) {
+                       const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist) {
   const int k = p.topk <= 0 ? 8 : p.topk;
   PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
-  uint16_t* qb = c->buf<uint16_t>("qbf16", (size_t)nq * ix.dk);
-  launch_queries_bf16(c, qp, nq, ix.dp, ix.dk, qb);
   const int S = brute_splits(nq);
   float* pd = c->buf<float>("bb_pd", (size_t)S * nq * 8);
   int32_t* pi = c->buf<int32_t>("bb_pi", (size_t)S * nq * 8);
@@ -29,8 +27,8 @@ bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H
 }
 
 int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
-                       const float* qp, int64_t nq, int32_t* nn, float* dist, bool* dist_done, bool bf16_scan,
-                       bool count_fallbacks) {
+                       const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist, bool* dist_done,
+                       bool bf16_scan, bool count_fallbacks) {
   *dist_done = false;
   const int P = p.n_proposals <= 0 ? 4 : p.n_proposals;
   PTS_REQUIRE(P >= 1 && P <= 8 && P <= ix.tree.n_leaves(), PTS_ERR_ARG, "n_proposals must be 1..8 (and <= leaves)");
@@ -51,7 +49,7 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   int32_t* fb = c->buf<int32_t>("ln_fallbacks", 1);
   launch_zero_i32(c, fb, 1);
   launch_learned_pairs(c, prop, margin, dleaf, nq, P, p.margin, L, pair_leaf, fb);
-  const int chunk = bf16_scan ? 512 : 64;
+  const int chunk = bf16_scan ? 512 : leaf_scan_f32_chunk(ix.dp);
   int max_tiles = 0;
   BucketBufs b = bucket_buffers(c, nq * P1, L, chunk, &max_tiles);
   launch_bucket(c, pair_leaf, nq * P1, L, chunk, b);
@@ -62,11 +60,9 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
                          max_tiles, P1, p.residual ? ix.zres.as<float>() : nullptr, pid, pdd);
     launch_merge_pairs_f32(c, pair_leaf, pid, pdd, nq, P1, nn);
   } else {
-    PTS_REQUIRE(ix.has_bf16, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
+    PTS_REQUIRE(ix.has_bf16 && qb, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
     const int k = p.topk <= 0 ? 8 : p.topk;
     PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
-    uint16_t* qb = c->buf<uint16_t>("qbf16", (size_t)nq * ix.dk);
-    launch_queries_bf16(c, qp, nq, ix.dp, ix.dk, qb);
     float* pdd = c->buf<float>("ln_pair_cd", (size_t)nq * P1 * 8);
     int32_t* pii = c->buf<int32_t>("ln_pair_ci", (size_t)nq * P1 * 8);
     const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();

@@ -30,30 +30,6 @@ namespace pts {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t b = __float_as_uint(f);
-  b += 0x7FFFu + ((b >> 16) & 1u);
-  return (uint16_t)(b >> 16);
-}
-
-// Qb[q][k] = bf16(-2 * Qp[q][k]) for k < dp, 0 up to dk
-__global__ __launch_bounds__(256) void k_queries_bf16(const float* __restrict__ Qp, int64_t nq, int dp, int dk,
-                                                      uint16_t* __restrict__ Qb) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nq * dk) return;
-  const int64_t q = t / dk;
-  const int k = (int)(t - q * dk);
-  Qb[t] = (k < dp) ? bf16_rne(-2.0f * Qp[q * dp + k]) : (uint16_t)0;
-}
-
-void launch_queries_bf16(Ctx* c, const float* Qp, int64_t nq, int dp, int dk, uint16_t* Qb) {
-  ProfScope ps(c, "queries_bf16");
-  if (nq == 0) return;
-  hipLaunchKernelGGL(k_queries_bf16, dim3((unsigned)ceil_div(nq * dk, 256)), dim3(256), 0, c->stream, Qp, nq, dp, dk,
-                     Qb);
-  check_launch("k_queries_bf16");
-}
-
 // ---------------------------------------------------------------------------
 // sorted top-K (ascending) in registers
 
@@ -89,6 +65,11 @@ constexpr int BB_QPB = BB_WAVES * 64;  // queries per block
 constexpr int BB_STAGE = 128;          // exemplar rows per LDS stage
 constexpr int BB_TOPK = 8;
 
+// Workgroup barrier for the LDS stage buffers: this wave's LDS reads and
+// writes complete, then s_barrier.  Unlike __syncthreads() it does not wait
+// for the wave's global loads, so the next stages stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int KS>
 struct BruteSmem {
   uint4 frag[2][BB_STAGE / 32][KS][64];  // [buffer][tile][k-step][lane] 16 B each
@@ -103,6 +84,9 @@ struct StageRegs {
   float zn;
 };
 
+// The loads carry no lane-dependent condition (rows past the range read the
+// last row; stage_store replaces them by zero rows with norm FLT_MAX), so
+// the compiler waits for them only right before the store.
 template <int KS>
 __device__ __forceinline__ void stage_load(StageRegs<KS>& R, const uint16_t* __restrict__ Zb,
                                            const float* __restrict__ zbn, int64_t r0, int64_t row_end, int tid) {
@@ -112,22 +96,18 @@ __device__ __forceinline__ void stage_load(StageRegs<KS>& R, const uint16_t* __r
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int c = tid + u * BB_QPB;
-    uint4 val = make_uint4(0, 0, 0, 0);
-    if (c < NCH) {
+    if (c < NCH) {  // uniform per wave
       const int row = c / CH, ch = c - row * CH;
-      const int64_t gr = r0 + row;
-      if (gr < row_end) val = reinterpret_cast<const uint4*>(Zb + gr * (KS * 16))[ch];
+      const int64_t gr = min(r0 + row, row_end - 1);
+      R.v[u] = reinterpret_cast<const uint4*>(Zb + gr * (KS * 16))[ch];
     }
-    R.v[u] = val;
   }
-  if (tid < BB_STAGE) {
-    const int64_t gr = r0 + tid;
-    R.zn = (gr < row_end) ? zbn[gr] : FLT_MAX;
-  }
+  R.zn = zbn[min(r0 + (tid & (BB_STAGE - 1)), row_end - 1)];
 }
 
 template <int KS>
-__device__ __forceinline__ void stage_store(const StageRegs<KS>& R, BruteSmem<KS>& S, int buf, int tid) {
+__device__ __forceinline__ void stage_store(const StageRegs<KS>& R, BruteSmem<KS>& S, int buf, int tid, int64_t r0,
+                                            int64_t row_end) {
   constexpr int CH = KS * 2;
   constexpr int NCH = BB_STAGE * CH;
   constexpr int PER = (NCH + BB_QPB - 1) / BB_QPB;
@@ -138,10 +118,10 @@ __device__ __forceinline__ void stage_store(const StageRegs<KS>& R, BruteSmem<KS
       const int row = c / CH, ch = c - row * CH;
       const int tile = row >> 5, i = row & 31;
       const int kk = ch >> 1, half = ch & 1;
-      S.frag[buf][tile][kk][half * 32 + i] = R.v[u];
+      S.frag[buf][tile][kk][half * 32 + i] = (r0 + row < row_end) ? R.v[u] : make_uint4(0, 0, 0, 0);
     }
   }
-  if (tid < BB_STAGE) S.zn[buf][tid] = R.zn;
+  if (tid < BB_STAGE) S.zn[buf][tid] = (r0 + tid < row_end) ? R.zn : FLT_MAX;
 }
 
 // One wave: 64 queries (two B tiles) against the staged 128 rows.
@@ -216,18 +196,27 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
   top[1].init();
   if (row_begin < row_end) {
     const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
-    StageRegs<KS> R;
-    stage_load<KS>(R, Zb, zbn, row_begin, row_end, tid);
-    stage_store<KS>(R, sm, 0, tid);
-    __syncthreads();
-    for (int st = 0; st < nstages; ++st) {
-      const int buf = st & 1;
-      const bool more = st + 1 < nstages;
-      if (more) stage_load<KS>(R, Zb, zbn, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end, tid);
-      stage_compute<KS>(sm, buf, B, top, row_begin + (int64_t)st * BB_STAGE, lane,
-                        (int)min((int64_t)BB_STAGE, row_end - row_begin - (int64_t)st * BB_STAGE));
-      if (more) stage_store<KS>(R, sm, buf ^ 1, tid);
-      __syncthreads();
+    // stages load two ahead (two register sets): stage st + 2 is issued at
+    // step st and stored at step st + 1
+    StageRegs<KS> R[2];
+    stage_load<KS>(R[0], Zb, zbn, row_begin, row_end, tid);
+    stage_load<KS>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
+    stage_store<KS>(R[0], sm, 0, tid, row_begin, row_end);
+    lds_barrier();
+    for (int s0 = 0; s0 < nstages; s0 += 2) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int st = s0 + u;
+        if (st >= nstages) break;
+        // unconditional (past the end: the last rows again, never stored), so
+        // the wait before the store covers only the older stage
+        stage_load<KS>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
+        stage_compute<KS>(sm, u, B, top, row_begin + (int64_t)st * BB_STAGE, lane,
+                          (int)min((int64_t)BB_STAGE, row_end - row_begin - (int64_t)st * BB_STAGE));
+        if (st + 1 < nstages)
+          stage_store<KS>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
+        lds_barrier();
+      }
     }
   }
   // merge the two lanes that share a query: the k smallest of two sorted lists
@@ -265,13 +254,15 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
 // class and tile.  The 16 classes of a query (two half-lanes) are ranked by
 // their minima and the best 4 contribute both rows of their tile (rows
 // i % 32 == b and b + 16): 8 candidates that always include the minimum.
-template <int KS>
+// FULL: all 128 rows of the stage are valid (no per-tile exit, so the whole
+// stage is one straight-line block the scheduler can interleave).
+template <int KS, bool FULL>
 __device__ __forceinline__ void stage_compute_cls(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
                                                   float (&cm)[2][8], int (&ct)[2][8], int pos0, int lane,
                                                   int nvalid) {
 #pragma unroll
   for (int t = 0; t < BB_STAGE / 32; ++t) {
-    if (t * 32 >= nvalid) break;
+    if (!FULL && t * 32 >= nvalid) break;
     bf16x8 A[KS];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
@@ -351,19 +342,29 @@ __global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restri
   const int row_begin = leaf_off[tile.x], row_end = leaf_off[tile.x + 1];
   if (row_begin < row_end) {
     const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
-    StageRegs<KS> R;
-    stage_load<KS>(R, Zb, zbn, row_begin, row_end, tid);
-    stage_store<KS>(R, sm, 0, tid);
-    __syncthreads();
-    for (int st = 0; st < nstages; ++st) {
-      const int buf = st & 1;
-      const bool more = st + 1 < nstages;
-      if (more) stage_load<KS>(R, Zb, zbn, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end, tid);
-      if (wave_active)
-        stage_compute_cls<KS>(sm, buf, B, cm, ct, row_begin + st * BB_STAGE, lane,
-                              min(BB_STAGE, row_end - row_begin - st * BB_STAGE));
-      if (more) stage_store<KS>(R, sm, buf ^ 1, tid);
-      __syncthreads();
+    // stages load two ahead, as in the brute-force kernel
+    StageRegs<KS> R[2];
+    stage_load<KS>(R[0], Zb, zbn, row_begin, row_end, tid);
+    stage_load<KS>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
+    stage_store<KS>(R[0], sm, 0, tid, row_begin, row_end);
+    lds_barrier();
+    for (int s0 = 0; s0 < nstages; s0 += 2) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int st = s0 + u;
+        if (st >= nstages) break;
+        // unconditional (past the end: the last rows again, never stored), so
+        // the wait before the store covers only the older stage
+        stage_load<KS>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
+        if (wave_active) {
+          const int nvalid = min(BB_STAGE, row_end - row_begin - st * BB_STAGE);
+          if (nvalid == BB_STAGE) stage_compute_cls<KS, true>(sm, u, B, cm, ct, row_begin + st * BB_STAGE, lane, nvalid);
+          else stage_compute_cls<KS, false>(sm, u, B, cm, ct, row_begin + st * BB_STAGE, lane, nvalid);
+        }
+        if (st + 1 < nstages)
+          stage_store<KS>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
+        lds_barrier();
+      }
     }
   }
   // rows of class c in half h of a tile: i = 8 (c / 4) + 4 h + (c % 4), and i + 16

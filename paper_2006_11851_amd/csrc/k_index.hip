@@ -217,7 +217,8 @@ constexpr int PM_CP = 16;             // pixels per basis chunk
 
 template <int NKT>
 __global__ __launch_bounds__(256) void k_project_mfma(WinGeom g, int64_t n, int D, const float* __restrict__ mu,
-                                                      const float* __restrict__ B, int dp, float* __restrict__ P) {
+                                                      const float* __restrict__ B, int dp, float* __restrict__ P,
+                                                      uint16_t* __restrict__ Qb, int dk) {
   constexpr int DPAD = 16 * NKT;
   constexpr int LS = DPAD + ((DPAD % 32 == 0) ? 16 : 0);  // row stride: the two half-waves hit disjoint banks
   __shared__ float Bs[PM_CP * 4][LS];
@@ -288,13 +289,33 @@ __global__ __launch_bounds__(256) void k_project_mfma(WinGeom g, int64_t n, int 
         *reinterpret_cast<float4*>(P + win[wt] * dp + k) =
             make_float4(acc[wt][kt][0], acc[wt][kt][1], acc[wt][kt][2], acc[wt][kt][3]);
     }
+    // optional bf16(-2 q') [n][dk] for the matrix-core search (zero past dp)
+    if (Qb && ok[wt]) {
+#pragma unroll
+      for (int kt = 0; kt < 8; ++kt) {
+        const int k = kt * 16 + 4 * kq;
+        if (k < dk) {
+          float v[4] = {0.f, 0.f, 0.f, 0.f};
+          if (kt < NKT && k < dp) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = -2.0f * acc[wt][kt < NKT ? kt : 0][r];
+          }
+          const __bf16 b0 = (__bf16)v[0], b1 = (__bf16)v[1], b2 = (__bf16)v[2], b3 = (__bf16)v[3];
+          uint2 pk;
+          pk.x = (uint32_t)__builtin_bit_cast(uint16_t, b0) | ((uint32_t)__builtin_bit_cast(uint16_t, b1) << 16);
+          pk.y = (uint32_t)__builtin_bit_cast(uint16_t, b2) | ((uint32_t)__builtin_bit_cast(uint16_t, b3) << 16);
+          *reinterpret_cast<uint2*>(Qb + win[wt] * dk + k) = pk;
+        }
+      }
+    }
   }
 }
 
 void launch_project_image(Ctx* c, const float* img, int H, int W, int w, int s, bool wrap, const float* mu,
-                          const float* B, int dp, float* P) {
+                          const float* B, int dp, float* P, uint16_t* Qb, int dk) {
   ProfScope ps(c, wrap ? "project_queries" : "project_exemplar");
   PTS_REQUIRE(dp >= 8 && dp <= 128 && dp % 8 == 0, PTS_ERR_UNSUPPORTED, "projection: padded width must be 8..128, /8");
+  PTS_REQUIRE(!Qb || (dk >= dp && dk <= 128 && dk % 16 == 0), PTS_ERR_UNSUPPORTED, "projection: bad bf16 width");
   const WinGeom g = geom(img, H, W, w, s, wrap);
   const int64_t rows = (H - w) / s + 1;
   const int64_t n = rows * g.cols;
@@ -302,14 +323,14 @@ void launch_project_image(Ctx* c, const float* img, int H, int W, int w, int s, 
   const dim3 grid((unsigned)ceil_div(n, PM_WPB));
   const int D = 4 * w * w;
   switch ((dp + 15) / 16) {
-    case 1: hipLaunchKernelGGL(k_project_mfma<1>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
-    case 2: hipLaunchKernelGGL(k_project_mfma<2>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
-    case 3: hipLaunchKernelGGL(k_project_mfma<3>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
-    case 4: hipLaunchKernelGGL(k_project_mfma<4>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
-    case 5: hipLaunchKernelGGL(k_project_mfma<5>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
-    case 6: hipLaunchKernelGGL(k_project_mfma<6>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
-    case 7: hipLaunchKernelGGL(k_project_mfma<7>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
-    default: hipLaunchKernelGGL(k_project_mfma<8>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P); break;
+    case 1: hipLaunchKernelGGL(k_project_mfma<1>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+    case 2: hipLaunchKernelGGL(k_project_mfma<2>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+    case 3: hipLaunchKernelGGL(k_project_mfma<3>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+    case 4: hipLaunchKernelGGL(k_project_mfma<4>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+    case 5: hipLaunchKernelGGL(k_project_mfma<5>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+    case 6: hipLaunchKernelGGL(k_project_mfma<6>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+    case 7: hipLaunchKernelGGL(k_project_mfma<7>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+    default: hipLaunchKernelGGL(k_project_mfma<8>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
   }
   check_launch("k_project_mfma");
 }

@@ -20,6 +20,7 @@
 // running top-P (descending, ties to the lower leaf) and an online softmax
 // normaliser, merged with the lane sharing its query at the end.
 #include <cfloat>
+#include <type_traits>
 #include <climits>
 
 #include "kernels_mlp.hpp"
@@ -268,23 +269,22 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-__global__ __launch_bounds__(256) void k_to_bf16_pad(const float* __restrict__ src, int rows, int cols, int rows_p,
-                                                     int cols_p, uint16_t* __restrict__ dst) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)rows_p * cols_p) return;
-  const int r = (int)(t / cols_p), cc = (int)(t % cols_p);
-  dst[t] = (r < rows && cc < cols) ? bf16_bits(src[(int64_t)r * cols + cc]) : (uint16_t)0;
+__global__ __launch_bounds__(256) void k_pad_f32(const float* __restrict__ src, int n, int n_p, float fill,
+                                                 float* __restrict__ dst) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_p) dst[t] = t < n ? src[t] : fill;
 }
 
-// Xb[q][k] = bf16(Qp[q][k] * scale[k]) for k < n_in, zero up to K
-__global__ __launch_bounds__(256) void k_mlp_inputs(const float* __restrict__ Qp, int ld, int64_t nq,
-                                                    const float* __restrict__ scale, int n_in, int K,
-                                                    uint16_t* __restrict__ Xb) {
+// dst [rows_p][cols_p] = bf16(src [rows][cols]), zero padded; with perm, the
+// columns of each group of 16 are reordered to the matrix-core lane order
+// (dst column k holds src column swap_bits23(k))
+__global__ __launch_bounds__(256) void k_to_bf16_pad(const float* __restrict__ src, int rows, int cols, int rows_p,
+                                                     int cols_p, int perm, uint16_t* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nq * K) return;
-  const int64_t q = t / K;
-  const int k = (int)(t - q * K);
-  Xb[t] = (k < n_in) ? bf16_bits(Qp[q * ld + k] * scale[k]) : (uint16_t)0;
+  if (t >= (int64_t)rows_p * cols_p) return;
+  const int r = (int)(t / cols_p), k = (int)(t % cols_p);
+  const int cc = perm ? ((k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1)) : k;
+  dst[t] = (r < rows && cc < cols) ? bf16_bits(src[(int64_t)r * cols + cc]) : (uint16_t)0;
 }
 
 unsigned eblocks(int64_t n) { return (unsigned)ceil_div(n, 256); }
@@ -329,63 +329,211 @@ void launch_adam(Ctx* c, float* p, const float* g, float* m, float* v, int64_t n
   hipLaunchKernelGGL(k_adam, dim3(eblocks(n)), dim3(256), 0, c->stream, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
   check_launch("k_adam");
 }
-void launch_to_bf16_pad(Ctx* c, const float* src, int rows, int cols, int rows_p, int cols_p, uint16_t* dst) {
-  hipLaunchKernelGGL(k_to_bf16_pad, dim3(eblocks((int64_t)rows_p * cols_p)), dim3(256), 0, c->stream, src, rows, cols,
-                     rows_p, cols_p, dst);
-  check_launch("k_to_bf16_pad");
+void launch_pad_f32(Ctx* c, const float* src, int n, int n_p, float fill, float* dst) {
+  hipLaunchKernelGGL(k_pad_f32, dim3(eblocks(n_p)), dim3(256), 0, c->stream, src, n, n_p, fill, dst);
+  check_launch("k_pad_f32");
 }
-void launch_mlp_inputs(Ctx* c, const float* Qp, int ld, int64_t nq, const float* scale, int n_in, int K, uint16_t* Xb) {
-  ProfScope ps(c, "mlp_inputs");
-  if (nq == 0) return;
-  hipLaunchKernelGGL(k_mlp_inputs, dim3(eblocks(nq * K)), dim3(256), 0, c->stream, Qp, ld, nq, scale, n_in, K, Xb);
-  check_launch("k_mlp_inputs");
+
+void launch_to_bf16_pad(Ctx* c, const float* src, int rows, int cols, int rows_p, int cols_p, bool perm,
+                        uint16_t* dst) {
+  PTS_REQUIRE(!perm || cols_p % 16 == 0, PTS_ERR_ARG, "to_bf16_pad: permuted width must be a multiple of 16");
+  hipLaunchKernelGGL(k_to_bf16_pad, dim3(eblocks((int64_t)rows_p * cols_p)), dim3(256), 0, c->stream, src, rows, cols,
+                     rows_p, cols_p, perm ? 1 : 0, dst);
+  check_launch("k_to_bf16_pad");
 }
 
 // ---------------------------------------------------------------------------
-// matrix-core inference layers
+// matrix-core inference
+//
+// v_mfma_f32_32x32x16_bf16 with A = 32 weight rows (neurons), B = 32
+// queries: lane l supplies query l % 32 and the 8 k-values 16 kk + 8 (l / 32)
+// + 0..7 of k-chunk kk, and receives 16 outputs of its query: neurons
+// 32 T + 8 g + 4 (l / 32) + i of tile T (g, i = 0..3, register 4 g + i).
+// Registers 8 c .. 8 c + 7 of tile T are therefore exactly a B operand of
+// the next layer if that layer's k-chunk 2 T + c lists its neurons in the
+// order in which the lanes hold them: k = 16 kk + 8 h + j stands for neuron
+// 16 kk + 8 (j / 4) + 4 h + j % 4, i.e. bits 2 and 3 of k swapped.  The bf16
+// copies of W2 and W3 have their columns permuted that way, so the hidden
+// activations go from one layer to the next without leaving the registers,
+// and the second hidden layer is stored in that same order for the output
+// layer.
 
 constexpr int ML_WAVES = 8;
 constexpr int ML_THREADS = ML_WAVES * 64;
 constexpr int ML_QPB = ML_WAVES * 32;  // queries per block (one 32-query tile per wave)
+constexpr int ML_P = 8;                // most proposals per query
+constexpr float ML_LOG2E = 1.4426950408889634f;
+
+__device__ __forceinline__ int swap_bits23(int k) { return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1); }
+
+// Workgroup barrier for the LDS double buffers: this wave's LDS reads and
+// writes complete, then s_barrier.  Unlike __syncthreads() it does not wait
+// for the wave's global loads, so a weight-tile prefetch stays in flight
+// across the barrier.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int KS>
-struct MlpSmem {
-  uint4 frag[2][KS][64];  // one 32-row weight tile per buffer, fragment order
-  float bias[2][32];
+struct WTile {
+  static constexpr int CH = KS * 2, NCH = 32 * CH, PER = (NCH + ML_THREADS - 1) / ML_THREADS;
 };
 
+// Staging registers of one weight tile: at most two 16-byte chunks per
+// thread (32 rows x 16 KS bf16 over 512 threads, KS <= 16) and one bias.
+// Plain scalars, so they never become a memory object.
+struct TileRegs {
+  uint4 c0, c1;
+  float b;
+};
+
+// One 32-row weight tile (rows n0 .. n0+31 of W [.][16 KS] bf16, which the
+// caller pads to whole tiles) into registers.  The loads carry no condition
+// (threads past the tile's chunks re-read its last chunk and do not store
+// it), so the registers are not touched until the store: the compiler waits
+// for them only there and a prefetch stays in flight across the matrix
+// products.
 template <int KS>
-__device__ __forceinline__ void wtile_load(uint4 (&R)[(32 * KS * 2 + ML_THREADS - 1) / ML_THREADS], float& rb,
-                                           const uint16_t* __restrict__ Wb, const float* __restrict__ bias, int n0,
-                                           int N, int tid) {
-  constexpr int CH = KS * 2, NCH = 32 * CH, PER = (NCH + ML_THREADS - 1) / ML_THREADS;
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int cidx = tid + u * ML_THREADS;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (cidx < NCH) {
-      const int row = cidx / CH, ch = cidx - row * CH;
-      if (n0 + row < N) v = reinterpret_cast<const uint4*>(Wb + (int64_t)(n0 + row) * (KS * 16))[ch];
-    }
-    R[u] = v;
-  }
-  if (tid < 32) rb = (n0 + tid < N) ? bias[n0 + tid] : -FLT_MAX;
+__device__ __forceinline__ uint4 wt_chunk(const uint16_t* __restrict__ Wb, int n0, int cidx) {
+  cidx = min(cidx, WTile<KS>::NCH - 1);
+  const int row = cidx / WTile<KS>::CH, ch = cidx - row * WTile<KS>::CH;
+  return reinterpret_cast<const uint4*>(Wb + (int64_t)(n0 + row) * (KS * 16))[ch];
 }
 
 template <int KS>
-__device__ __forceinline__ void wtile_store(const uint4 (&R)[(32 * KS * 2 + ML_THREADS - 1) / ML_THREADS], float rb,
-                                            MlpSmem<KS>& S, int buf, int tid) {
-  constexpr int CH = KS * 2, NCH = 32 * CH, PER = (NCH + ML_THREADS - 1) / ML_THREADS;
+__device__ __forceinline__ TileRegs wt_load(const uint16_t* __restrict__ Wb, const float* __restrict__ bias, int n0,
+                                            int tid) {
+  static_assert(WTile<KS>::PER <= 2, "at most two chunks per thread");
+  TileRegs T;
+  T.c0 = wt_chunk<KS>(Wb, n0, tid);
+  T.c1 = WTile<KS>::PER > 1 ? wt_chunk<KS>(Wb, n0, tid + ML_THREADS) : T.c0;
+  T.b = bias[n0 + (tid & 31)];
+  return T;
+}
+
+// registers -> LDS in fragment order: frag[kk][h * 32 + row] = W[row][16 kk + 8 h .. + 7]
+template <int KS>
+__device__ __forceinline__ void wt_store(const TileRegs& T, uint4 (*frag)[64], float* bs, int tid) {
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
+  for (int u = 0; u < WTile<KS>::PER; ++u) {
     const int cidx = tid + u * ML_THREADS;
-    if (cidx < NCH) {
-      const int row = cidx / CH, ch = cidx - row * CH;
-      S.frag[buf][ch >> 1][(ch & 1) * 32 + row] = R[u];
+    if (cidx < WTile<KS>::NCH) {
+      const int row = cidx / WTile<KS>::CH, ch = cidx - row * WTile<KS>::CH;
+      frag[ch >> 1][(ch & 1) * 32 + row] = u ? T.c1 : T.c0;
     }
   }
-  if (tid < 32) S.bias[buf][tid] = rb;
+  if (tid < 32) bs[tid] = T.b;
 }
+
+// acc = bias (of the lane's 16 rows) + sum_kk A[kk] B[kk]
+template <int KS>
+__device__ __forceinline__ floatx16 tile_mfma(const uint4 (*frag)[64], const float* bs, const bf16x8 (&B)[KS],
+                                              int lane) {
+  floatx16 acc;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float4 b4 = *reinterpret_cast<const float4*>(&bs[8 * g + 4 * (lane >> 5)]);
+    acc[4 * g + 0] = b4.x;
+    acc[4 * g + 1] = b4.y;
+    acc[4 * g + 2] = b4.z;
+    acc[4 * g + 3] = b4.w;
+  }
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const uint4 u = frag[kk][lane];
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(&u), B[kk], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ bf16x8 gelu_bf16x8(const floatx16& acc, int c) {
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = (__bf16)gelu_poly_f(acc[8 * c + j]);
+  return o;
+}
+
+// Both hidden layers: H2 = GELU(GELU(bf16(Qp * scale) W1^T + b1) W2p^T + b2),
+// stored bf16 [nq][16 KSH] in the lanes' order (see above).  W1b [16 KSH][16
+// KS1] (natural order, zero-padded inputs), W2b [16 KSH][16 KSH] (columns
+// permuted).
+template <int KS1, int KSH>
+__global__ __launch_bounds__(ML_THREADS) void k_mlp_hidden2(const float* __restrict__ Qp, int ld, int64_t nq,
+                                                            const float* __restrict__ scale, int n_in,
+                                                            const uint16_t* __restrict__ W1b,
+                                                            const float* __restrict__ b1,
+                                                            const uint16_t* __restrict__ W2b,
+                                                            const float* __restrict__ b2,
+                                                            uint16_t* __restrict__ H2) {
+  constexpr int KSM = KS1 > KSH ? KS1 : KSH;
+  constexpr int PERM = WTile<KSM>::PER;
+  constexpr int NT = KSH / 2;  // tiles of 32 hidden units per layer
+  __shared__ uint4 frag[2][KSM][64];
+  __shared__ float bs[2][32];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+  const int64_t q = (int64_t)blockIdx.x * ML_QPB + wave * 32 + (lane & 31);
+  const bool qok = q < nq;
+  bf16x8 X[KS1];
+#pragma unroll
+  for (int kk = 0; kk < KS1; ++kk) {
+    const int k0 = 16 * kk + 8 * h;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + j;
+      X[kk][j] = (__bf16)((qok && k < n_in) ? Qp[q * ld + k] * scale[k] : 0.f);
+    }
+  }
+  bf16x8 H1[KSH];
+  TileRegs T0, T1;
+  // Software pipelined over the 2 NT tiles (NT of each layer), loads two
+  // tiles ahead: step t issues the loads of tile t + 2, the matrix products
+  // of tile t and the epilogue (bias is in the accumulator; GELU, bf16) of
+  // tile t - 1, and stores tile t + 1 into LDS.  The first layer-2 tile
+  // needs every layer-1 activation, so there the epilogue goes first.
+  auto epilogue = [&](const floatx16& acc, int t) {
+    if (t < NT) {
+      H1[2 * t] = gelu_bf16x8(acc, 0);
+      H1[2 * t + 1] = gelu_bf16x8(acc, 1);
+    } else if (qok) {
+      uint16_t* dst = H2 + q * (16 * KSH) + 32 * (t - NT) + 8 * h;
+      const bf16x8 o0 = gelu_bf16x8(acc, 0), o1 = gelu_bf16x8(acc, 1);
+      *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(&o0);
+      *reinterpret_cast<uint4*>(dst + 16) = *reinterpret_cast<const uint4*>(&o1);
+    }
+  };
+  // tile k of the stream: layer-1 tile k (k < NT) or layer-2 tile k - NT
+  // tile k of the stream goes through register set k % 2 (t is compile-time below)
+  auto fetch = [&](int k) {
+    return k < NT ? wt_load<KS1>(W1b, b1, k * 32, tid) : wt_load<KSH>(W2b, b2, (k - NT) * 32, tid);
+  };
+  auto load = [&](int k) {
+    if (k & 1) T1 = fetch(k);
+    else T0 = fetch(k);
+  };
+  auto store = [&](int k) {
+    const TileRegs T = (k & 1) ? T1 : T0;
+    if (k < NT) wt_store<KS1>(T, frag[k & 1], bs[k & 1], tid);
+    else wt_store<KSH>(T, frag[k & 1], bs[k & 1], tid);
+  };
+  load(0);
+  load(1);
+  store(0);
+  lds_barrier();
+  floatx16 acc_prev = {};
+#pragma unroll
+  for (int t = 0; t <= 2 * NT; ++t) {
+    if (t + 2 < 2 * NT) load(t + 2);
+    if (t == NT) epilogue(acc_prev, t - 1);
+    floatx16 acc_cur = {};
+    if (t < NT) acc_cur = tile_mfma<KS1>(frag[t & 1], bs[t & 1], X, lane);
+    else if (t < 2 * NT) acc_cur = tile_mfma<KSH>(frag[t & 1], bs[t & 1], H1, lane);
+    if (t >= 1 && t != NT) epilogue(acc_prev, t - 1);
+    if (t + 1 < 2 * NT) store(t + 1);
+    lds_barrier();
+    acc_prev = acc_cur;
+  }
+}
+
+// descending by value, ties to the lower id
+__device__ __forceinline__ bool desc_lt(float a, int ia, float b, int ib) { return a > b || (a == b && ia < ib); }
 
 template <int P>
 struct TopP {
@@ -398,364 +546,254 @@ struct TopP {
       i[t] = INT_MAX;
     }
   }
-  __device__ __forceinline__ void insert(float x, int id) {  // descending; ties keep the earlier (lower) id
+  __device__ __forceinline__ void insert(float x, int id) {
+    bool b[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) b[t] = desc_lt(x, id, v[t], i[t]);
 #pragma unroll
     for (int t = P - 1; t > 0; --t) {
-      const bool s = x > v[t - 1];
-      const bool n = x > v[t];
-      v[t] = s ? v[t - 1] : (n ? x : v[t]);
-      i[t] = s ? i[t - 1] : (n ? id : i[t]);
+      v[t] = b[t - 1] ? v[t - 1] : (b[t] ? x : v[t]);
+      i[t] = b[t - 1] ? i[t - 1] : (b[t] ? id : i[t]);
     }
-    if (x > v[0]) {
-      v[0] = x;
-      i[0] = id;
-    }
+    v[0] = b[0] ? x : v[0];
+    i[0] = b[0] ? id : i[0];
   }
 };
 
-constexpr int ML_P = 8;
-constexpr int ML_QT = 1;  // 32-query tiles per wave
-
-// MODE 0: Y[q][n] = bf16(GELU(X W^T + b)); MODE 1: top-P leaves + margin.
-template <int KS, int MODE>
-__global__ __launch_bounds__(512) void k_mlp_layer(const uint16_t* __restrict__ X, int64_t nq,
-                                                   const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
-                                                   int N, uint16_t* __restrict__ Y, int kout,
-                                                   int32_t* __restrict__ leaves, float* __restrict__ margin) {
-  __shared__ MlpSmem<KS> sm;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t qbase = (int64_t)blockIdx.x * ML_QPB + wave * 32;
-  bf16x8 B[ML_QT][KS];
-#pragma unroll
-  for (int qt = 0; qt < ML_QT; ++qt) {
-    const int64_t q = qbase + qt * 32 + (lane & 31);
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      uint4 u = make_uint4(0, 0, 0, 0);
-      if (q < nq) u = reinterpret_cast<const uint4*>(X + q * (KS * 16))[2 * kk + (lane >> 5)];
-      B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
+// Software-pipelined stream of the ntiles 32-row tiles of W through the LDS
+// double buffer.  Step t issues the global loads of tile t + 2 (into one of
+// two register sets), the matrix products of tile t, the epilogue epi(acc,
+// t - 1) of the previous tile, and stores tile t + 1 (loaded one step
+// earlier) into the buffer tile t - 1 used; the barrier between steps does
+// not wait for the loads in flight, so every load has two steps to arrive.
+// Two steps per trip keep the register sets and accumulators static.
+template <int KS, class Epi>
+__device__ __forceinline__ void stream_tiles(uint4 (*frag)[KS][64], float (*bs)[32], const uint16_t* __restrict__ Wb,
+                                             const float* __restrict__ bias, int ntiles, const bf16x8 (&B)[KS],
+                                             int tid, int lane, Epi&& epi) {
+  TileRegs T0 = wt_load<KS>(Wb, bias, 0, tid), T1 = T0;
+  if (ntiles > 1) T1 = wt_load<KS>(Wb, bias, 32, tid);
+  lds_barrier();  // earlier readers of the buffers are done
+  wt_store<KS>(T0, frag[0], bs[0], tid);
+  lds_barrier();
+  floatx16 acc[2] = {{}, {}};
+  // one step on tile tt with register set / buffer / accumulator U (= tt % 2)
+  auto step = [&](auto U, int tt) {
+    constexpr int u = decltype(U)::value;
+    // issued unconditionally (past the end: the last tile again, never
+    // stored), so the compiler's count of loads in flight is the same on
+    // every path and the store below waits only for the older tile
+    const int tn = min(tt + 2, ntiles - 1) * 32;
+    if constexpr (u == 0) T0 = wt_load<KS>(Wb, bias, tn, tid);
+    else T1 = wt_load<KS>(Wb, bias, tn, tid);
+    if (tt < ntiles) acc[u] = tile_mfma<KS>(frag[u], bs[u], B, lane);
+    if (tt >= 1) epi(acc[u ^ 1], tt - 1);
+    if (tt + 1 < ntiles) {
+      if constexpr (u == 0) wt_store<KS>(T1, frag[1], bs[1], tid);
+      else wt_store<KS>(T0, frag[0], bs[0], tid);
     }
-  }
-  TopP<ML_P> top[ML_QT];
-  float smax[ML_QT], ssum[ML_QT];
-  if (MODE == 1) {
-#pragma unroll
-    for (int qt = 0; qt < ML_QT; ++qt) {
-      top[qt].init();
-      smax[qt] = -FLT_MAX;
-      ssum[qt] = 0.f;
-    }
-  }
-  const int ntiles = (N + 31) / 32;
-  uint4 R[(32 * KS * 2 + ML_THREADS - 1) / ML_THREADS];
-  float rb = 0.f;
-  wtile_load<KS>(R, rb, Wb, bias, 0, N, tid);
-  wtile_store<KS>(R, rb, sm, 0, tid);
-  __syncthreads();
-  for (int t = 0; t < ntiles; ++t) {
-    const int buf = t & 1;
-    const bool more = t + 1 < ntiles;
-    if (more) wtile_load<KS>(R, rb, Wb, bias, (t + 1) * 32, N, tid);
-    bf16x8 A[KS];
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const uint4 u = sm.frag[buf][kk][lane];
-      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
-    }
-    floatx16 cinit;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const float4 b4 = *reinterpret_cast<const float4*>(&sm.bias[buf][8 * g + 4 * (lane >> 5)]);
-      cinit[4 * g + 0] = b4.x;
-      cinit[4 * g + 1] = b4.y;
-      cinit[4 * g + 2] = b4.z;
-      cinit[4 * g + 3] = b4.w;
-    }
-    const int nbase = t * 32 + 4 * (lane >> 5);
-#pragma unroll
-    for (int qt = 0; qt < ML_QT; ++qt) {
-      floatx16 acc = cinit;
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc, 0, 0, 0);
-      const int64_t q = qbase + qt * 32 + (lane & 31);
-      if (MODE == 0) {
-        if (q < nq) {
-#pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            const int n = nbase + 8 * g;
-            if (n < N) {  // N is a multiple of 4: a group of 4 is all in or all out
-              uint2 pk;
-              pk.x = (uint32_t)bf16_bits(gelu_poly_f(acc[4 * g + 0])) |
-                     ((uint32_t)bf16_bits(gelu_poly_f(acc[4 * g + 1])) << 16);
-              pk.y = (uint32_t)bf16_bits(gelu_poly_f(acc[4 * g + 2])) |
-                     ((uint32_t)bf16_bits(gelu_poly_f(acc[4 * g + 3])) << 16);
-              *reinterpret_cast<uint2*>(Y + q * kout + n) = pk;
-            }
-          }
-        }
-      } else {
-        float mloc = acc[0];
-#pragma unroll
-        for (int r = 1; r < 16; ++r) mloc = fmaxf(mloc, acc[r]);
-        if (mloc > smax[qt]) {  // rescale the running sum to the new maximum
-          ssum[qt] *= expf(smax[qt] - mloc);
-          smax[qt] = mloc;
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int n = nbase + 8 * (r >> 2) + (r & 3);
-          if (n < N) ssum[qt] += expf(acc[r] - smax[qt]);
-        }
-        if (__any(mloc > top[qt].v[ML_P - 1])) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int n = nbase + 8 * (r >> 2) + (r & 3);
-            if (n < N && acc[r] > top[qt].v[ML_P - 1]) top[qt].insert(acc[r], n);
-          }
-        }
-      }
-    }
-    if (more) wtile_store<KS>(R, rb, sm, buf ^ 1, tid);
-    __syncthreads();
-  }
-  if (MODE == 1) {
-#pragma unroll
-    for (int qt = 0; qt < ML_QT; ++qt) {
-      // merge with the partner lane (same query, other 16 rows of each tile)
-      const float om = __shfl_xor(smax[qt], 32, 64);
-      const float os = __shfl_xor(ssum[qt], 32, 64);
-      const float m = fmaxf(smax[qt], om);
-      const float s = ssum[qt] * expf(smax[qt] - m) + os * expf(om - m);
-      float ov[ML_P];
-      int oi[ML_P];
-#pragma unroll
-      for (int t = 0; t < ML_P; ++t) {
-        ov[t] = __shfl_xor(top[qt].v[t], 32, 64);
-        oi[t] = __shfl_xor(top[qt].i[t], 32, 64);
-      }
-      const int64_t q = qbase + qt * 32 + (lane & 31);
-      if (lane < 32 && q < nq) {
-        // merge two descending lists; equal scores: lower leaf first
-        int a = 0, b = 0;
-        float best[2] = {-FLT_MAX, -FLT_MAX};
-#pragma unroll
-        for (int t = 0; t < ML_P; ++t) {
-          float va = -FLT_MAX, vb = -FLT_MAX;
-          int ia = INT_MAX, ib = INT_MAX;
-#pragma unroll
-          for (int u = 0; u < ML_P; ++u) {
-            if (u == a) {
-              va = top[qt].v[u];
-              ia = top[qt].i[u];
-            }
-            if (u == b) {
-              vb = ov[u];
-              ib = oi[u];
-            }
-          }
-          const bool take_a = (va > vb) || (va == vb && ia < ib);
-          const int id = take_a ? ia : ib;
-          const float vv = take_a ? va : vb;
-          if (take_a) ++a;
-          else ++b;
-          if (t < kout) leaves[q * kout + t] = (id == INT_MAX) ? -1 : id;
-          if (t < 2) best[t] = vv;
-        }
-        // p1 - p2 = (1 - exp(l2 - l1)) / sum_j exp(l_j - l1)
-        const float denom = s * expf(m - best[0]);
-        margin[q] = (best[1] == -FLT_MAX) ? 1.0f : (1.0f - expf(best[1] - best[0])) / denom;
-      }
-    }
+    lds_barrier();
+  };
+  for (int t = 0; t <= ntiles; t += 2) {
+    step(std::integral_constant<int, 0>(), t);
+    if (t + 1 <= ntiles) step(std::integral_constant<int, 1>(), t + 1);
   }
 }
 
-// Output layer, exact top-P in two passes over the weight tiles.  Pass 1
-// keeps, per value slot, the running maximum of the logits (one max per
-// logit, no ids).  After it the query's largest logit m is known, and the
-// P-th largest of its 32 slot maxima (two half-lanes x 16 slots) is at most
-// its P-th largest logit.  Pass 2 recomputes the logits on the matrix cores,
-// inserts only logits at or above that bound into the sorted top-P, and sums
-// exp(l - m) for the softmax normaliser, skipping tiles whose logits are all
-// below m - 30 (their terms are below 1e-13 of the largest).
+// Output layer, exact top-P leaves and the softmax margin p1 - p2, in two
+// passes over the weight tiles (the logits are never stored).
+//  Pass 1: per value slot (lane, register) the largest and second-largest
+//    logit (3 operations per logit).  Then per query: m = the largest logit
+//    and tau = the P-th largest of the 64 slot values, which are 64 distinct
+//    logits, so tau <= the P-th largest logit: every top-P logit is >= tau,
+//    and usually only those are.
+//  Pass 2: recompute the logits; append each logit >= tau (with its leaf) to
+//    a per-lane list in LDS (into the in-register top-P should the list be
+//    full), and accumulate sum exp(l - m).
+//  Finally each lane ranks its list, and the two lanes of each query merge
+//  their top-P lists.
 template <int KS, int PP>
-__global__ __launch_bounds__(512) void k_mlp_out_topk(const uint16_t* __restrict__ X, int64_t nq,
-                                                      const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
-                                                      int N, int kout, int32_t* __restrict__ leaves,
-                                                      float* __restrict__ margin) {
-  __shared__ MlpSmem<KS> sm;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t qbase = (int64_t)blockIdx.x * ML_QPB + wave * 32;
-  bf16x8 B[ML_QT][KS];
+__global__ __launch_bounds__(ML_THREADS) void k_mlp_out_topk(const uint16_t* __restrict__ X, int64_t nq,
+                                                             const uint16_t* __restrict__ Wb,
+                                                             const float* __restrict__ bias, int N, int kout,
+                                                             int32_t* __restrict__ leaves,
+                                                             float* __restrict__ margin) {
+  constexpr int PERM = WTile<KS>::PER;
+  constexpr int HC = 8;  // hit-list capacity per lane
+  __shared__ uint4 frag[2][KS][64];
+  __shared__ float bs[2][32];
+  __shared__ float hv[HC][ML_THREADS];
+  __shared__ int hid[HC][ML_THREADS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+  const int64_t q = (int64_t)blockIdx.x * ML_QPB + wave * 32 + (lane & 31);
+  bf16x8 B[KS];
 #pragma unroll
-  for (int qt = 0; qt < ML_QT; ++qt) {
-    const int64_t q = qbase + qt * 32 + (lane & 31);
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      uint4 u = make_uint4(0, 0, 0, 0);
-      if (q < nq) u = reinterpret_cast<const uint4*>(X + q * (KS * 16))[2 * kk + (lane >> 5)];
-      B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
-    }
-  }
-  float slot[ML_QT][16], tau[ML_QT], mx[ML_QT], ssum[ML_QT];
-  TopP<PP> top[ML_QT];
-#pragma unroll
-  for (int qt = 0; qt < ML_QT; ++qt) {
-    ssum[qt] = 0.f;
-    top[qt].init();
-#pragma unroll
-    for (int r = 0; r < 16; ++r) slot[qt][r] = -FLT_MAX;
+  for (int kk = 0; kk < KS; ++kk) {
+    uint4 u = make_uint4(0, 0, 0, 0);
+    if (q < nq) u = reinterpret_cast<const uint4*>(X + q * (KS * 16))[2 * kk + h];
+    B[kk] = *reinterpret_cast<const bf16x8*>(&u);
   }
   const int ntiles = (N + 31) / 32;
-  uint4 R[(32 * KS * 2 + ML_THREADS - 1) / ML_THREADS];
-  float rb = 0.f;
-  for (int pass = 0; pass < 2; ++pass) {
-    wtile_load<KS>(R, rb, Wb, bias, 0, N, tid);
-    __syncthreads();  // the previous pass has finished reading the buffers
-    wtile_store<KS>(R, rb, sm, 0, tid);
-    __syncthreads();
-    for (int t = 0; t < ntiles; ++t) {
-      const int buf = t & 1;
-      const bool more = t + 1 < ntiles;
-      if (more) wtile_load<KS>(R, rb, Wb, bias, (t + 1) * 32, N, tid);
-      bf16x8 A[KS];
+  // pass 1
+  float m1[16], m2[16];
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        const uint4 u = sm.frag[buf][kk][lane];
-        A[kk] = *reinterpret_cast<const bf16x8*>(&u);
-      }
-      floatx16 cinit;
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const float4 b4 = *reinterpret_cast<const float4*>(&sm.bias[buf][8 * g + 4 * (lane >> 5)]);
-        cinit[4 * g + 0] = b4.x;
-        cinit[4 * g + 1] = b4.y;
-        cinit[4 * g + 2] = b4.z;
-        cinit[4 * g + 3] = b4.w;
-      }
-      const int nbase = t * 32 + 4 * (lane >> 5);
-#pragma unroll
-      for (int qt = 0; qt < ML_QT; ++qt) {
-        floatx16 acc = cinit;
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc, 0, 0, 0);
-        // rows past N carry bias -FLT_MAX and zero weights: acc = -FLT_MAX, never selected
-        if (pass == 0) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) slot[qt][r] = fmaxf(slot[qt][r], acc[r]);
-        } else {
-          float mloc = acc[0];
-#pragma unroll
-          for (int r = 1; r < 16; ++r) mloc = fmaxf(mloc, acc[r]);
-          if (__any(mloc >= tau[qt])) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int n = nbase + 8 * (r >> 2) + (r & 3);
-              if (acc[r] >= tau[qt] && acc[r] > top[qt].v[PP - 1]) top[qt].insert(acc[r], n);
-            }
-          }
-          if (__any(mloc >= mx[qt] - 30.0f)) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) ssum[qt] += __expf(acc[r] - mx[qt]);
-          }
-        }
-      }
-      if (more) wtile_store<KS>(R, rb, sm, buf ^ 1, tid);
-      __syncthreads();
-    }
-    if (pass == 0) {
-      // m = largest logit; tau = kout-th largest of the 32 slot maxima
-#pragma unroll
-      for (int qt = 0; qt < ML_QT; ++qt) {
-        TopP<ML_P> s8;
-        s8.init();
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          s8.insert(slot[qt][r], r);
-          s8.insert(__shfl_xor(slot[qt][r], 32, 64), 16 + r);
-        }
-        float tk = s8.v[0];
-#pragma unroll
-        for (int u = 1; u < ML_P; ++u)
-          if (u < kout) tk = s8.v[u];
-        tau[qt] = tk;
-        mx[qt] = s8.v[0];
-      }
-    }
+  for (int r = 0; r < 16; ++r) {
+    m1[r] = -FLT_MAX;
+    m2[r] = -FLT_MAX;
   }
+  stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int) {
 #pragma unroll
-  for (int qt = 0; qt < ML_QT; ++qt) {
-    const float s = ssum[qt] + __shfl_xor(ssum[qt], 32, 64);  // both halves share mx
-    float ov[PP];
-    int oi[PP];
-#pragma unroll
-    for (int t = 0; t < PP; ++t) {
-      ov[t] = __shfl_xor(top[qt].v[t], 32, 64);
-      oi[t] = __shfl_xor(top[qt].i[t], 32, 64);
+    for (int r = 0; r < 16; ++r) {
+      m2[r] = fmaxf(m2[r], fminf(m1[r], acc[r]));
+      m1[r] = fmaxf(m1[r], acc[r]);
     }
-    const int64_t q = qbase + qt * 32 + (lane & 31);
-    if (lane < 32 && q < nq) {
-      int a = 0, b = 0;
-      float best[2] = {-FLT_MAX, -FLT_MAX};
+  });
+  // tau and m: the P-th largest and the largest of the query's 64 slot values
+  // (values only: a max/min exchange network keeps v sorted descending)
+  float tau, mxl2;
+  {
+    float v[ML_P];
 #pragma unroll
-      for (int t = 0; t < PP; ++t) {
-        float va = -FLT_MAX, vb = -FLT_MAX;
-        int ia = INT_MAX, ib = INT_MAX;
+    for (int u = 0; u < ML_P; ++u) v[u] = -FLT_MAX;
+    auto push = [&](float x) {
 #pragma unroll
-        for (int u = 0; u < PP; ++u) {
-          if (u == a) {
-            va = top[qt].v[u];
-            ia = top[qt].i[u];
-          }
-          if (u == b) {
-            vb = ov[u];
-            ib = oi[u];
-          }
-        }
-        const bool take_a = (va > vb) || (va == vb && ia < ib);
-        const int id = take_a ? ia : ib;
-        const float vv = take_a ? va : vb;
-        if (take_a) ++a;
-        else ++b;
-        if (t < kout) leaves[q * kout + t] = (id == INT_MAX) ? -1 : id;
-        if (t < 2) best[t] = vv;
+      for (int u = 0; u < ML_P; ++u) {
+        const float hi = fmaxf(v[u], x);
+        x = fminf(v[u], x);
+        v[u] = hi;
       }
-      // p1 - p2 = (1 - exp(l2 - l1)) / sum_j exp(l_j - l1), with l1 = mx
-      margin[q] = (best[1] == -FLT_MAX) ? 1.0f : (1.0f - __expf(best[1] - best[0])) / s;
+    };
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      push(m1[r]);
+      push(m2[r]);
     }
+    float ov[ML_P];
+#pragma unroll
+    for (int u = 0; u < ML_P; ++u) ov[u] = __shfl_xor(v[u], 32, 64);
+#pragma unroll
+    for (int u = 0; u < ML_P; ++u) push(ov[u]);
+    float tk = v[0];
+#pragma unroll
+    for (int u = 1; u < ML_P; ++u)
+      if (u < kout) tk = v[u];
+    tau = tk;
+    mxl2 = v[0] * ML_LOG2E;
+  }
+  // pass 2: hits into the per-lane LDS list, softmax normaliser
+  int cnt = 0;
+  bool ovf = false;
+  float ssum = 0.f;
+  stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const bool hit = acc[r] >= tau;
+      const bool app = hit && cnt < HC;
+      ovf = ovf || (hit && !app);
+      if (app) {
+        hv[cnt][tid] = acc[r];
+        hid[cnt][tid] = t * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        ++cnt;
+      }
+      ssum += __builtin_amdgcn_exp2f(fmaf(acc[r], ML_LOG2E, -mxl2));
+    }
+  });
+  TopP<PP> top;
+  top.init();
+  // a full list (ties or many logits >= tau; not seen in practice): one more
+  // pass in which the lanes concerned insert every hit into the top-P
+  if (__syncthreads_or(ovf ? 1 : 0)) {
+    stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t) {
+      if (ovf) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (acc[r] >= tau) top.insert(acc[r], t * 32 + 8 * (r >> 2) + 4 * h + (r & 3));
+      }
+    });
+  }
+  if (!ovf)
+    for (int c = 0; c < cnt; ++c) top.insert(hv[c][tid], hid[c][tid]);
+  const float s = ssum + __shfl_xor(ssum, 32, 64);  // both halves use the same m
+  float ov[PP];
+  int oi[PP];
+#pragma unroll
+  for (int t = 0; t < PP; ++t) {
+    ov[t] = __shfl_xor(top.v[t], 32, 64);
+    oi[t] = __shfl_xor(top.i[t], 32, 64);
+  }
+  if (lane < 32 && q < nq) {
+    int a = 0, b = 0;
+    float best[2] = {-FLT_MAX, -FLT_MAX};
+#pragma unroll
+    for (int t = 0; t < PP; ++t) {  // merge two descending lists
+      float va = -FLT_MAX, vb = -FLT_MAX;
+      int ia = INT_MAX, ib = INT_MAX;
+#pragma unroll
+      for (int u = 0; u < PP; ++u) {
+        if (u == a) {
+          va = top.v[u];
+          ia = top.i[u];
+        }
+        if (u == b) {
+          vb = ov[u];
+          ib = oi[u];
+        }
+      }
+      const bool take_a = desc_lt(va, ia, vb, ib);
+      const int id = take_a ? ia : ib;
+      const float vv = take_a ? va : vb;
+      if (take_a) ++a;
+      else ++b;
+      if (t < kout) leaves[q * kout + t] = (id == INT_MAX) ? -1 : id;
+      if (t < 2) best[t] = vv;
+    }
+    // p1 - p2 = (1 - exp(l2 - l1)) / sum_j exp(l_j - l1), l1 = m
+    margin[q] = (best[1] == -FLT_MAX) ? 1.0f : (1.0f - exp2f((best[1] - best[0]) * ML_LOG2E)) / s;
   }
 }
 
-#define PTS_MLP_KS_SWITCH(K, ...)                                                                  \
+#define PTS_MLP_KIN_SWITCH(K, ...)                                                                 \
   switch (K) {                                                                                     \
+    case 32: { constexpr int KS1C = 2; __VA_ARGS__; } break;                                       \
+    case 64: { constexpr int KS1C = 4; __VA_ARGS__; } break;                                       \
+    case 96: { constexpr int KS1C = 6; __VA_ARGS__; } break;                                       \
+    case 128: { constexpr int KS1C = 8; __VA_ARGS__; } break;                                      \
+    default: ::pts::fail(PTS_ERR_UNSUPPORTED, "MLP input width must be 32/64/96/128");             \
+  }
+#define PTS_MLP_HID_SWITCH(H, ...)                                                                 \
+  switch (H) {                                                                                     \
     case 32: { constexpr int KSC = 2; __VA_ARGS__; } break;                                        \
     case 64: { constexpr int KSC = 4; __VA_ARGS__; } break;                                        \
-    case 96: { constexpr int KSC = 6; __VA_ARGS__; } break;                                        \
     case 128: { constexpr int KSC = 8; __VA_ARGS__; } break;                                       \
     case 256: { constexpr int KSC = 16; __VA_ARGS__; } break;                                      \
-    default: ::pts::fail(PTS_ERR_UNSUPPORTED, "MLP layer width must be 32/64/96/128/256");         \
+    default: ::pts::fail(PTS_ERR_UNSUPPORTED, "MLP hidden width must be 32/64/128/256");           \
   }
 
-void launch_mlp_hidden(Ctx* c, const uint16_t* X, int64_t nq, int K, const uint16_t* Wb, const float* bias, int N,
-                       uint16_t* Y) {
+void launch_mlp_hidden2(Ctx* c, const float* Qp, int ld, int64_t nq, const float* scale, int n_in, int K1,
+                        const uint16_t* W1b, const float* b1, const uint16_t* W2b, const float* b2, int hidden,
+                        uint16_t* H2) {
   ProfScope ps(c, "mlp_hidden_mfma");
   if (nq == 0) return;
-  PTS_REQUIRE(N % 4 == 0, PTS_ERR_UNSUPPORTED, "MLP hidden width must be a multiple of 4");
-  PTS_MLP_KS_SWITCH(K, hipLaunchKernelGGL((k_mlp_layer<KSC, 0>), dim3((unsigned)ceil_div(nq, ML_QPB)), dim3(ML_THREADS), 0,
-                                          c->stream, X, nq, Wb, bias, N, Y, N, nullptr, nullptr));
-  check_launch("k_mlp_layer<hidden>");
+  PTS_REQUIRE(n_in >= 1 && n_in <= K1 && n_in <= ld, PTS_ERR_ARG, "mlp_hidden2: bad input width");
+  const dim3 grid((unsigned)ceil_div(nq, ML_QPB));
+  PTS_MLP_KIN_SWITCH(K1, PTS_MLP_HID_SWITCH(hidden, hipLaunchKernelGGL((k_mlp_hidden2<KS1C, KSC>), grid,
+                                                                       dim3(ML_THREADS), 0, c->stream, Qp, ld, nq,
+                                                                       scale, n_in, W1b, b1, W2b, b2, H2)));
+  check_launch("k_mlp_hidden2");
 }
 
 void launch_mlp_out_topk(Ctx* c, const uint16_t* X, int64_t nq, int K, const uint16_t* Wb, const float* bias, int N,
                          int k, int32_t* leaves, float* margin) {
   ProfScope ps(c, "mlp_out_topk_mfma");
   if (nq == 0) return;
-  PTS_REQUIRE(k >= 1 && k <= ML_P, PTS_ERR_ARG, "proposals must be 1..8");
+  PTS_REQUIRE(k >= 1 && k <= ML_P && k <= N, PTS_ERR_ARG, "proposals must be 1..8 and at most n_out");
+  const dim3 grid((unsigned)ceil_div(nq, ML_QPB));
   if (k <= 4) {
-    PTS_MLP_KS_SWITCH(K, hipLaunchKernelGGL((k_mlp_out_topk<KSC, 4>), dim3((unsigned)ceil_div(nq, ML_QPB)), dim3(ML_THREADS),
-                                            0, c->stream, X, nq, Wb, bias, N, k, leaves, margin));
+    PTS_MLP_HID_SWITCH(K, hipLaunchKernelGGL((k_mlp_out_topk<KSC, 4>), grid, dim3(ML_THREADS), 0, c->stream, X, nq,
+                                             Wb, bias, N, k, leaves, margin));
   } else {
-    PTS_MLP_KS_SWITCH(K, hipLaunchKernelGGL((k_mlp_out_topk<KSC, 8>), dim3((unsigned)ceil_div(nq, ML_QPB)), dim3(ML_THREADS),
-                                            0, c->stream, X, nq, Wb, bias, N, k, leaves, margin));
+    PTS_MLP_HID_SWITCH(K, hipLaunchKernelGGL((k_mlp_out_topk<KSC, 8>), grid, dim3(ML_THREADS), 0, c->stream, X, nq,
+                                             Wb, bias, N, k, leaves, margin));
   }
   check_launch("k_mlp_out_topk");
 }

@@ -18,6 +18,50 @@
 
 namespace pts {
 
+// nearest child of `node` (ties to the lowest child); the centroid rows are
+// read with the addresses the lanes hold (uniform for the root, so the
+// compiler reads them through the scalar cache)
+template <int DP>
+__device__ __forceinline__ int nearest_child(const float (&qv)[DP], int f, int nc, const float* __restrict__ cent) {
+  float best = FLT_MAX;
+  int bj = 0;
+  for (int j = 0; j < nc; ++j) {
+    const float* cr = cent + (int64_t)(f + j) * DP;
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < DP; k += 4) {
+      const float4 cv = *reinterpret_cast<const float4*>(cr + k);
+      const float t0 = qv[k] - cv.x, t1 = qv[k + 1] - cv.y, t2 = qv[k + 2] - cv.z, t3 = qv[k + 3] - cv.w;
+      acc = fmaf(t0, t0, acc);
+      acc = fmaf(t1, t1, acc);
+      acc = fmaf(t2, t2, acc);
+      acc = fmaf(t3, t3, acc);
+    }
+    if (acc < best) {
+      best = acc;
+      bj = j;
+    }
+  }
+  return f + bj;
+}
+
+// greedy descent from the root: the root's children are the same for every
+// lane (uniform loads), deeper levels follow each lane's own node
+template <int DP>
+__device__ __forceinline__ int descend_one(const float (&qv)[DP], const float* __restrict__ cent,
+                                           const int32_t* __restrict__ first_child,
+                                           const int32_t* __restrict__ n_children) {
+  const int nc0 = n_children[0];
+  if (nc0 == 0) return 0;
+  int node = nearest_child<DP>(qv, first_child[0], nc0, cent);
+  for (int depth = 1; depth < 64; ++depth) {  // bounded: a valid tree ends at a leaf long before
+    const int nc = n_children[node];
+    if (nc == 0) break;
+    node = nearest_child<DP>(qv, first_child[node], nc, cent);
+  }
+  return node;
+}
+
 template <int DP>
 __global__ __launch_bounds__(256) void k_descend(const float* __restrict__ Qp, int64_t nq,
                                                  const float* __restrict__ cent,
@@ -36,33 +80,7 @@ __global__ __launch_bounds__(256) void k_descend(const float* __restrict__ Qp, i
     qv[k + 2] = v.z;
     qv[k + 3] = v.w;
   }
-  int node = 0;
-  for (int depth = 0; depth < 64; ++depth) {  // bounded: a valid tree ends at a leaf long before
-    const int nc = n_children[node];
-    if (nc == 0) break;
-    const int f = first_child[node];
-    float best = FLT_MAX;
-    int bj = 0;
-    for (int j = 0; j < nc; ++j) {
-      const float* cr = cent + (int64_t)(f + j) * DP;
-      float acc = 0.f;
-#pragma unroll
-      for (int k = 0; k < DP; k += 4) {
-        const float4 cv = *reinterpret_cast<const float4*>(cr + k);
-        const float t0 = qv[k] - cv.x, t1 = qv[k + 1] - cv.y, t2 = qv[k + 2] - cv.z, t3 = qv[k + 3] - cv.w;
-        acc = fmaf(t0, t0, acc);
-        acc = fmaf(t1, t1, acc);
-        acc = fmaf(t2, t2, acc);
-        acc = fmaf(t3, t3, acc);
-      }
-      if (acc < best) {
-        best = acc;
-        bj = j;
-      }
-    }
-    node = f + bj;
-  }
-  leaf[q] = leaf_of_node[node];
+  leaf[q] = leaf_of_node[descend_one<DP>(qv, cent, first_child, n_children)];
 }
 
 // Descent restricted to queries whose margin is below thr: a compaction
@@ -74,7 +92,15 @@ __global__ __launch_bounds__(256) void k_compact_low(const float* __restrict__ m
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   leaf[q] = -1;
-  if (!(margin[q] >= thr)) list[atomicAdd(n, 1)] = (int32_t)q;
+  // wave-aggregated append: one atomic per wave reserves the wave's slots
+  const bool low = !(margin[q] >= thr);
+  const uint64_t m = __ballot(low);
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+  int base = 0;
+  if (lane == leader && m) base = atomicAdd(n, (int)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (low) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)q;
 }
 
 template <int DP>
@@ -96,33 +122,7 @@ __global__ __launch_bounds__(256) void k_descend_list(const float* __restrict__ 
     qv[k + 2] = v.z;
     qv[k + 3] = v.w;
   }
-  int node = 0;
-  for (int depth = 0; depth < 64; ++depth) {
-    const int nc = n_children[node];
-    if (nc == 0) break;
-    const int f = first_child[node];
-    float best = FLT_MAX;
-    int bj = 0;
-    for (int j = 0; j < nc; ++j) {
-      const float* cr = cent + (int64_t)(f + j) * DP;
-      float acc = 0.f;
-#pragma unroll
-      for (int k = 0; k < DP; k += 4) {
-        const float4 cv = *reinterpret_cast<const float4*>(cr + k);
-        const float t0 = qv[k] - cv.x, t1 = qv[k + 1] - cv.y, t2 = qv[k + 2] - cv.z, t3 = qv[k + 3] - cv.w;
-        acc = fmaf(t0, t0, acc);
-        acc = fmaf(t1, t1, acc);
-        acc = fmaf(t2, t2, acc);
-        acc = fmaf(t3, t3, acc);
-      }
-      if (acc < best) {
-        best = acc;
-        bj = j;
-      }
-    }
-    node = f + bj;
-  }
-  leaf[q] = leaf_of_node[node];
+  leaf[q] = leaf_of_node[descend_one<DP>(qv, cent, first_child, n_children)];
 }
 
 void launch_descend_low_margin(Ctx* c, const float* Qp, int64_t nq, int dp, const float* margin, float thr,
@@ -322,6 +322,16 @@ void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chu
 
 constexpr int LS_Q = 64, LS_M = 64;
 
+// Workgroup barrier for LDS buffers: this wave's LDS reads and writes
+// complete, then s_barrier; unlike __syncthreads() it leaves the wave's
+// global loads in flight.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+int leaf_scan_f32_chunk(int dp) {
+  (void)dp;
+  return LS_Q;
+}
+
 __device__ __forceinline__ bool better_id(float d, int id, float bd, int bid) {
   return d < bd || (d == bd && id < bid);
 }
@@ -336,9 +346,13 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
                                                        const int32_t* __restrict__ ntiles, int P,
                                                        const float* __restrict__ zres,
                                                        int32_t* __restrict__ nn, float* __restrict__ best_d2) {
-  __shared__ float4 Zs[LS_M][DP / 4];
-  __shared__ int Zid[LS_M];
-  __shared__ float Zr[LS_M];
+  // member rows stream through two LDS buffers: chunk c + 1 is stored while
+  // chunk c is scanned, and chunk c + 2 is loaded into registers meanwhile
+  constexpr int NF4 = LS_M * (DP / 4);          // float4 per chunk
+  constexpr int PERT = (NF4 + 255) / 256;        // per thread
+  __shared__ float4 Zs[2][LS_M][DP / 4];
+  __shared__ int Zid[2][LS_M];
+  __shared__ float Zr[2][LS_M];
   __shared__ float rd[4][LS_Q];
   __shared__ int ri[4][LS_Q];
   const int t = blockIdx.x;
@@ -346,7 +360,7 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
   const int2 tile = tiles[t];
   const int l = tile.x;
   const int qend = qoff[l + 1];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int pos = tile.y + lane;
   const bool active = pos < qend && pos < tile.y + LS_Q;
   const int pair = active ? order[pos] : -1;  // query * P + slot
@@ -364,23 +378,55 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
   float bd = FLT_MAX;
   int bi = INT_MAX;
   const int m0 = leaf_off[l], m1 = leaf_off[l + 1];
-  for (int mb = m0; mb < m1; mb += LS_M) {
-    const int mcount = min(LS_M, m1 - mb);
-    for (int idx = threadIdx.x; idx < LS_M * (DP / 4); idx += 256) {
+  const int nchunks = (m1 - m0 + LS_M - 1) / LS_M;
+  // chunk loads carry no condition (rows past the leaf re-read its last row
+  // and are replaced when stored), so the barriers leave them in flight
+  float4 zreg[PERT];
+  int idreg = 0;
+  float rreg = 0.f;
+  auto load_chunk = [&](int c) {
+    const int mb = m0 + c * LS_M;
+#pragma unroll
+    for (int u = 0; u < PERT; ++u) {
+      const int idx = min(tid + u * 256, NF4 - 1);
       const int r = idx / (DP / 4), k4 = idx - r * (DP / 4);
-      Zs[r][k4] = (r < mcount) ? reinterpret_cast<const float4*>(Zp + (int64_t)(mb + r) * DP)[k4]
-                               : make_float4(0.f, 0.f, 0.f, 0.f);
+      zreg[u] = reinterpret_cast<const float4*>(Zp + (int64_t)min(mb + r, m1 - 1) * DP)[k4];
     }
-    if (threadIdx.x < LS_M) {
-      Zid[threadIdx.x] = (threadIdx.x < mcount) ? perm[mb + threadIdx.x] : INT_MAX;
-      Zr[threadIdx.x] = (zres && threadIdx.x < mcount) ? zres[mb + threadIdx.x] : 0.f;
+    const int rr = min(mb + (tid & (LS_M - 1)), m1 - 1);
+    idreg = perm[rr];
+    rreg = zres ? zres[rr] : 0.f;
+  };
+  auto store_chunk = [&](int c) {
+    const int mb = m0 + c * LS_M, b = c & 1;
+#pragma unroll
+    for (int u = 0; u < PERT; ++u) {
+      const int idx = tid + u * 256;
+      if (idx < NF4) {
+        const int r = idx / (DP / 4), k4 = idx - r * (DP / 4);
+        Zs[b][r][k4] = (mb + r < m1) ? zreg[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
-    __syncthreads();
+    if (tid < LS_M) {
+      Zid[b][tid] = (mb + tid < m1) ? idreg : INT_MAX;
+      Zr[b][tid] = (mb + tid < m1) ? rreg : 0.f;
+    }
+  };
+  if (nchunks > 0) {
+    load_chunk(0);
+    store_chunk(0);
+    load_chunk(min(1, nchunks - 1));
+    lds_barrier();
+  }
+  for (int c = 0; c < nchunks; ++c) {
+    const int b = c & 1;
+    if (c + 1 < nchunks) store_chunk(c + 1);  // into the buffer chunk c - 1 used
+    load_chunk(min(c + 2, nchunks - 1));       // past the end: the last chunk again, never stored
+    const int mcount = min(LS_M, m1 - (m0 + c * LS_M));
     for (int r = wave; r < mcount; r += 4) {
       float acc = 0.f;
 #pragma unroll
       for (int k4 = 0; k4 < DP / 4; ++k4) {
-        const float4 z = Zs[r][k4];
+        const float4 z = Zs[b][r][k4];
         const float t0 = qv[4 * k4] - z.x, t1 = qv[4 * k4 + 1] - z.y;
         const float t2 = qv[4 * k4 + 2] - z.z, t3 = qv[4 * k4 + 3] - z.w;
         acc = fmaf(t0, t0, acc);
@@ -388,14 +434,14 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
         acc = fmaf(t2, t2, acc);
         acc = fmaf(t3, t3, acc);
       }
-      acc += Zr[r];
-      const int id = Zid[r];
+      acc += Zr[b][r];
+      const int id = Zid[b][r];
       if (better_id(acc, id, bd, bi)) {
         bd = acc;
         bi = id;
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   rd[wave][lane] = bd;
   ri[wave][lane] = bi;
@@ -455,7 +501,10 @@ __global__ __launch_bounds__(256) void k_learned_pairs(const int32_t* __restrict
     pair_leaf[q * (P + 1) + s] = l;
   }
   pair_leaf[q * (P + 1) + P] = (fb && !dup && dl >= 0 && dl < n_leaves) ? dl : -1;
-  if (fb) atomicAdd(fallbacks, 1);
+  // one atomic per wave: the wave's count of fallbacks
+  const uint64_t m = __ballot(fb);
+  if ((threadIdx.x & 63) == (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1) && m)
+    atomicAdd(fallbacks, (int)__popcll(m));
 }
 
 void launch_learned_pairs(Ctx* c, const int32_t* prop, const float* margin, const int32_t* dleaf, int64_t nq, int P,

@@ -38,9 +38,10 @@ void launch_energy(Ctx* c, const float* dist, int64_t n, float r, float delta, f
 
 // ---- index (k_index.hip)
 void launch_mean_cov_image(Ctx* c, const float* img, int H, int W, int w, double* mean, double* cov);
-// P = (window - mu) B for every window of the grid; B is [D][dp]
+// P = (window - mu) B for every window of the grid; B is [D][dp]; Qb
+// (optional) [n][dk] = bf16(-2 P), zero past dp
 void launch_project_image(Ctx* c, const float* img, int H, int W, int w, int s, bool wrap, const float* mu,
-                          const float* B, int dp, float* P);
+                          const float* B, int dp, float* P, uint16_t* Qb = nullptr, int dk = 0);
 void launch_kmeans_mindist(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m, const int32_t* seg_of,
                            const float* cand, float* mind, int first);
 void launch_kmeans_assign(Ctx* c, const float* P, int dp, const int32_t* members, int64_t m, const int32_t* seg_of,
@@ -76,7 +77,9 @@ void launch_descend_low_margin(Ctx* c, const float* Qp, int64_t nq, int dp, cons
                                const float* cent, const int32_t* first_child, const int32_t* n_children,
                                const int32_t* leaf_of_node, int32_t* list, int32_t* n, int32_t* leaf);
 void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b);
-// order[] holds pair indices (query * P + slot); results per pair
+// order[] holds pair indices (query * P + slot); results per pair.  The
+// bucketing for it must use chunks of leaf_scan_f32_chunk(dp) pairs.
+int leaf_scan_f32_chunk(int dp);
 void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
                           const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, const float* zres,
                           int32_t* nn, float* best_d2);

@@ -17,8 +17,6 @@ namespace pts {
     default: ::pts::fail(PTS_ERR_UNSUPPORTED, "padded PCA width must be 16/24/32/48/64/96/128");   \
   }
 
-// Qb [nq][dk] = bf16(-2 Qp), zero padded
-void launch_queries_bf16(Ctx* c, const float* Qp, int64_t nq, int dp, int dk, uint16_t* Qb);
 // number of exemplar splits for the brute-force kernel
 int brute_splits(int64_t nq);
 // partial top-8 (score, leaf position) per (split, query): part [S][nq][8]

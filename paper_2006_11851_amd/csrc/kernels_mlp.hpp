@@ -18,12 +18,19 @@ void launch_colsum(Ctx* c, const float* G, int64_t M, int N, float* out);
 void launch_mean(Ctx* c, const float* v, int64_t n, float* out);
 void launch_adam(Ctx* c, float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                  float eps, int64_t t);
-void launch_to_bf16_pad(Ctx* c, const float* src, int rows, int cols, int rows_p, int cols_p, uint16_t* dst);
-void launch_mlp_inputs(Ctx* c, const float* Qp, int ld, int64_t nq, const float* scale, int n_in, int K, uint16_t* Xb);
-// Y [nq][N] bf16 = GELU(X W^T + b), X bf16 [nq][K], W bf16 [N][K]
-void launch_mlp_hidden(Ctx* c, const uint16_t* X, int64_t nq, int K, const uint16_t* Wb, const float* bias, int N,
-                       uint16_t* Y);
+// dst [n_p] = src [n] followed by `fill`
+void launch_pad_f32(Ctx* c, const float* src, int n, int n_p, float fill, float* dst);
+// bf16 copy, zero padded; perm: columns in the matrix-core lane order
+void launch_to_bf16_pad(Ctx* c, const float* src, int rows, int cols, int rows_p, int cols_p, bool perm,
+                        uint16_t* dst);
+// H2 [nq][hidden] bf16 (lane order) = both hidden layers applied to
+// bf16(Qp * scale); W1b [hidden][K1] natural order, W2b [hidden][hidden] permuted
+void launch_mlp_hidden2(Ctx* c, const float* Qp, int ld, int64_t nq, const float* scale, int n_in, int K1,
+                        const uint16_t* W1b, const float* b1, const uint16_t* W2b, const float* b2, int hidden,
+                        uint16_t* H2);
 // leaves [nq][k] (descending logit, ties to the lower leaf) and margin p1 - p2
+// from H2 [nq][K] (lane order), W3b [round_up(N, 32)][K] (permuted, zero
+// rows past N) and the bias padded to round_up(N, 32) with -FLT_MAX
 void launch_mlp_out_topk(Ctx* c, const uint16_t* X, int64_t nq, int K, const uint16_t* Wb, const float* bias, int N,
                          int k, int32_t* leaves, float* margin);
 

@@ -6,6 +6,7 @@
 // (or FP32 for gradient checks).  Minibatches are drawn on the GPU from a
 // counter-based hash, so training needs no host round trips except the
 // logged losses.
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 
@@ -110,9 +111,11 @@ const Mlp& bf_weights(Ctx* c) {
     uint16_t* w1 = static_cast<uint16_t*>(m.w1b.ensure(c, (size_t)m.h * K1 * 2));
     uint16_t* w2 = static_cast<uint16_t*>(m.w2b.ensure(c, (size_t)m.h * m.h * 2));
     uint16_t* w3 = static_cast<uint16_t*>(m.w3b.ensure(c, (size_t)round_up(m.n_out, 32) * m.h * 2));
-    launch_to_bf16_pad(c, P + L.W1, m.h, m.n_in, m.h, K1, w1);
-    launch_to_bf16_pad(c, P + L.W2, m.h, m.h, m.h, m.h, w2);
-    launch_to_bf16_pad(c, P + L.W3, m.n_out, m.h, (int)round_up(m.n_out, 32), m.h, w3);
+    launch_to_bf16_pad(c, P + L.W1, m.h, m.n_in, m.h, K1, false, w1);
+    launch_to_bf16_pad(c, P + L.W2, m.h, m.h, m.h, m.h, true, w2);
+    launch_to_bf16_pad(c, P + L.W3, m.n_out, m.h, (int)round_up(m.n_out, 32), m.h, true, w3);
+    float* b3p = static_cast<float*>(m.b3p.ensure(c, (size_t)round_up(m.n_out, 32) * 4));
+    launch_pad_f32(c, P + L.b3, m.n_out, (int)round_up(m.n_out, 32), -FLT_MAX, b3p);
     m.bf_version = m.version;
   }
   return m;
@@ -126,13 +129,10 @@ void mlp_propose_rows(Ctx* c, const float* Qp, int ld, int64_t n, int k, int32_t
   const Layout L = layout(m);
   const float* P = m.params.as<float>();
   const int K1 = k_in(m);
-  uint16_t* xb = c->buf<uint16_t>("mlp_xb", (size_t)n * K1);
-  uint16_t* h1 = c->buf<uint16_t>("mlp_h1b", (size_t)n * m.h);
   uint16_t* h2 = c->buf<uint16_t>("mlp_h2b", (size_t)n * m.h);
-  launch_mlp_inputs(c, Qp, ld, n, m.in_scale.as<float>(), m.n_in, K1, xb);
-  launch_mlp_hidden(c, xb, n, K1, bc.w1b.as<uint16_t>(), P + L.b1, m.h, h1);
-  launch_mlp_hidden(c, h1, n, m.h, bc.w2b.as<uint16_t>(), P + L.b2, m.h, h2);
-  launch_mlp_out_topk(c, h2, n, m.h, bc.w3b.as<uint16_t>(), P + L.b3, m.n_out, k, leaves, margin);
+  launch_mlp_hidden2(c, Qp, ld, n, m.in_scale.as<float>(), m.n_in, K1, bc.w1b.as<uint16_t>(), P + L.b1,
+                     bc.w2b.as<uint16_t>(), P + L.b2, m.h, h2);
+  launch_mlp_out_topk(c, h2, n, m.h, bc.w3b.as<uint16_t>(), bc.b3p.as<float>(), m.n_out, k, leaves, margin);
 }
 
 }  // namespace pts
