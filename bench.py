@@ -243,7 +243,27 @@ def roofline(ctx, head, info, nq, a, forms):
                 "traffic": None, "ms_per_launch": per_launch_ms}
     ach = flops / (per_launch_ms * 1e-3) / 1e12
     return {"kernel": dom, "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-            "traffic": None, "ms_per_launch": per_launch_ms, "algorithmic_flops_per_launch": flops}
+            "traffic": measured_traffic(dom), "ms_per_launch": per_launch_ms, "algorithmic_flops_per_launch": flops}
+
+
+def measured_traffic(label):
+    """HBM bytes per full-size launch of the kernel behind `label`, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy
+    calibration), or None when there is none or the kernel's source file has
+    changed since the counters were taken."""
+    import glob
+    import hashlib
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+        for line in open(path):
+            f = line.split()
+            if len(f) == 5 and f[0] == "traffic:" and f[1] == label:
+                src = os.path.join(ROOT, "paper_2006_11851_amd", "csrc", f[3])
+                if not os.path.exists(src):
+                    return None
+                digest = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+                return float(f[2]) if digest == f[4] else None
+    return None
 
 
 def scanned_pairs(ctx, head, info, nq):

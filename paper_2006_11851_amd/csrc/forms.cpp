@@ -46,8 +46,9 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
                             ix.n_children.as<int32_t>(), ix.leaf_of_node.as<int32_t>(), lowq, nlow, dleaf);
   const int P1 = P + 1;  // proposals + the tree's leaf for low-margin queries
   int32_t* pair_leaf = c->buf<int32_t>("ln_pair_leaf", (size_t)nq * P1);
-  int32_t* fb = c->buf<int32_t>("ln_fallbacks", 1);
-  launch_zero_i32(c, fb, 1);
+  // the fallback count (one atomic per wave) only when statistics are asked for
+  int32_t* fb = count_fallbacks ? c->buf<int32_t>("ln_fallbacks", 1) : nullptr;
+  if (fb) launch_zero_i32(c, fb, 1);
   launch_learned_pairs(c, prop, margin, dleaf, nq, P, p.margin, L, pair_leaf, fb);
   const int chunk = bf16_scan ? 512 : leaf_scan_f32_chunk(ix.dp);
   int max_tiles = 0;

@@ -24,6 +24,7 @@
 #include <climits>
 
 #include "kernels_bf16.hpp"
+#include "device_util.hpp"
 
 namespace pts {
 
@@ -310,6 +311,8 @@ __global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restri
                                                         const int32_t* __restrict__ ntiles,
                                                         float* __restrict__ pair_d, int32_t* __restrict__ pair_i) {
   __shared__ BruteSmem<KS> sm;
+  // plain hardware order: the tile costs vary with the leaf size and cluster
+  // along the list, so a contiguous range per XCD would be unbalanced
   const int t = blockIdx.x;
   if (t >= *ntiles) return;  // uniform per block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -622,12 +625,13 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     int32_t* __restrict__ nn, float* __restrict__ dist) {
   __shared__ int32_t cand[BB_TOPK][SR_QPB];
   const int tid = threadIdx.x;
-  const int64_t q0 = (int64_t)blockIdx.x * SR_QPB;
+  const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SR_QPB;
   {
     const int64_t q = q0 + tid;
     Top8Lex top;
     top.init();
     if (q < nq) {
+#pragma unroll 2
       for (int li = 0; li < S; ++li) {
         const int64_t row = q * qs + (int64_t)li * ss;
         if (valid && valid[row] < 0) continue;
@@ -678,6 +682,7 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
       dx -= w;
       ++dy;
     }
+#pragma unroll 4
     for (int p = g; p < npx; p += 16) {
       int xx = u + dx;
       if (xx >= W) xx -= W;

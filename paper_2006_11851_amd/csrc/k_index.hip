@@ -14,6 +14,7 @@
 #include <climits>
 
 #include "kernels.hpp"
+#include "device_util.hpp"
 
 namespace pts {
 
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) void k_project_mfma(WinGeom g, int64_t n, int 
   bool ok[PM_WT];
 #pragma unroll
   for (int wt = 0; wt < PM_WT; ++wt) {
-    win[wt] = (int64_t)blockIdx.x * PM_WPB + wave * (16 * PM_WT) + wt * 16 + col;
+    win[wt] = (int64_t)xcd_block(blockIdx.x, gridDim.x) * PM_WPB + wave * (16 * PM_WT) + wt * 16 + col;
     ok[wt] = win[wt] < n;
     const int64_t wc = ok[wt] ? win[wt] : 0;
     const int i = (int)(wc / g.cols), j = (int)(wc - (int64_t)i * g.cols);

@@ -19,6 +19,7 @@
 // initialises the accumulator and each lane folds its 16 values into a
 // running top-P (descending, ties to the lower leaf) and an online softmax
 // normaliser, merged with the lane sharing its query at the end.
+#include <algorithm>
 #include <cfloat>
 #include <type_traits>
 #include <climits>
@@ -75,19 +76,25 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 // TA: A stored [K][M] (else [M][K]); TB: B stored [N][K] (else [K][N]).
 // 256 threads, 64 x 64 tile, K chunks of 16; thread owns 4 x 4 outputs.
 
+// Split over K when the output has few tiles: slice z = blockIdx.z covers
+// k in [z kc, (z + 1) kc) and writes its partial product to P[z]; the
+// slices are then summed in order (k_splitk_sum).  With one slice the block
+// writes C directly.
 template <bool TA, bool TB, bool BF>
 __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, const float* __restrict__ B,
-                                              float* __restrict__ C, int M, int N, int K, int accumulate) {
+                                              float* __restrict__ C, int M, int N, int K, int accumulate, int kc,
+                                              float* __restrict__ P) {
   __shared__ float As[16][64 + 1];
   __shared__ float Bs[16][64 + 1];
   const int tid = threadIdx.x, tm = tid & 15, tn = tid >> 4;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
   float acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     for (int t = tid; t < 16 * 64; t += 256) {
       // A chunk: element (k, m)
       int kk, mm;
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, const
       }
       const int gk = k0 + kk, gm = m0 + mm;
       float va = 0.f;
-      if (gk < K && gm < M) va = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
+      if (gk < ke && gm < M) va = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
       As[kk][mm] = BF ? round_bf16f(va) : va;
       int kb, nb;
       if (TB) {
@@ -112,7 +119,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, const
       }
       const int gkb = k0 + kb, gn = n0 + nb;
       float vb = 0.f;
-      if (gkb < K && gn < N) vb = TB ? B[(int64_t)gn * K + gkb] : B[(int64_t)gkb * N + gn];
+      if (gkb < ke && gn < N) vb = TB ? B[(int64_t)gn * K + gkb] : B[(int64_t)gkb * N + gn];
       Bs[kb][nb] = BF ? round_bf16f(vb) : vb;
     }
     __syncthreads();
@@ -138,19 +145,42 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, const
     for (int b = 0; b < 4; ++b) {
       const int gn = n0 + tn + 16 * b;
       if (gn >= N) continue;
-      float* dst = C + (int64_t)gm * N + gn;
-      *dst = accumulate ? *dst + acc[a][b] : acc[a][b];
+      if (gridDim.z > 1) {
+        P[((int64_t)blockIdx.z * M + gm) * N + gn] = acc[a][b];
+      } else {
+        float* dst = C + (int64_t)gm * N + gn;
+        *dst = accumulate ? *dst + acc[a][b] : acc[a][b];
+      }
     }
   }
 }
+
+__global__ __launch_bounds__(256) void k_splitk_sum(const float* __restrict__ P, int S, int64_t n,
+                                                    float* __restrict__ C, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < S; ++z) s += P[(int64_t)z * n + i];
+  C[i] = accumulate ? C[i] + s : s;
+}
+
+unsigned eblocks(int64_t n) { return (unsigned)ceil_div(n, 256); }
 
 void launch_gemm(Ctx* c, bool ta, bool tb, bool bf, const float* A, const float* B, float* C, int M, int N, int K,
                  bool accumulate) {
   ProfScope ps(c, "mlp_gemm");
   if (M == 0 || N == 0) return;
-  dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64));
+  // enough blocks to fill the chip: split K when the output has few tiles
+  const int64_t tiles = ceil_div(N, 64) * ceil_div(M, 64);
+  int S = 1;
+  if (tiles < 512 && K >= 256) S = (int)std::min<int64_t>({16, ceil_div(512, tiles), K / 128});
+  const int kc = (int)round_up(ceil_div(std::max(K, 1), S), 16);
+  S = (int)ceil_div(std::max(K, 1), kc);
+  float* P = S > 1 ? c->buf<float>("gemm_splitk", (size_t)S * M * N) : nullptr;
+  dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64), (unsigned)S);
 #define PTS_GEMM(TA_, TB_, BF_) \
-  hipLaunchKernelGGL((k_gemm<TA_, TB_, BF_>), grid, dim3(256), 0, c->stream, A, B, C, M, N, K, accumulate ? 1 : 0)
+  hipLaunchKernelGGL((k_gemm<TA_, TB_, BF_>), grid, dim3(256), 0, c->stream, A, B, C, M, N, K, accumulate ? 1 : 0, \
+                     kc, P)
   if (!ta && tb && !bf) PTS_GEMM(false, true, false);
   else if (!ta && tb && bf) PTS_GEMM(false, true, true);
   else if (!ta && !tb && !bf) PTS_GEMM(false, false, false);
@@ -160,6 +190,11 @@ void launch_gemm(Ctx* c, bool ta, bool tb, bool bf, const float* A, const float*
   else fail(PTS_ERR_ARG, "gemm: unsupported transpose form");
 #undef PTS_GEMM
   check_launch("k_gemm");
+  if (S > 1) {
+    hipLaunchKernelGGL(k_splitk_sum, dim3(eblocks((int64_t)M * N)), dim3(256), 0, c->stream, P, S, (int64_t)M * N, C,
+                       accumulate ? 1 : 0);
+    check_launch("k_splitk_sum");
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -234,12 +269,28 @@ __global__ __launch_bounds__(256) void k_gelu_bwd(float* __restrict__ dH, const 
   dH[t] *= gelu_grad_f(Z[t]);
 }
 
-// out[n] = sum_m G[m][n] in row order
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ G, int64_t M, int N, float* __restrict__ out) {
+// out[n] = sum_m G[m][n]: segments of CS_ROWS rows summed in row order into
+// part[seg][n], then the segments summed in order (a fixed order: the
+// result does not depend on the launch).
+constexpr int CS_ROWS = 64;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ G, int64_t M, int N,
+                                                     float* __restrict__ part) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t seg = blockIdx.y;
+  if (n >= N) return;
+  const int64_t m0 = seg * CS_ROWS, m1 = min(M, m0 + CS_ROWS);
+  float s = 0.f;
+  for (int64_t m = m0; m < m1; ++m) s += G[m * N + n];
+  part[seg * N + n] = s;
+}
+
+__global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int nseg, int N,
+                                                      float* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   float s = 0.f;
-  for (int64_t m = 0; m < M; ++m) s += G[m * N + n];
+  for (int g = 0; g < nseg; ++g) s += part[(int64_t)g * N + n];
   out[n] = s;
 }
 
@@ -287,7 +338,6 @@ __global__ __launch_bounds__(256) void k_to_bf16_pad(const float* __restrict__ s
   dst[t] = (r < rows && cc < cols) ? bf16_bits(src[(int64_t)r * cols + cc]) : (uint16_t)0;
 }
 
-unsigned eblocks(int64_t n) { return (unsigned)ceil_div(n, 256); }
 
 void launch_sample_idx(Ctx* c, uint64_t seed, int64_t step, int batch, int64_t n, int64_t* idx) {
   hipLaunchKernelGGL(k_sample_idx, dim3(eblocks(batch)), dim3(256), 0, c->stream, seed, step, batch, n, idx);
@@ -316,8 +366,13 @@ void launch_gelu_bwd(Ctx* c, float* dH, const float* Z, int64_t n) {
   check_launch("k_gelu_bwd");
 }
 void launch_colsum(Ctx* c, const float* G, int64_t M, int N, float* out) {
-  hipLaunchKernelGGL(k_colsum, dim3(eblocks(N)), dim3(256), 0, c->stream, G, M, N, out);
-  check_launch("k_colsum");
+  const int nseg = (int)std::max<int64_t>(1, ceil_div(M, CS_ROWS));
+  PTS_REQUIRE(nseg < 65536, PTS_ERR_UNSUPPORTED, "colsum: too many rows");
+  float* part = c->buf<float>("colsum_part", (size_t)nseg * N);
+  hipLaunchKernelGGL(k_colsum_part, dim3(eblocks(N), nseg), dim3(256), 0, c->stream, G, M, N, part);
+  check_launch("k_colsum_part");
+  hipLaunchKernelGGL(k_colsum_final, dim3(eblocks(N)), dim3(256), 0, c->stream, part, nseg, N, out);
+  check_launch("k_colsum_final");
 }
 void launch_mean(Ctx* c, const float* v, int64_t n, float* out) {
   hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, c->stream, v, n, out);
@@ -577,6 +632,7 @@ __device__ __forceinline__ void stream_tiles(uint4 (*frag)[KS][64], float (*bs)[
   wt_store<KS>(T0, frag[0], bs[0], tid);
   lds_barrier();
   floatx16 acc[2] = {{}, {}};
+  const bool epi_first = (tid >> 8) & 1;
   // one step on tile tt with register set / buffer / accumulator U (= tt % 2)
   auto step = [&](auto U, int tt) {
     constexpr int u = decltype(U)::value;
@@ -586,8 +642,11 @@ __device__ __forceinline__ void stream_tiles(uint4 (*frag)[KS][64], float (*bs)[
     const int tn = min(tt + 2, ntiles - 1) * 32;
     if constexpr (u == 0) T0 = wt_load<KS>(Wb, bias, tn, tid);
     else T1 = wt_load<KS>(Wb, bias, tn, tid);
+    // the second wave of each SIMD (waves 4..7) runs the epilogue first, so
+    // that one wave's vector work overlaps the other's matrix products
+    if (epi_first && tt >= 1) epi(acc[u ^ 1], tt - 1);
     if (tt < ntiles) acc[u] = tile_mfma<KS>(frag[u], bs[u], B, lane);
-    if (tt >= 1) epi(acc[u ^ 1], tt - 1);
+    if (!epi_first && tt >= 1) epi(acc[u ^ 1], tt - 1);
     if (tt + 1 < ntiles) {
       if constexpr (u == 0) wt_store<KS>(T1, frag[1], bs[1], tid);
       else wt_store<KS>(T0, frag[0], bs[0], tid);

@@ -11,6 +11,7 @@
 // at zero distance), and the energy uses the matching smooth penalty
 //   rho(d) = d^r (d >= delta),  (1 - r/2) delta^r + (r/2) delta^(r-2) d^2 (d < delta).
 #include "kernels.hpp"
+#include "device_util.hpp"
 
 namespace pts {
 
@@ -21,7 +22,7 @@ __global__ __launch_bounds__(256) void k_mstep_patch2x2(const int32_t* __restric
                                                         int H, int W, int w, int s, const float4* __restrict__ ex,
                                                         int Hz, int Wz, float r, float delta, int o, int npx,
                                                         int npy) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= (int64_t)npx * npy) return;
   const int a = (int)(t % npx);
   const int b = (int)(t / npx) - o;

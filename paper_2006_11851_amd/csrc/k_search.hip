@@ -9,6 +9,7 @@
 #include <climits>
 
 #include "kernels.hpp"
+#include "device_util.hpp"
 
 namespace pts {
 
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_winner_dist(const float4* __restrict__ 
                                                      const int32_t* __restrict__ nn, int64_t nq,
                                                      float* __restrict__ dist) {
   const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t q = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (q >= nq) return;  // uniform per wave
   const int i = (int)(q / cols), j = (int)(q - (int64_t)i * cols);
   const int v = i * s, u = j * s;

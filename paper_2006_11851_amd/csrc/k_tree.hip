@@ -89,18 +89,26 @@ __global__ __launch_bounds__(256) void k_descend(const float* __restrict__ Qp, i
 __global__ __launch_bounds__(256) void k_compact_low(const float* __restrict__ margin, int64_t nq, float thr,
                                                      int32_t* __restrict__ list, int32_t* __restrict__ n,
                                                      int32_t* __restrict__ leaf) {
+  // block-aggregated append: the block's count from the four wave ballots,
+  // one atomic per block reserves its slots
+  __shared__ int wcount[4];
+  __shared__ int base;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
-  leaf[q] = -1;
-  // wave-aggregated append: one atomic per wave reserves the wave's slots
-  const bool low = !(margin[q] >= thr);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool in = q < nq;
+  if (in) leaf[q] = -1;
+  const bool low = in && !(margin[q] >= thr);
   const uint64_t m = __ballot(low);
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
-  int base = 0;
-  if (lane == leader && m) base = atomicAdd(n, (int)__popcll(m));
-  base = __shfl(base, leader, 64);
-  if (low) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)q;
+  if (lane == 0) wcount[wave] = (int)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    base = tot ? atomicAdd(n, tot) : 0;
+  }
+  __syncthreads();
+  int off = base;
+  for (int w = 0; w < wave; ++w) off += wcount[w];
+  if (low) list[off + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)q;
 }
 
 template <int DP>
@@ -355,6 +363,8 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
   __shared__ float Zr[2][LS_M];
   __shared__ float rd[4][LS_Q];
   __shared__ int ri[4][LS_Q];
+  // plain hardware order: the tile costs vary with the leaf size and cluster
+  // along the list, so a contiguous range per XCD would be unbalanced
   const int t = blockIdx.x;
   if (t >= *ntiles) return;  // uniform per block
   const int2 tile = tiles[t];
@@ -501,10 +511,12 @@ __global__ __launch_bounds__(256) void k_learned_pairs(const int32_t* __restrict
     pair_leaf[q * (P + 1) + s] = l;
   }
   pair_leaf[q * (P + 1) + P] = (fb && !dup && dl >= 0 && dl < n_leaves) ? dl : -1;
-  // one atomic per wave: the wave's count of fallbacks
-  const uint64_t m = __ballot(fb);
-  if ((threadIdx.x & 63) == (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1) && m)
-    atomicAdd(fallbacks, (int)__popcll(m));
+  // one atomic per wave: the wave's count of fallbacks (when counted)
+  if (fallbacks) {
+    const uint64_t m = __ballot(fb);
+    if ((threadIdx.x & 63) == (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1) && m)
+      atomicAdd(fallbacks, (int)__popcll(m));
+  }
 }
 
 void launch_learned_pairs(Ctx* c, const int32_t* prop, const float* margin, const int32_t* dleaf, int64_t nq, int P,
