@@ -71,11 +71,31 @@ constexpr int BB_TOPK = 8;
 // for the wave's global loads, so the next stages stay in flight across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Fragment layout of a stage, in 16-byte units: 32-row tile t, k-chunk kk,
+// half hh (k-values 16 kk + 8 hh .. + 7), row i at t TS + kk KKS + hh HS + i.
+// The MFMA read (lane l: half l / 32, row l % 32) is contiguous for every 16
+// lanes.  A store cycle of 16 lanes covers 16 / (2 KS) rows and all their
+// chunks (2 KS per row); with HS = 32 + SP and KKS = 64 + 2 SP, SP = 16 / (2
+// KS), chunk c of row i lands in bank group (SP c + i) mod 16: distinct over
+// the cycle, where unpadded strides would put a row's chunks in one group.
+template <int KS>
+struct StageLayout {
+  static constexpr int SP = 2 * KS >= 16 ? 1 : 16 / (2 * KS);
+  static constexpr int HS = 32 + SP, KKS = 64 + 2 * SP, TS = KS * KKS;
+};
+
 template <int KS>
 struct BruteSmem {
-  uint4 frag[2][BB_STAGE / 32][KS][64];  // [buffer][tile][k-step][lane] 16 B each
+  uint4 frag[2][BB_STAGE / 32 * StageLayout<KS>::TS];  // [buffer][fragment layout above]
   float zn[2][BB_STAGE];
 };
+
+// the lane's 16-byte fragment of tile t, k-chunk kk
+template <int KS>
+__device__ __forceinline__ uint4 stage_frag(const BruteSmem<KS>& S, int buf, int t, int kk, int lane) {
+  using L = StageLayout<KS>;
+  return S.frag[buf][t * L::TS + kk * L::KKS + (lane >> 5) * L::HS + (lane & 31)];
+}
 
 // Loads one stage (rows r0 .. r0+127 of [row_begin, row_end)) from global
 // into registers: each thread owns up to 2 chunks of 16 B plus zn entries.
@@ -119,7 +139,8 @@ __device__ __forceinline__ void stage_store(const StageRegs<KS>& R, BruteSmem<KS
       const int row = c / CH, ch = c - row * CH;
       const int tile = row >> 5, i = row & 31;
       const int kk = ch >> 1, half = ch & 1;
-      S.frag[buf][tile][kk][half * 32 + i] = (r0 + row < row_end) ? R.v[u] : make_uint4(0, 0, 0, 0);
+      S.frag[buf][tile * StageLayout<KS>::TS + kk * StageLayout<KS>::KKS + half * StageLayout<KS>::HS + i] =
+          (r0 + row < row_end) ? R.v[u] : make_uint4(0, 0, 0, 0);
     }
   }
   if (tid < BB_STAGE) S.zn[buf][tid] = (r0 + tid < row_end) ? R.zn : FLT_MAX;
@@ -135,7 +156,7 @@ __device__ __forceinline__ void stage_compute(const BruteSmem<KS>& S, int buf, c
     bf16x8 A[KS];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      const uint4 u = S.frag[buf][t][kk][lane];
+      const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
       A[kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
     floatx16 cinit;
@@ -267,7 +288,7 @@ __device__ __forceinline__ void stage_compute_cls(const BruteSmem<KS>& S, int bu
     bf16x8 A[KS];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      const uint4 u = S.frag[buf][t][kk][lane];
+      const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
       A[kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
     floatx16 cinit;

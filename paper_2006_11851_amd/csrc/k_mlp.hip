@@ -464,24 +464,38 @@ __device__ __forceinline__ TileRegs wt_load(const uint16_t* __restrict__ Wb, con
   return T;
 }
 
-// registers -> LDS in fragment order: frag[kk][h * 32 + row] = W[row][16 kk + 8 h .. + 7]
+// LDS fragment layout of one weight tile, in 16-byte units: k-chunk kk,
+// half hh (k-values 16 kk + 8 hh .. + 7), row r at kk * WF_KK + hh * WF_HALF
+// + r.  The MFMA read (lane l: half l / 32, row l % 32) is contiguous for
+// every 16 lanes; the padding (33 and 66 instead of 32 and 64) spreads the
+// stores, where the 32 chunks of one row go to 16 KS different (kk, hh), over
+// all banks: (2 kk + hh + r) mod 16 differs for the 16 lanes of a store
+// cycle.
+constexpr int WF_HALF = 33, WF_KK = 2 * WF_HALF;
+
+// registers -> LDS in fragment order
 template <int KS>
-__device__ __forceinline__ void wt_store(const TileRegs& T, uint4 (*frag)[64], float* bs, int tid) {
+__device__ __forceinline__ void wt_store(const TileRegs& T, uint4* frag, float* bs, int tid) {
 #pragma unroll
   for (int u = 0; u < WTile<KS>::PER; ++u) {
     const int cidx = tid + u * ML_THREADS;
     if (cidx < WTile<KS>::NCH) {
       const int row = cidx / WTile<KS>::CH, ch = cidx - row * WTile<KS>::CH;
-      frag[ch >> 1][(ch & 1) * 32 + row] = u ? T.c1 : T.c0;
+      frag[(ch >> 1) * WF_KK + (ch & 1) * WF_HALF + row] = u ? T.c1 : T.c0;
     }
   }
   if (tid < 32) bs[tid] = T.b;
 }
 
-// acc = bias (of the lane's 16 rows) + sum_kk A[kk] B[kk]
+// acc = bias (of the lane's 16 rows) + sum_kk A[kk] B[kk]; the A fragments
+// are read from LDS four k-chunks ahead of their matrix product
 template <int KS>
-__device__ __forceinline__ floatx16 tile_mfma(const uint4 (*frag)[64], const float* bs, const bf16x8 (&B)[KS],
-                                              int lane) {
+__device__ __forceinline__ floatx16 tile_mfma(const uint4* frag, const float* bs, const bf16x8 (&B)[KS], int lane) {
+  constexpr int AH = KS < 4 ? KS : 4;
+  const uint4* fp = frag + (lane >> 5) * WF_HALF + (lane & 31);
+  uint4 a[AH];
+#pragma unroll
+  for (int j = 0; j < AH; ++j) a[j] = fp[j * WF_KK];
   floatx16 acc;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
@@ -493,8 +507,17 @@ __device__ __forceinline__ floatx16 tile_mfma(const uint4 (*frag)[64], const flo
   }
 #pragma unroll
   for (int kk = 0; kk < KS; ++kk) {
-    const uint4 u = frag[kk][lane];
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(&u), B[kk], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(&a[kk % AH]), B[kk], acc, 0, 0, 0);
+    if (kk + AH < KS) a[kk % AH] = fp[(kk + AH) * WF_KK];
+  }
+  // keep that order (the scheduler would otherwise pull the reads next to
+  // their products): the AH + 4 first LDS reads (fragments, bias), then one
+  // product and one read at a time
+  __builtin_amdgcn_sched_group_barrier(0x100, AH + 4, 0);
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    if (kk + AH < KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
   }
   return acc;
 }
@@ -521,7 +544,7 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_hidden2(const float* __restr
   constexpr int KSM = KS1 > KSH ? KS1 : KSH;
   constexpr int PERM = WTile<KSM>::PER;
   constexpr int NT = KSH / 2;  // tiles of 32 hidden units per layer
-  __shared__ uint4 frag[2][KSM][64];
+  __shared__ uint4 frag[2][KSM * WF_KK];
   __shared__ float bs[2][32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
   const int64_t q = (int64_t)blockIdx.x * ML_QPB + wave * 32 + (lane & 31);
@@ -623,7 +646,7 @@ struct TopP {
 // not wait for the loads in flight, so every load has two steps to arrive.
 // Two steps per trip keep the register sets and accumulators static.
 template <int KS, class Epi>
-__device__ __forceinline__ void stream_tiles(uint4 (*frag)[KS][64], float (*bs)[32], const uint16_t* __restrict__ Wb,
+__device__ __forceinline__ void stream_tiles(uint4 (*frag)[KS * WF_KK], float (*bs)[32], const uint16_t* __restrict__ Wb,
                                              const float* __restrict__ bias, int ntiles, const bf16x8 (&B)[KS],
                                              int tid, int lane, Epi&& epi) {
   TileRegs T0 = wt_load<KS>(Wb, bias, 0, tid), T1 = T0;
@@ -662,13 +685,15 @@ __device__ __forceinline__ void stream_tiles(uint4 (*frag)[KS][64], float (*bs)[
 // Output layer, exact top-P leaves and the softmax margin p1 - p2, in two
 // passes over the weight tiles (the logits are never stored).
 //  Pass 1: per value slot (lane, register) the largest and second-largest
-//    logit (3 operations per logit).  Then per query: m = the largest logit
-//    and tau = the P-th largest of the 64 slot values, which are 64 distinct
-//    logits, so tau <= the P-th largest logit: every top-P logit is >= tau,
-//    and usually only those are.
+//    logit and the tile of the largest (4 operations per logit).  Then per
+//    query: m = the largest logit and tau = the P-th largest of the 64 slot
+//    values, which are 64 distinct logits, so tau <= the P-th largest logit:
+//    every top-P logit is >= tau, and usually only those are.
 //  Pass 2: recompute the logits; append each logit >= tau (with its leaf) to
 //    a per-lane list in LDS (into the in-register top-P should the list be
-//    full), and accumulate sum exp(l - m).
+//    full) - only for slots whose second-largest logit is >= tau, the others
+//    holding at most their maximum, appended before the pass - and
+//    accumulate sum exp(l - m).
 //  Finally each lane ranks its list, and the two lanes of each query merge
 //  their top-P lists.
 template <int KS, int PP>
@@ -679,7 +704,7 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_out_topk(const uint16_t* __r
                                                              float* __restrict__ margin) {
   constexpr int PERM = WTile<KS>::PER;
   constexpr int HC = 8;  // hit-list capacity per lane
-  __shared__ uint4 frag[2][KS][64];
+  __shared__ uint4 frag[2][KS * WF_KK];
   __shared__ float bs[2][32];
   __shared__ float hv[HC][ML_THREADS];
   __shared__ int hid[HC][ML_THREADS];
@@ -695,16 +720,23 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_out_topk(const uint16_t* __r
   const int ntiles = (N + 31) / 32;
   // pass 1
   float m1[16], m2[16];
+  int i1[16];  // tile of m1 (the first one on ties)
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     m1[r] = -FLT_MAX;
     m2[r] = -FLT_MAX;
+    i1[r] = 0;
   }
-  stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int) {
+  stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      m2[r] = fmaxf(m2[r], fminf(m1[r], acc[r]));
-      m1[r] = fmaxf(m1[r], acc[r]);
+      // with m2 <= m1, max(m2, min(m1, x)) is the median of the three; a
+      // compare-select for the maximum (fmaxf would first quieten its
+      // operands, one more instruction each)
+      const bool gt = acc[r] > m1[r];
+      m2[r] = __builtin_amdgcn_fmed3f(acc[r], m1[r], m2[r]);
+      m1[r] = gt ? acc[r] : m1[r];
+      i1[r] = gt ? t : i1[r];
     }
   });
   // tau and m: the P-th largest and the largest of the query's 64 slot values
@@ -739,22 +771,51 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_out_topk(const uint16_t* __r
     tau = tk;
     mxl2 = v[0] * ML_LOG2E;
   }
-  // pass 2: hits into the per-lane LDS list, softmax normaliser
+  // A slot whose second-largest logit is below tau holds at most one logit
+  // >= tau, its maximum, known with its tile from pass 1: appended here.
+  // Only slots with m2 >= tau (several top logits in one slot, or ties) are
+  // searched again in pass 2, and a slot index r that no lane of the wave
+  // needs is skipped there by a wave-uniform branch.
   int cnt = 0;
   bool ovf = false;
+  uint32_t need = 0, flagged = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const bool flag = m2[r] >= tau;
+    if (__ballot(flag)) need |= 1u << r;
+    flagged |= (flag ? 1u : 0u) << r;
+    const bool direct = !flag && m1[r] >= tau;
+    const bool app = direct && cnt < HC;
+    ovf = ovf || (direct && !app);
+    if (app) {
+      hv[cnt][tid] = m1[r];
+      hid[cnt][tid] = i1[r] * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      ++cnt;
+    }
+  }
+  need = __builtin_amdgcn_readfirstlane(need);
+  // pass 2: hits of the flagged slots into the per-lane LDS list, softmax
+  // normaliser
   float ssum = 0.f;
   stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t) {
+    float e[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const bool hit = acc[r] >= tau;
+    for (int r = 0; r < 16; ++r) e[r] = __builtin_amdgcn_exp2f(fmaf(acc[r], ML_LOG2E, -mxl2));
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) ssum += e[r] + e[r + 1];
+    // the slot indices some lane needs, one at a time (a wave-uniform index
+    // into the accumulator)
+    for (uint32_t m = need; m != 0; m &= m - 1) {
+      const int r = __builtin_ctz(m);
+      const float v = acc[r];
+      const bool hit = v >= tau && ((flagged >> r) & 1u);
       const bool app = hit && cnt < HC;
       ovf = ovf || (hit && !app);
       if (app) {
-        hv[cnt][tid] = acc[r];
+        hv[cnt][tid] = v;
         hid[cnt][tid] = t * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
         ++cnt;
       }
-      ssum += __builtin_amdgcn_exp2f(fmaf(acc[r], ML_LOG2E, -mxl2));
     }
   });
   TopP<PP> top;
