@@ -77,7 +77,7 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       project_on(c, *ix, x, H, W, p.stride, qp);
       int32_t* leaf = c->buf<int32_t>("qleaf", nq);
       launch_descend(c, qp, nq, ix->dp, ix->cent.as<float>(), ix->first_child.as<int32_t>(),
-                     ix->n_children.as<int32_t>(), ix->leaf_of_node.as<int32_t>(), leaf);
+                     ix->n_children.as<int32_t>(), ix->leaf_of_node.as<int32_t>(), ix->tree.n_nodes(), leaf);
       int max_tiles = 0;
       const int chunk = leaf_scan_f32_chunk(ix->dp);
       BucketBufs b = bucket_buffers(c, nq, ix->tree.n_leaves(), chunk, &max_tiles);
@@ -166,7 +166,7 @@ void descend_unpadded(Ctx* c, const float* qproj, int64_t n, int32_t* leaf) {
   PTS_HIP(hipMemcpy2DAsync(qp, (size_t)ix.dp * 4, qproj, (size_t)ix.d * 4, (size_t)ix.d * 4, (size_t)n,
                            hipMemcpyDeviceToDevice, c->stream));
   launch_descend(c, qp, n, ix.dp, ix.cent.as<float>(), ix.first_child.as<int32_t>(), ix.n_children.as<int32_t>(),
-                 ix.leaf_of_node.as<int32_t>(), leaf);
+                 ix.leaf_of_node.as<int32_t>(), ix.tree.n_nodes(), leaf);
 }
 
 }  // namespace pts

@@ -43,7 +43,8 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   int32_t* nlow = c->buf<int32_t>("ln_nlow", 1);
   launch_zero_i32(c, nlow, 1);
   launch_descend_low_margin(c, qp, nq, ix.dp, margin, p.margin, ix.cent.as<float>(), ix.first_child.as<int32_t>(),
-                            ix.n_children.as<int32_t>(), ix.leaf_of_node.as<int32_t>(), lowq, nlow, dleaf);
+                            ix.n_children.as<int32_t>(), ix.leaf_of_node.as<int32_t>(), ix.tree.n_nodes(), lowq, nlow,
+                            dleaf);
   const int P1 = P + 1;  // proposals + the tree's leaf for low-margin queries
   int32_t* pair_leaf = c->buf<int32_t>("ln_pair_leaf", (size_t)nq * P1);
   // the fallback count (one atomic per wave) only when statistics are asked for

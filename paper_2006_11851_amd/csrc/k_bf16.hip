@@ -652,7 +652,6 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     Top8Lex top;
     top.init();
     if (q < nq) {
-#pragma unroll 2
       for (int li = 0; li < S; ++li) {
         const int64_t row = q * qs + (int64_t)li * ss;
         if (valid && valid[row] < 0) continue;

@@ -13,12 +13,12 @@
 //
 // Inference (bf16 weights, FP32 accumulation) on the matrix cores
 // (v_mfma_f32_32x32x16_bf16): A = 32 weight rows, B = 32 queries, so each
-// lane owns one query and 16 output features; weight tiles stream through
-// LDS shared by the block's 4 waves (256 queries).  Hidden layers write
-// GELU(acc + b) as bf16; the output layer never writes logits: the bias
-// initialises the accumulator and each lane folds its 16 values into a
-// running top-P (descending, ties to the lower leaf) and an online softmax
-// normaliser, merged with the lane sharing its query at the end.
+// lane owns half of one query's 32 output features of a tile (16 values);
+// weight tiles stream through LDS shared by the block's 8 waves (256
+// queries).  Both hidden layers run in one kernel and write GELU(acc + b) of
+// the second as bf16; the output layer never writes logits: two passes over
+// its weight tiles give the exact top-P leaves (descending, ties to the lower
+// leaf) and the softmax margin, the two lanes of a query merging at the end.
 #include <algorithm>
 #include <cfloat>
 #include <type_traits>
@@ -542,7 +542,6 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_hidden2(const float* __restr
                                                             const float* __restrict__ b2,
                                                             uint16_t* __restrict__ H2) {
   constexpr int KSM = KS1 > KSH ? KS1 : KSH;
-  constexpr int PERM = WTile<KSM>::PER;
   constexpr int NT = KSH / 2;  // tiles of 32 hidden units per layer
   __shared__ uint4 frag[2][KSM * WF_KK];
   __shared__ float bs[2][32];
@@ -702,7 +701,6 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_out_topk(const uint16_t* __r
                                                              const float* __restrict__ bias, int N, int kout,
                                                              int32_t* __restrict__ leaves,
                                                              float* __restrict__ margin) {
-  constexpr int PERM = WTile<KS>::PER;
   constexpr int HC = 8;  // hit-list capacity per lane
   __shared__ uint4 frag[2][KS * WF_KK];
   __shared__ float bs[2][32];

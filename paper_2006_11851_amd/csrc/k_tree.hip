@@ -2,7 +2,8 @@
 // reduced neighbourhoods).
 //
 //  * descent: greedy, nearest child centroid at every level (ties to the
-//    lowest child), one lane per query;
+//    lowest child): the first level per query, then per bucket of queries
+//    that share their level-1 node (that node's rows read once per wave);
 //  * bucketing: counting sort of the queries by leaf, then a work list of
 //    (leaf, 64-query chunk) tiles, so a leaf's members are streamed once per
 //    64 queries instead of once per query;
@@ -45,32 +46,32 @@ __device__ __forceinline__ int nearest_child(const float (&qv)[DP], int f, int n
   return f + bj;
 }
 
-// greedy descent from the root: the root's children are the same for every
-// lane (uniform loads), deeper levels follow each lane's own node
+// Descent in two kernels.  Level 1 (the root's children, the same rows for
+// every lane) per entry; entries are then bucketed by the level-1 node they
+// reached, and the rest runs per (node, 64 entries) tile with one wave per
+// tile: the node is the same for the whole wave, so its children's rows are
+// read once for all lanes through the scalar cache instead of by every lane
+// from its own node.  Levels below the second follow each lane.  The
+// arithmetic and tie rule are those of a plain per-query descent.
+//
+// Entry i is query list ? list[i] : i; with n_list, entries at or past
+// *n_list are empty.  node1[i] = the level-1 node to continue from, or -1
+// (empty entry, or the level-1 child is a leaf: its leaf is written here).
 template <int DP>
-__device__ __forceinline__ int descend_one(const float (&qv)[DP], const float* __restrict__ cent,
-                                           const int32_t* __restrict__ first_child,
-                                           const int32_t* __restrict__ n_children) {
-  const int nc0 = n_children[0];
-  if (nc0 == 0) return 0;
-  int node = nearest_child<DP>(qv, first_child[0], nc0, cent);
-  for (int depth = 1; depth < 64; ++depth) {  // bounded: a valid tree ends at a leaf long before
-    const int nc = n_children[node];
-    if (nc == 0) break;
-    node = nearest_child<DP>(qv, first_child[node], nc, cent);
+__global__ __launch_bounds__(256) void k_descend_root(const float* __restrict__ Qp, const int32_t* __restrict__ list,
+                                                      const int32_t* __restrict__ n_list, int64_t n,
+                                                      const float* __restrict__ cent,
+                                                      const int32_t* __restrict__ first_child,
+                                                      const int32_t* __restrict__ n_children,
+                                                      const int32_t* __restrict__ leaf_of_node,
+                                                      int32_t* __restrict__ node1, int32_t* __restrict__ leaf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (n_list && i >= *n_list) {
+    node1[i] = -1;
+    return;
   }
-  return node;
-}
-
-template <int DP>
-__global__ __launch_bounds__(256) void k_descend(const float* __restrict__ Qp, int64_t nq,
-                                                 const float* __restrict__ cent,
-                                                 const int32_t* __restrict__ first_child,
-                                                 const int32_t* __restrict__ n_children,
-                                                 const int32_t* __restrict__ leaf_of_node,
-                                                 int32_t* __restrict__ leaf) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+  const int64_t q = list ? list[i] : i;
   float qv[DP];
 #pragma unroll
   for (int k = 0; k < DP; k += 4) {
@@ -80,7 +81,50 @@ __global__ __launch_bounds__(256) void k_descend(const float* __restrict__ Qp, i
     qv[k + 2] = v.z;
     qv[k + 3] = v.w;
   }
-  leaf[q] = leaf_of_node[descend_one<DP>(qv, cent, first_child, n_children)];
+  const int nc0 = n_children[0];
+  const int node = nc0 > 0 ? nearest_child<DP>(qv, first_child[0], nc0, cent) : 0;
+  const bool inner = n_children[node] > 0;
+  node1[i] = inner ? node : -1;
+  if (!inner) leaf[q] = leaf_of_node[node];
+}
+
+constexpr int DS_CHUNK = 64;  // entries per tile: one wave
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_descend_tiles(const float* __restrict__ Qp, const int32_t* __restrict__ list,
+                                                       const float* __restrict__ cent,
+                                                       const int32_t* __restrict__ first_child,
+                                                       const int32_t* __restrict__ n_children,
+                                                       const int32_t* __restrict__ leaf_of_node,
+                                                       const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ order,
+                                                       const int2* __restrict__ tiles,
+                                                       const int32_t* __restrict__ ntiles,
+                                                       int32_t* __restrict__ leaf) {
+  const int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (t >= *ntiles) return;  // uniform per wave
+  const int2 tile = tiles[t];
+  const int node = tile.x;
+  const int pos = tile.y + (int)(threadIdx.x & 63);
+  if (pos >= min(off[node + 1], tile.y + DS_CHUNK)) return;
+  const int i = order[pos];
+  const int64_t q = list ? list[i] : i;
+  float qv[DP];
+#pragma unroll
+  for (int k = 0; k < DP; k += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(Qp + q * DP + k);
+    qv[k] = v.x;
+    qv[k + 1] = v.y;
+    qv[k + 2] = v.z;
+    qv[k + 3] = v.w;
+  }
+  int nd = nearest_child<DP>(qv, first_child[node], n_children[node], cent);
+  for (int depth = 2; depth < 64; ++depth) {  // bounded: a valid tree ends at a leaf long before
+    const int nc = n_children[nd];
+    if (nc == 0) break;
+    nd = nearest_child<DP>(qv, first_child[nd], nc, cent);
+  }
+  leaf[q] = leaf_of_node[nd];
 }
 
 // Descent restricted to queries whose margin is below thr: a compaction
@@ -111,48 +155,48 @@ __global__ __launch_bounds__(256) void k_compact_low(const float* __restrict__ m
   if (low) list[off + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)q;
 }
 
-template <int DP>
-__global__ __launch_bounds__(256) void k_descend_list(const float* __restrict__ Qp, const int32_t* __restrict__ list,
-                                                      const int32_t* __restrict__ n, const float* __restrict__ cent,
-                                                      const int32_t* __restrict__ first_child,
-                                                      const int32_t* __restrict__ n_children,
-                                                      const int32_t* __restrict__ leaf_of_node,
-                                                      int32_t* __restrict__ leaf) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= *n) return;
-  const int64_t q = list[t];
-  float qv[DP];
-#pragma unroll
-  for (int k = 0; k < DP; k += 4) {
-    const float4 v = *reinterpret_cast<const float4*>(Qp + q * DP + k);
-    qv[k] = v.x;
-    qv[k + 1] = v.y;
-    qv[k + 2] = v.z;
-    qv[k + 3] = v.w;
-  }
-  leaf[q] = leaf_of_node[descend_one<DP>(qv, cent, first_child, n_children)];
+static void bucket_core(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, const BucketBufs& b);
+
+// entries of (list, n_list) or 0 .. n-1
+static void descend_entries(Ctx* c, const float* Qp, const int32_t* list, const int32_t* n_list, int64_t n, int dp,
+                            const float* cent, const int32_t* first_child, const int32_t* n_children,
+                            const int32_t* leaf_of_node, int n_nodes, int32_t* leaf) {
+  int32_t* node1 = c->buf<int32_t>("ds_node1", (size_t)n);
+  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_descend_root<DPC>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream,
+                                       Qp, list, n_list, n, cent, first_child, n_children, leaf_of_node, node1, leaf));
+  check_launch("k_descend_root");
+  BucketBufs b;
+  b.counts = c->buf<int32_t>("ds_counts", (size_t)n_nodes);
+  b.off = c->buf<int32_t>("ds_off", (size_t)n_nodes + 1);
+  b.cursor = c->buf<int32_t>("ds_cursor", (size_t)n_nodes);
+  b.tile_off = c->buf<int32_t>("ds_tile_off", (size_t)n_nodes + 1);
+  b.ntiles = c->buf<int32_t>("ds_ntiles", 1);
+  b.order = c->buf<int32_t>("ds_order", (size_t)n);
+  const int64_t max_tiles = ceil_div(n, DS_CHUNK) + n_nodes;
+  b.tiles = c->buf<int2>("ds_tiles", (size_t)max_tiles);
+  bucket_core(c, node1, n, n_nodes, DS_CHUNK, b);
+  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_descend_tiles<DPC>, dim3((unsigned)ceil_div(max_tiles, 4)), dim3(256), 0,
+                                       c->stream, Qp, list, cent, first_child, n_children, leaf_of_node, b.off,
+                                       b.order, b.tiles, b.ntiles, leaf));
+  check_launch("k_descend_tiles");
 }
 
 void launch_descend_low_margin(Ctx* c, const float* Qp, int64_t nq, int dp, const float* margin, float thr,
                                const float* cent, const int32_t* first_child, const int32_t* n_children,
-                               const int32_t* leaf_of_node, int32_t* list, int32_t* n, int32_t* leaf) {
+                               const int32_t* leaf_of_node, int n_nodes, int32_t* list, int32_t* n, int32_t* leaf) {
   ProfScope ps(c, "tree_descend_low");
   if (nq == 0) return;
   hipLaunchKernelGGL(k_compact_low, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, margin, nq, thr, list, n,
                      leaf);
   check_launch("k_compact_low");
-  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_descend_list<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
-                                       c->stream, Qp, list, n, cent, first_child, n_children, leaf_of_node, leaf));
-  check_launch("k_descend_list");
+  descend_entries(c, Qp, list, n, nq, dp, cent, first_child, n_children, leaf_of_node, n_nodes, leaf);
 }
 
 void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* cent, const int32_t* first_child,
-                    const int32_t* n_children, const int32_t* leaf_of_node, int32_t* leaf) {
+                    const int32_t* n_children, const int32_t* leaf_of_node, int n_nodes, int32_t* leaf) {
   ProfScope ps(c, "tree_descend");
   if (nq == 0) return;
-  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_descend<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, Qp,
-                                       nq, cent, first_child, n_children, leaf_of_node, leaf));
-  check_launch("k_descend");
+  descend_entries(c, Qp, nullptr, nullptr, nq, dp, cent, first_child, n_children, leaf_of_node, n_nodes, leaf);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,8 +337,7 @@ __global__ __launch_bounds__(256) void k_leaf_scatter_lds(const int32_t* __restr
   }
 }
 
-void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b) {
-  ProfScope ps(c, "leaf_bucket");
+static void bucket_core(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, const BucketBufs& b) {
   hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)ceil_div(n_leaves, 256)), dim3(256), 0, c->stream, b.counts,
                      (int64_t)n_leaves);
   check_launch("k_zero_i32");
@@ -323,6 +366,11 @@ void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chu
   hipLaunchKernelGGL(k_leaf_tiles, dim3((unsigned)ceil_div(n_leaves, 256)), dim3(256), 0, c->stream, b.off, b.tile_off,
                      n_leaves, chunk, b.tiles);
   check_launch("k_leaf_tiles");
+}
+
+void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b) {
+  ProfScope ps(c, "leaf_bucket");
+  bucket_core(c, leaf, n, n_leaves, chunk, b);
 }
 
 // ---------------------------------------------------------------------------

@@ -71,11 +71,11 @@ struct BucketBufs {
   int2* tiles;        // [max_tiles] (leaf, first position in order)
 };
 void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* cent, const int32_t* first_child,
-                    const int32_t* n_children, const int32_t* leaf_of_node, int32_t* leaf);
+                    const int32_t* n_children, const int32_t* leaf_of_node, int n_nodes, int32_t* leaf);
 // descent of the queries with margin < thr only (others: leaf -1); list, n scratch
 void launch_descend_low_margin(Ctx* c, const float* Qp, int64_t nq, int dp, const float* margin, float thr,
                                const float* cent, const int32_t* first_child, const int32_t* n_children,
-                               const int32_t* leaf_of_node, int32_t* list, int32_t* n, int32_t* leaf);
+                               const int32_t* leaf_of_node, int n_nodes, int32_t* list, int32_t* n, int32_t* leaf);
 void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b);
 // order[] holds pair indices (query * P + slot); results per pair.  The
 // bucketing for it must use chunks of leaf_scan_f32_chunk(dp) pairs.
