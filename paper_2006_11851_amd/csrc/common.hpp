@@ -114,6 +114,7 @@ struct ProfEntry {
 
 struct Ctx {
   int device = 0;
+  int n_cu = 256;  // compute units of the device
   hipStream_t stream = nullptr;
   pts_alloc alloc{};
   bool has_alloc = false;

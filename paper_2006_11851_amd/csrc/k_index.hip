@@ -11,6 +11,7 @@
 //    centroid sums in 2^-30 fixed point with 64-bit integer atomics (integer
 //    addition is associative, so the centroids are bitwise reproducible),
 //    running minimum distance for k-means++ seeding.
+#include <algorithm>
 #include <climits>
 
 #include "kernels.hpp"
@@ -312,6 +313,122 @@ __global__ __launch_bounds__(256) void k_project_mfma(WinGeom g, int64_t n, int 
   }
 }
 
+// Resident-basis form for D <= 256 and an even window (w = 2, 4, 6, 8): one
+// block of 16 waves per compute unit keeps the whole basis (and mu) in LDS,
+// loaded once, and its waves walk over 32-window tiles with no further
+// barrier.  The k-steps are regrouped so that every lane loads whole pixels:
+// for 4 consecutive pixels of a window, lane (col, kq) reads pixel 4 pp + kq
+// of window col as one float4, and 4 matrix products (one per channel c)
+// take k-slice kq = that pixel's channel c, against basis rows 4 (4 pp + kq)
+// + c.  Same products and FP32 accumulation as k_project_mfma, in another
+// order.
+constexpr int PR_ROWS = 256;  // basis rows held in LDS
+constexpr int PR_WAVES = 16;
+
+template <int NKT>
+__global__ __launch_bounds__(PR_WAVES * 64) void k_project_res(WinGeom g, int64_t n, int D,
+                                                               const float* __restrict__ mu,
+                                                               const float* __restrict__ B, int dp,
+                                                               float* __restrict__ P, uint16_t* __restrict__ Qb,
+                                                               int dk) {
+  constexpr int DPAD = 16 * NKT;
+  // row stride = 4 mod 16 (in floats): the four k-rows of a step, 4 rows
+  // apart, start 16 banks apart
+  constexpr int LS = DPAD + 4;
+  __shared__ float Bs[PR_ROWS][LS];
+  __shared__ float4 mus4[PR_ROWS / 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  for (int t = tid; t < PR_ROWS * DPAD; t += PR_WAVES * 64) {
+    const int r = t / DPAD, k = t - r * DPAD;
+    Bs[r][k] = (r < D && k < dp) ? B[(int64_t)r * dp + k] : 0.f;
+  }
+  if (tid < PR_ROWS / 4) {
+    float4 m;
+    m.x = 4 * tid < D ? mu[4 * tid] : 0.f;
+    m.y = 4 * tid + 1 < D ? mu[4 * tid + 1] : 0.f;
+    m.z = 4 * tid + 2 < D ? mu[4 * tid + 2] : 0.f;
+    m.w = 4 * tid + 3 < D ? mu[4 * tid + 3] : 0.f;
+    mus4[tid] = m;
+  }
+  __syncthreads();
+  const float4* img = g.img;
+  const int ngroups = D / 16;  // groups of 4 pixels
+  const int64_t ntile = ceil_div(n, (int64_t)(16 * PM_WT));
+  for (int64_t tile = (int64_t)blockIdx.x * PR_WAVES + wave; tile < ntile; tile += (int64_t)gridDim.x * PR_WAVES) {
+    int64_t win[PM_WT];
+    int vrow[PM_WT], ucol[PM_WT];
+    bool ok[PM_WT];
+#pragma unroll
+    for (int wt = 0; wt < PM_WT; ++wt) {
+      win[wt] = tile * (16 * PM_WT) + wt * 16 + col;
+      ok[wt] = win[wt] < n;
+      const int64_t wc = ok[wt] ? win[wt] : 0;
+      const int i = (int)(wc / g.cols), j = (int)(wc - (int64_t)i * g.cols);
+      vrow[wt] = i * g.s;
+      ucol[wt] = j * g.s;
+    }
+    floatx4 acc[PM_WT][NKT];
+#pragma unroll
+    for (int wt = 0; wt < PM_WT; ++wt)
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) acc[wt][kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int pg = 0; pg < ngroups; ++pg) {
+      const int px = 4 * pg + kq;  // this lane's pixel of the group
+      const int dy = px / g.w, dx = px - dy * g.w;
+      const float4 m = mus4[px];
+      float4 xv[PM_WT];
+#pragma unroll
+      for (int wt = 0; wt < PM_WT; ++wt) {
+        int xx = ucol[wt] + dx;
+        if (g.wrap && xx >= g.W) xx -= g.W;
+        const float4 v = ok[wt] ? img[(int64_t)(vrow[wt] + dy) * g.W + xx] : m;
+        xv[wt] = make_float4(v.x - m.x, v.y - m.y, v.z - m.z, v.w - m.w);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+          const float a = Bs[4 * px + c][kt * 16 + col];
+#pragma unroll
+          for (int wt = 0; wt < PM_WT; ++wt) {
+            const float b = c == 0 ? xv[wt].x : c == 1 ? xv[wt].y : c == 2 ? xv[wt].z : xv[wt].w;
+            acc[wt][kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[wt][kt], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int wt = 0; wt < PM_WT; ++wt) {
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) {
+        const int k = kt * 16 + 4 * kq;
+        if (ok[wt] && k < dp)
+          *reinterpret_cast<float4*>(P + win[wt] * dp + k) =
+              make_float4(acc[wt][kt][0], acc[wt][kt][1], acc[wt][kt][2], acc[wt][kt][3]);
+      }
+      if (Qb && ok[wt]) {
+#pragma unroll
+        for (int kt = 0; kt < 8; ++kt) {
+          const int k = kt * 16 + 4 * kq;
+          if (k < dk) {
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (kt < NKT && k < dp) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) v[r] = -2.0f * acc[wt][kt < NKT ? kt : 0][r];
+            }
+            const __bf16 b0 = (__bf16)v[0], b1 = (__bf16)v[1], b2 = (__bf16)v[2], b3 = (__bf16)v[3];
+            uint2 pk;
+            pk.x = (uint32_t)__builtin_bit_cast(uint16_t, b0) | ((uint32_t)__builtin_bit_cast(uint16_t, b1) << 16);
+            pk.y = (uint32_t)__builtin_bit_cast(uint16_t, b2) | ((uint32_t)__builtin_bit_cast(uint16_t, b3) << 16);
+            *reinterpret_cast<uint2*>(Qb + win[wt] * dk + k) = pk;
+          }
+        }
+      }
+    }
+  }
+}
+
 void launch_project_image(Ctx* c, const float* img, int H, int W, int w, int s, bool wrap, const float* mu,
                           const float* B, int dp, float* P, uint16_t* Qb, int dk) {
   ProfScope ps(c, wrap ? "project_queries" : "project_exemplar");
@@ -321,8 +438,24 @@ void launch_project_image(Ctx* c, const float* img, int H, int W, int w, int s, 
   const int64_t rows = (H - w) / s + 1;
   const int64_t n = rows * g.cols;
   if (n == 0) return;
-  const dim3 grid((unsigned)ceil_div(n, PM_WPB));
   const int D = 4 * w * w;
+  if (D <= PR_ROWS && w % 2 == 0) {
+    const int64_t ntile = ceil_div(n, (int64_t)(16 * PM_WT));
+    const dim3 gr((unsigned)std::min<int64_t>(c->n_cu, ceil_div(ntile, PR_WAVES)));
+    switch ((dp + 15) / 16) {
+      case 1: hipLaunchKernelGGL(k_project_res<1>, gr, dim3(PR_WAVES * 64), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+      case 2: hipLaunchKernelGGL(k_project_res<2>, gr, dim3(PR_WAVES * 64), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+      case 3: hipLaunchKernelGGL(k_project_res<3>, gr, dim3(PR_WAVES * 64), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+      case 4: hipLaunchKernelGGL(k_project_res<4>, gr, dim3(PR_WAVES * 64), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+      case 5: hipLaunchKernelGGL(k_project_res<5>, gr, dim3(PR_WAVES * 64), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+      case 6: hipLaunchKernelGGL(k_project_res<6>, gr, dim3(PR_WAVES * 64), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+      case 7: hipLaunchKernelGGL(k_project_res<7>, gr, dim3(PR_WAVES * 64), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+      default: hipLaunchKernelGGL(k_project_res<8>, gr, dim3(PR_WAVES * 64), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
+    }
+    check_launch("k_project_res");
+    return;
+  }
+  const dim3 grid((unsigned)ceil_div(n, PM_WPB));
   switch ((dp + 15) / 16) {
     case 1: hipLaunchKernelGGL(k_project_mfma<1>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;
     case 2: hipLaunchKernelGGL(k_project_mfma<2>, grid, dim3(256), 0, c->stream, g, n, D, mu, B, dp, P, Qb, dk); break;

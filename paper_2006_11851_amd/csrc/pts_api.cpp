@@ -68,6 +68,7 @@ int pts_create(pts_ctx** out, int device, void* hip_stream, const pts_alloc* all
     }
     pts_ctx* c = new pts_ctx();
     c->device = device;
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (alloc_or_null) {
       c->alloc = *alloc_or_null;
