@@ -282,8 +282,8 @@ int pts_upsample2(pts_ctx* ctx, const float* x_rgbs, int H, int W, float guidanc
 /* ---- learned leaf proposal ----------------------------------------------- */
 
 /* MLP n_in -> hidden -> hidden -> n_out, GELU (exact erf; the matrix-core
- * inference of pts_mlp_propose and the learned modes evaluates it within 3e-6
- * of that, below the bf16 rounding of the activations), input scaled per
+ * inference of pts_mlp_propose and the learned modes evaluates it within
+ * 4.2e-4, below the bf16 rounding of the activations), input scaled per
  * feature by a fixed vector (default 1 / sqrt(eigenvalue) of the index).
  * Parameters packed W1 [h][n_in], b1 [h], W2 [h][h], b2 [h], W3 [n_out][h],
  * b3 [n_out], float32.  n_out must equal the index's leaf count to be used
