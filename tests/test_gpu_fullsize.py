@@ -1,0 +1,103 @@
+"""The headline workload at full size: the finest level of the 1024^2 ->
+2048^2 solve (N = 1 034 289 exemplar windows, nq = 1 045 504 queries, w = 8,
+stride 2, PCA 64, tree b32 L2), in the launch configuration the benchmark
+times.  Both search forms run over every query on the GPU; a seeded sample
+of 1024 queries is re-searched by the oracle one by one, teacher-forced on the
+GPU's FP32 projections, tree and proposals (the parts checked at small sizes
+elsewhere), in FP64:
+
+* plain FP32 tree: greedy descent plus exhaustive leaf scan, ids equal or
+  within the tie tolerance, descent near-ties excused, winner distances from
+  the images;
+* BF16 + learned (residual ranking, full-D re-rank of 8 candidates): the
+  candidate rule over the proposed leaves (plus the tree's leaf below margin
+  0.2), then the full-D re-rank."""
+import numpy as np
+import pytest
+
+from oracle import bf16 as obf16
+from oracle import parity, tree, vectors
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def headline(gpu_ctx):
+    from paper_2006_11851_amd import synth, training
+
+    wl = synth.workload("ex1024_out2048")
+    ex = wl.exemplar()
+    w, s, H = wl.w[-1], wl.stride[-1], wl.out_size
+    print("case: headline full size (N=1034289, nq=1045504)", flush=True)
+    ctx = gpu_ctx
+    ctx.set_exemplar_u8(ex, 0.5)
+    info = ctx.build_index(w, wl.pca_dims, wl.branching, wl.depth, seed=0, make_bf16=True)
+    assert info.N == 1034289 and info.n_leaves == 1024
+    init, _ = synth.row_matched_init(wl.init_seed, ex, H, H, w)
+    x = ctx.rgbs_from_u8(init, 0.5)
+    nq = ctx.nq(H, H, w, s)
+    assert nq == 1045504
+    # a briefly trained network: the parity below does not depend on its quality
+    q, lab = training.collect_pairs_sampled(ctx, x, w, s, 1, 65536, seed=1)
+    ctx.mlp_init(info.d, 256, info.n_leaves, seed=0)
+    training.train(ctx, q, lab, epochs=2, batch=4096, lr=2e-3, log_every=0)
+    sample = np.sort(np.random.default_rng(11).choice(nq, 1024, replace=False))
+    g = ctx.export_index()
+    Z = vectors.rgbs(ex, 0.5)
+    X = vectors.rgbs(init, 0.5)
+    u, v = vectors.output_grid(H, H, w, s)
+    Q = np.stack([vectors.window(X, int(u[i]), int(v[i]), w, True) for i in sample])
+    qp = ctx.project(x, s)
+    Zm = vectors.exemplar_matrix(Z, w)  # [N][D], 2 GB in FP64
+    return dict(ctx=ctx, x=x, w=w, s=s, sample=sample, g=g, Zm=Zm, Q=Q, qp=qp,
+                Qp=_np(qp)[sample].astype(np.float64),
+                Zp=_np(ctx.exemplar_projection()).astype(np.float64), t=helpers.dict_to_oracle_tree(g))
+
+
+def test_headline_tree_sampled(headline):
+    S = headline
+    nn, dist = S["ctx"].estep(S["x"], S["w"], S["s"], mode="tree")
+    got = _np(nn)[S["sample"]]
+    nn_o, _, _, gaps = tree.tree_nn(S["Qp"], S["Zp"], S["t"])
+    ok, same, _ = parity.nn_agreement(S["Qp"], S["Zp"], got, nn_o)
+    flips = (got != nn_o) & (gaps < 1e-4)
+    print(f"tree: agreement {ok:.4f} (exact {same:.4f}), descent near-ties {flips.mean():.4f}", flush=True)
+    assert ok + flips.mean() >= 0.999, (ok, same)
+    diff = S["Q"] - S["Zm"][got]
+    d_full = np.einsum("ij,ij->i", diff, diff)
+    assert np.allclose(_np(dist)[S["sample"]], np.sqrt(d_full), rtol=1e-5, atol=1e-6)
+
+
+def test_headline_learned_bf16_sampled(headline):
+    S = headline
+    ctx, sample, t, w = S["ctx"], S["sample"], S["t"], S["w"]
+    nn, dist = ctx.estep(S["x"], w, S["s"], mode="learned_bf16", residual=1, rerank_full=1, n_proposals=4,
+                         margin=0.2)
+    leaves, margin = ctx.mlp_propose(S["qp"], 4)
+    dleaf = ctx.descend(S["qp"])
+    L, M, DL = _np(leaves)[sample], _np(margin)[sample], _np(dleaf)[sample]
+    Zp, Qp = S["Zp"], S["Qp"]
+    off = obf16.residual(S["Zm"], S["g"]["mu"], Zp)  # residual ranking offsets, every window
+    cand = []
+    for i in range(len(sample)):
+        ls = list(L[i]) + ([int(DL[i])] if not (M[i] >= 0.2) and DL[i] not in L[i] else [])
+        pos, sc = [], []
+        for l in ls:
+            mem = t.leaf_members(l)
+            p_, s_ = obf16.class_candidates(Qp[i], Zp[mem], off[mem])
+            pos.append(mem[p_])
+            sc.append(s_)
+        pos, sc = np.concatenate(pos), np.concatenate(sc)
+        cand.append(pos[np.lexsort((pos, sc))[:8]])
+    nn_o, _ = obf16.rerank(S["Q"], S["Zm"], cand)
+    got = _np(nn)[sample]
+    ok, same, _ = parity.nn_agreement(S["Q"], S["Zm"], got, nn_o)
+    print(f"learned bf16: agreement {ok:.4f} (exact {same:.4f}), fallbacks {np.mean(~(M >= 0.2)):.3f}", flush=True)
+    assert ok >= 0.995, (ok, same)
+    dg = parity.sqdist_rows(S["Q"], S["Zm"], got)
+    assert np.allclose(_np(dist)[sample], np.sqrt(dg), rtol=1e-5, atol=1e-6)
