@@ -121,20 +121,26 @@ def main():
         ctx.estep(x, w, s, nn=nn, dist=dist, **kw)
         g0 = gap(x, dist)
 
-        def step():
+        # every step records its energy on the device; they are read after the
+        # timed region, so the steps are not serialised by host round trips
+        Edev = torch.zeros((max(a.steps, a.warmup), 2), dtype=torch.float32, device="cuda")
+
+        def step(i):
             ctx.estep(x, w, s, nn=nn, dist=dist, **kw)
             ctx.mstep(nn, dist, x, w, s)
-            return ctx.energy(dist)
+            ctx.energy_device(dist, Edev[i])
 
-        for _ in range(a.warmup):
-            step()
+        for i in range(a.warmup):
+            step(i)
         torch.cuda.synchronize()
         ctx.profile_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        E = [step() for _ in range(a.steps)]
+        for i in range(a.steps):
+            step(i)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        E = Edev[: a.steps].double().cpu().tolist()
         prof = ctx.profile_read()
         ctx.profile_enable(False)
         _, _, st = ctx.estep(x, w, s, nn=nn, dist=dist, stats=True, **kw)

@@ -229,6 +229,14 @@ int pts_mstep(pts_ctx* ctx, const int32_t* nn, const float* dist, float* x_rgbs,
 int pts_energy(pts_ctx* ctx, const float* dist, int64_t nq, float r, float delta, double* E_host,
                double* E2_host);
 
+/* The same energy (Eqs. 4-5), left on the device: out_device[0] = E,
+ * out_device[1] = E2 as float32, the same deterministic reduction and
+ * values as pts_energy (which rounds them to double).  out_device: caller-owned device
+ * memory of 2 floats.  Asynchronous: ordered on the context's stream and
+ * returns without waiting, so iterations that only record their energy
+ * need no host round trip.  nq == 0 writes zeros. */
+int pts_energy_device(pts_ctx* ctx, const float* dist, int64_t nq, float r, float delta, float* out_device);
+
 /* ---- multiscale solve (Methodology 2.1: coarse-to-fine) ---------------- */
 
 typedef struct pts_level_params {

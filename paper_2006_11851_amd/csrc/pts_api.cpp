@@ -277,6 +277,17 @@ int pts_energy(pts_ctx* c, const float* dist, int64_t nq, float r, float delta, 
   });
 }
 
+int pts_energy_device(pts_ctx* c, const float* dist, int64_t nq, float r, float delta, float* out) {
+  CTX_REQUIRED(c);
+  return guard(c, [&] {
+    PTS_REQUIRE(nq >= 0 && (nq == 0 || dist) && out, PTS_ERR_ARG, "energy_device: bad arguments");
+    PTS_REQUIRE(r > 0.f && r <= 2.f && delta > 0.f, PTS_ERR_ARG, "energy_device: need 0 < r <= 2, delta > 0");
+    // a fill kernel, not a memset node, so that a caller may capture the call
+    if (nq > 0) launch_energy(c, dist, nq, r, delta, out);
+    else launch_zero_i32(c, reinterpret_cast<int32_t*>(out), 2);
+  });
+}
+
 // ---------------------------------------------------------------- multiscale helpers
 
 int pts_exemplar_pyramid_level(pts_ctx* c, int levels, int level, float gw, float* out) {

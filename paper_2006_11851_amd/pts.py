@@ -211,6 +211,7 @@ SIGNATURES = {
     "pts_descend": (_I, [_P, _P, _I64, _P]),
     "pts_mstep": (_I, [_P, _P, _P, _P, _I, _I, C.POINTER(pts_mstep_params)]),
     "pts_energy": (_I, [_P, _P, _I64, _F, _F, C.POINTER(_D), C.POINTER(_D)]),
+    "pts_energy_device": (_I, [_P, _P, _I64, _F, _F, _P]),
     "pts_solve": (_I, [_P, C.POINTER(pts_solve_params), _P, _I, _I, _P, _I, _I, C.POINTER(pts_solve_trace)]),
     "pts_exemplar_pyramid_level": (_I, [_P, _I, _I, _F, _P]),
     "pts_upsample2": (_I, [_P, _P, _I, _I, _F, _P]),
@@ -474,6 +475,13 @@ class Context:
         E2 = C.c_double()
         self._ok(lib().pts_energy(self._h, _ptr(dist), dist.numel(), r, delta, C.byref(E), C.byref(E2)))
         return E.value, E2.value
+
+    def energy_device(self, dist, out=None, r=0.8, delta=1e-3):
+        """(E, E2) as a float32 device tensor [2], without waiting for it."""
+        if out is None:
+            out = self._f32((2,))
+        self._ok(lib().pts_energy_device(self._h, _ptr(dist), dist.numel(), r, delta, _ptr(out)))
+        return out
 
     # -- multiscale
     def pyramid_level(self, levels, level, guidance_weight=0.5):

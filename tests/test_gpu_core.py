@@ -68,9 +68,18 @@ def test_energy_teacher_forced(gpu_ctx):
         d = r.gamma(2.0, 0.5, size=n).astype(np.float32)
         d[: max(1, n // 50)] = 0.0  # below delta: smooth branch
         d[-1] = 5e-4
-        E, E2 = gpu_ctx.energy(torch.from_numpy(d).cuda())
+        dt = torch.from_numpy(d).cuda()
+        E, E2 = gpu_ctx.energy(dt)
         Eo, E2o = irls.energy(d.astype(np.float64))
         assert helpers.rel(E, Eo) <= 1e-5 and helpers.rel(E2, E2o) <= 1e-5, (n, E, Eo, E2, E2o)
+        # the asynchronous form leaves the same two values on the device
+        out = torch.full((3,), -1.0, device="cuda")
+        gpu_ctx.energy_device(dt, out[1:])
+        o = _np(out)
+        assert o[0] == -1.0 and o[1] == np.float32(E) and o[2] == np.float32(E2), (n, o, E, E2)
+    z = torch.full((2,), 7.0, device="cuda")
+    gpu_ctx.energy_device(torch.empty(0, device="cuda"), z)
+    assert _np(z).tolist() == [0.0, 0.0]
 
 
 def test_pca_basis_matches_oracle(c1):
