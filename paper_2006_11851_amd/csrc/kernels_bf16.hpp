@@ -29,7 +29,8 @@ void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16
 void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
                              int64_t ss, const int32_t* valid, int k, const float* Qp, int dp, const float* Zp,
                              const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out, int32_t* nn);
-// BF16 top-8 of each bucketed (query, leaf) pair over the leaf's members: pair [nq*P][8]
+// 8 class-minimum candidates (score, leaf position) of each bucketed (query,
+// leaf) pair over the leaf's members: pair [nq*P][8]
 void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb, const float* zbn, int dk,
                            const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* pair_d,
                            int32_t* pair_i);
