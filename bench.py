@@ -229,7 +229,11 @@ def roofline(ctx, head, info, nq, a, forms):
     d, h, L = info.d, 256, info.n_leaves
     dk = -(-d // 32) * 32
     K1 = -(-d // 32) * 32
-    if dom == "mlp_out_topk_mfma":
+    if dom == "mlp_propose_mfma":
+        # both hidden layers and the output layer (counted once; its two passes run it twice)
+        flops = 2.0 * (K1 * h + h * h + h * (-(-L // 32) * 32)) * nq
+        bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
+    elif dom == "mlp_out_topk_mfma":
         flops = 2.0 * h * (-(-L // 32) * 32) * nq
         bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
     elif dom == "mlp_hidden_mfma":

@@ -528,25 +528,21 @@ __device__ __forceinline__ bf16x8 gelu_bf16x8(const floatx16& acc, int c) {
   return o;
 }
 
-// Both hidden layers: H2 = GELU(GELU(bf16(Qp * scale) W1^T + b1) W2p^T + b2),
-// stored bf16 [nq][16 KSH] in the lanes' order (see above).  W1b [16 KSH][16
+// Both hidden layers: H2 = GELU(GELU(bf16(Qp * scale) W1^T + b1) W2p^T + b2)
+// of query q, left in registers in the lanes' order (see above): H2[kk] is
+// this lane's B operand of k-chunk kk of the next layer.  W1b [16 KSH][16
 // KS1] (natural order, zero-padded inputs), W2b [16 KSH][16 KSH] (columns
-// permuted).
-template <int KS1, int KSH>
-__global__ __launch_bounds__(ML_THREADS) void k_mlp_hidden2(const float* __restrict__ Qp, int ld, int64_t nq,
-                                                            const float* __restrict__ scale, int n_in,
-                                                            const uint16_t* __restrict__ W1b,
-                                                            const float* __restrict__ b1,
-                                                            const uint16_t* __restrict__ W2b,
-                                                            const float* __restrict__ b2,
-                                                            uint16_t* __restrict__ H2) {
-  constexpr int KSM = KS1 > KSH ? KS1 : KSH;
+// permuted).  frag / bs: the block's two LDS tile buffers (KSM >= KS1, KSH).
+template <int KS1, int KSH, int KSM>
+__device__ __forceinline__ void hidden_layers(const float* __restrict__ Qp, int ld, int64_t q, bool qok,
+                                              const float* __restrict__ scale, int n_in,
+                                              const uint16_t* __restrict__ W1b, const float* __restrict__ b1,
+                                              const uint16_t* __restrict__ W2b, const float* __restrict__ b2,
+                                              uint4 (*frag)[KSM * WF_KK], float (*bs)[32], int tid, int lane,
+                                              bf16x8 (&H2)[KSH]) {
+  static_assert(KSM >= KS1 && KSM >= KSH, "tile buffers too small");
   constexpr int NT = KSH / 2;  // tiles of 32 hidden units per layer
-  __shared__ uint4 frag[2][KSM * WF_KK];
-  __shared__ float bs[2][32];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
-  const int64_t q = (int64_t)blockIdx.x * ML_QPB + wave * 32 + (lane & 31);
-  const bool qok = q < nq;
+  const int h = lane >> 5;
   bf16x8 X[KS1];
 #pragma unroll
   for (int kk = 0; kk < KS1; ++kk) {
@@ -568,11 +564,9 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_hidden2(const float* __restr
     if (t < NT) {
       H1[2 * t] = gelu_bf16x8(acc, 0);
       H1[2 * t + 1] = gelu_bf16x8(acc, 1);
-    } else if (qok) {
-      uint16_t* dst = H2 + q * (16 * KSH) + 32 * (t - NT) + 8 * h;
-      const bf16x8 o0 = gelu_bf16x8(acc, 0), o1 = gelu_bf16x8(acc, 1);
-      *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(&o0);
-      *reinterpret_cast<uint4*>(dst + 16) = *reinterpret_cast<const uint4*>(&o1);
+    } else {
+      H2[2 * (t - NT)] = gelu_bf16x8(acc, 0);
+      H2[2 * (t - NT) + 1] = gelu_bf16x8(acc, 1);
     }
   };
   // tile k of the stream: layer-1 tile k (k < NT) or layer-2 tile k - NT
@@ -695,25 +689,13 @@ __device__ __forceinline__ void stream_tiles(uint4 (*frag)[KS * WF_KK], float (*
 //  Finally each lane ranks its list, and the two lanes of each query merge
 //  their top-P lists.
 template <int KS, int PP>
-__global__ __launch_bounds__(ML_THREADS) void k_mlp_out_topk(const uint16_t* __restrict__ X, int64_t nq,
-                                                             const uint16_t* __restrict__ Wb,
-                                                             const float* __restrict__ bias, int N, int kout,
-                                                             int32_t* __restrict__ leaves,
-                                                             float* __restrict__ margin) {
+__device__ __forceinline__ void out_topk(const bf16x8 (&B)[KS], int64_t q, int64_t nq,
+                                         const uint16_t* __restrict__ Wb, const float* __restrict__ bias, int N,
+                                         int kout, uint4 (*frag)[KS * WF_KK], float (*bs)[32],
+                                         float (*hv)[ML_THREADS], int (*hid)[ML_THREADS], int tid, int lane,
+                                         int32_t* __restrict__ leaves, float* __restrict__ margin) {
   constexpr int HC = 8;  // hit-list capacity per lane
-  __shared__ uint4 frag[2][KS * WF_KK];
-  __shared__ float bs[2][32];
-  __shared__ float hv[HC][ML_THREADS];
-  __shared__ int hid[HC][ML_THREADS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
-  const int64_t q = (int64_t)blockIdx.x * ML_QPB + wave * 32 + (lane & 31);
-  bf16x8 B[KS];
-#pragma unroll
-  for (int kk = 0; kk < KS; ++kk) {
-    uint4 u = make_uint4(0, 0, 0, 0);
-    if (q < nq) u = reinterpret_cast<const uint4*>(X + q * (KS * 16))[2 * kk + h];
-    B[kk] = *reinterpret_cast<const bf16x8*>(&u);
-  }
+  const int h = lane >> 5;
   const int ntiles = (N + 31) / 32;
   // pass 1
   float m1[16], m2[16];
@@ -869,6 +851,34 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_out_topk(const uint16_t* __r
   }
 }
 
+// The whole proposal network for 256 queries per block: both hidden layers,
+// then the output layer's exact top-P and margin, the hidden activations
+// never leaving the registers.  The two phases share the LDS tile buffers.
+template <int KS1, int KSH, int PP>
+__global__ __launch_bounds__(ML_THREADS) void k_mlp_propose(const float* __restrict__ Qp, int ld, int64_t nq,
+                                                            const float* __restrict__ scale, int n_in,
+                                                            const uint16_t* __restrict__ W1b,
+                                                            const float* __restrict__ b1,
+                                                            const uint16_t* __restrict__ W2b,
+                                                            const float* __restrict__ b2,
+                                                            const uint16_t* __restrict__ W3b,
+                                                            const float* __restrict__ b3, int N, int kout,
+                                                            int32_t* __restrict__ leaves,
+                                                            float* __restrict__ margin) {
+  constexpr int KSM = KS1 > KSH ? KS1 : KSH;
+  __shared__ uint4 frag[2][KSM * WF_KK];
+  __shared__ float bs[2][32];
+  __shared__ float hv[8][ML_THREADS];
+  __shared__ int hid[8][ML_THREADS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t q = (int64_t)blockIdx.x * ML_QPB + wave * 32 + (lane & 31);
+  bf16x8 H2[KSH];
+  hidden_layers<KS1, KSH, KSM>(Qp, ld, q, q < nq, scale, n_in, W1b, b1, W2b, b2, frag, bs, tid, lane, H2);
+  // the output layer streams KSH-wide tiles through the first part of each buffer
+  out_topk<KSH, PP>(H2, q, nq, W3b, b3, N, kout, reinterpret_cast<uint4(*)[KSH * WF_KK]>(&frag[0][0]), bs, hv, hid,
+                    tid, lane, leaves, margin);
+}
+
 #define PTS_MLP_KIN_SWITCH(K, ...)                                                                 \
   switch (K) {                                                                                     \
     case 32: { constexpr int KS1C = 2; __VA_ARGS__; } break;                                       \
@@ -886,33 +896,26 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_out_topk(const uint16_t* __r
     default: ::pts::fail(PTS_ERR_UNSUPPORTED, "MLP hidden width must be 32/64/128/256");           \
   }
 
-void launch_mlp_hidden2(Ctx* c, const float* Qp, int ld, int64_t nq, const float* scale, int n_in, int K1,
+void launch_mlp_propose(Ctx* c, const float* Qp, int ld, int64_t nq, const float* scale, int n_in, int K1,
                         const uint16_t* W1b, const float* b1, const uint16_t* W2b, const float* b2, int hidden,
-                        uint16_t* H2) {
-  ProfScope ps(c, "mlp_hidden_mfma");
+                        const uint16_t* W3b, const float* b3, int N, int k, int32_t* leaves, float* margin) {
+  ProfScope ps(c, "mlp_propose_mfma");
   if (nq == 0) return;
-  PTS_REQUIRE(n_in >= 1 && n_in <= K1 && n_in <= ld, PTS_ERR_ARG, "mlp_hidden2: bad input width");
-  const dim3 grid((unsigned)ceil_div(nq, ML_QPB));
-  PTS_MLP_KIN_SWITCH(K1, PTS_MLP_HID_SWITCH(hidden, hipLaunchKernelGGL((k_mlp_hidden2<KS1C, KSC>), grid,
-                                                                       dim3(ML_THREADS), 0, c->stream, Qp, ld, nq,
-                                                                       scale, n_in, W1b, b1, W2b, b2, H2)));
-  check_launch("k_mlp_hidden2");
-}
-
-void launch_mlp_out_topk(Ctx* c, const uint16_t* X, int64_t nq, int K, const uint16_t* Wb, const float* bias, int N,
-                         int k, int32_t* leaves, float* margin) {
-  ProfScope ps(c, "mlp_out_topk_mfma");
-  if (nq == 0) return;
+  PTS_REQUIRE(n_in >= 1 && n_in <= K1 && n_in <= ld, PTS_ERR_ARG, "mlp_propose: bad input width");
   PTS_REQUIRE(k >= 1 && k <= ML_P && k <= N, PTS_ERR_ARG, "proposals must be 1..8 and at most n_out");
   const dim3 grid((unsigned)ceil_div(nq, ML_QPB));
   if (k <= 4) {
-    PTS_MLP_HID_SWITCH(K, hipLaunchKernelGGL((k_mlp_out_topk<KSC, 4>), grid, dim3(ML_THREADS), 0, c->stream, X, nq,
-                                             Wb, bias, N, k, leaves, margin));
+    PTS_MLP_KIN_SWITCH(K1, PTS_MLP_HID_SWITCH(hidden, hipLaunchKernelGGL((k_mlp_propose<KS1C, KSC, 4>), grid,
+                                                                         dim3(ML_THREADS), 0, c->stream, Qp, ld, nq,
+                                                                         scale, n_in, W1b, b1, W2b, b2, W3b, b3, N,
+                                                                         k, leaves, margin)));
   } else {
-    PTS_MLP_HID_SWITCH(K, hipLaunchKernelGGL((k_mlp_out_topk<KSC, 8>), grid, dim3(ML_THREADS), 0, c->stream, X, nq,
-                                             Wb, bias, N, k, leaves, margin));
+    PTS_MLP_KIN_SWITCH(K1, PTS_MLP_HID_SWITCH(hidden, hipLaunchKernelGGL((k_mlp_propose<KS1C, KSC, 8>), grid,
+                                                                         dim3(ML_THREADS), 0, c->stream, Qp, ld, nq,
+                                                                         scale, n_in, W1b, b1, W2b, b2, W3b, b3, N,
+                                                                         k, leaves, margin)));
   }
-  check_launch("k_mlp_out_topk");
+  check_launch("k_mlp_propose");
 }
 
 }  // namespace pts

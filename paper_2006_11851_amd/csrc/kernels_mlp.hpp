@@ -23,16 +23,13 @@ void launch_pad_f32(Ctx* c, const float* src, int n, int n_p, float fill, float*
 // bf16 copy, zero padded; perm: columns in the matrix-core lane order
 void launch_to_bf16_pad(Ctx* c, const float* src, int rows, int cols, int rows_p, int cols_p, bool perm,
                         uint16_t* dst);
-// H2 [nq][hidden] bf16 (lane order) = both hidden layers applied to
-// bf16(Qp * scale); W1b [hidden][K1] natural order, W2b [hidden][hidden] permuted
-void launch_mlp_hidden2(Ctx* c, const float* Qp, int ld, int64_t nq, const float* scale, int n_in, int K1,
-                        const uint16_t* W1b, const float* b1, const uint16_t* W2b, const float* b2, int hidden,
-                        uint16_t* H2);
 // leaves [nq][k] (descending logit, ties to the lower leaf) and margin p1 - p2
-// from H2 [nq][K] (lane order), W3b [round_up(N, 32)][K] (permuted, zero
-// rows past N) and the bias padded to round_up(N, 32) with -FLT_MAX
-void launch_mlp_out_topk(Ctx* c, const uint16_t* X, int64_t nq, int K, const uint16_t* Wb, const float* bias, int N,
-                         int k, int32_t* leaves, float* margin);
+// of the network applied to bf16(Qp * scale): W1b [hidden][K1] natural order,
+// W2b [hidden][hidden] and W3b [round_up(N, 32)][hidden] with columns in the
+// lane order (zero rows past N), b3 padded to round_up(N, 32) with -FLT_MAX
+void launch_mlp_propose(Ctx* c, const float* Qp, int ld, int64_t nq, const float* scale, int n_in, int K1,
+                        const uint16_t* W1b, const float* b1, const uint16_t* W2b, const float* b2, int hidden,
+                        const uint16_t* W3b, const float* b3, int N, int k, int32_t* leaves, float* margin);
 
 // mlp.cpp: proposals for projected queries (rows of stride ld) with the context's MLP
 void mlp_propose_rows(Ctx* c, const float* Qp, int ld, int64_t n, int k, int32_t* leaves, float* margin);

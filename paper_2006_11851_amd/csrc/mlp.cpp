@@ -129,10 +129,9 @@ void mlp_propose_rows(Ctx* c, const float* Qp, int ld, int64_t n, int k, int32_t
   const Layout L = layout(m);
   const float* P = m.params.as<float>();
   const int K1 = k_in(m);
-  uint16_t* h2 = c->buf<uint16_t>("mlp_h2b", (size_t)n * m.h);
-  launch_mlp_hidden2(c, Qp, ld, n, m.in_scale.as<float>(), m.n_in, K1, bc.w1b.as<uint16_t>(), P + L.b1,
-                     bc.w2b.as<uint16_t>(), P + L.b2, m.h, h2);
-  launch_mlp_out_topk(c, h2, n, m.h, bc.w3b.as<uint16_t>(), bc.b3p.as<float>(), m.n_out, k, leaves, margin);
+  launch_mlp_propose(c, Qp, ld, n, m.in_scale.as<float>(), m.n_in, K1, bc.w1b.as<uint16_t>(), P + L.b1,
+                     bc.w2b.as<uint16_t>(), P + L.b2, m.h, bc.w3b.as<uint16_t>(), bc.b3p.as<float>(), m.n_out, k,
+                     leaves, margin);
 }
 
 }  // namespace pts
