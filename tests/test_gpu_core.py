@@ -242,9 +242,17 @@ def test_ragged_and_small_shapes(gpu_ctx):
         ok, _, _ = parity.nn_agreement(Q, Zm, _np(nn), exact.exact_nn(Q, Zm)[0])
         assert ok == 1.0
         d = min(16, 4 * w * w)
-        gpu_ctx.build_index(w, d, 2, 2, seed=1)
+        info = gpu_ctx.build_index(w, d, 2, 2, seed=1)
         nn2, _ = gpu_ctx.estep(x, w, s, mode="tree")
         assert np.all((_np(nn2) >= 0) & (_np(nn2) < Zm.shape[0]))
+        # the learned BF16 form on the same ragged shapes (untrained network,
+        # tree leaf added below the margin): valid ids, full-D distances
+        gpu_ctx.mlp_init(info.d, 32, info.n_leaves, seed=2)
+        P = min(4, info.n_leaves)
+        nn3, d3 = gpu_ctx.estep(x, w, s, mode="learned_bf16", n_proposals=P, rerank_full=1, residual=1)
+        g3 = _np(nn3)
+        assert np.all((g3 >= 0) & (g3 < Zm.shape[0]))
+        assert np.allclose(_np(d3), np.sqrt(parity.sqdist_rows(Q, Zm, g3)), rtol=1e-5, atol=1e-6)
 
 
 def test_error_codes(gpu_ctx):
