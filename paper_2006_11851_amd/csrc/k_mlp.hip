@@ -674,6 +674,10 @@ __device__ __forceinline__ void stream_tiles(uint4 (*frag)[KS * WF_KK], float (*
   }
 }
 
+template <int PP>
+__device__ __forceinline__ void topp_finish(const TopP<PP>& top, float s, int lane, int64_t q, int64_t nq, int kout,
+                                            bool write, int32_t* __restrict__ leaves, float* __restrict__ margin);
+
 // Output layer, exact top-P leaves and the softmax margin p1 - p2, in two
 // passes over the weight tiles (the logits are never stored).
 //  Pass 1: per value slot (lane, register) the largest and second-largest
@@ -813,6 +817,15 @@ __device__ __forceinline__ void out_topk(const bf16x8 (&B)[KS], int64_t q, int64
   if (!ovf)
     for (int c = 0; c < cnt; ++c) top.insert(hv[c][tid], hid[c][tid]);
   const float s = ssum + __shfl_xor(ssum, 32, 64);  // both halves use the same m
+  topp_finish<PP>(top, s, lane, q, nq, kout, true, leaves, margin);
+}
+
+// The two lanes of query q merge their top-P lists; lane h = 0 writes the
+// kout leaves and the margin p1 - p2 = (1 - exp(l2 - l1)) / s, with s =
+// sum_j exp(l_j - l1) over all leaves (l1 the largest logit), if `write`.
+template <int PP>
+__device__ __forceinline__ void topp_finish(const TopP<PP>& top, float s, int lane, int64_t q, int64_t nq, int kout,
+                                            bool write, int32_t* __restrict__ leaves, float* __restrict__ margin) {
   float ov[PP];
   int oi[PP];
 #pragma unroll
@@ -820,7 +833,7 @@ __device__ __forceinline__ void out_topk(const bf16x8 (&B)[KS], int64_t q, int64
     ov[t] = __shfl_xor(top.v[t], 32, 64);
     oi[t] = __shfl_xor(top.i[t], 32, 64);
   }
-  if (lane < 32 && q < nq) {
+  if (write && lane < 32 && q < nq) {
     int a = 0, b = 0;
     float best[2] = {-FLT_MAX, -FLT_MAX};
 #pragma unroll
@@ -851,10 +864,133 @@ __device__ __forceinline__ void out_topk(const bf16x8 (&B)[KS], int64_t q, int64
   }
 }
 
+// Output layer in one pass over the weight tiles.  Per value slot (lane,
+// register) the three largest logits m1 >= m2 >= m3, the tiles of the first
+// two, and sum_j exp(l_j - m1) over the slot (rescaled whenever m1 grows),
+// about 12 operations and one exponential per logit.  Then tau = the P-th
+// largest of the query's 64 values m1, m2 (as in the two-pass form, a lower
+// bound of the P-th largest logit); a slot whose m3 is below tau holds no
+// logit >= tau beyond m1 and m2, whose leaves are known, so the top-P is
+// exact unless some slot has m3 >= tau (three or more top logits in one
+// slot, or ties).  Returns that case - the caller hands the query to the
+// two-pass form - and writes nothing for it; otherwise writes the top-P and
+// the margin.
+template <int KS, int PP>
+__device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q, int64_t nq,
+                                               const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
+                                               int N, int kout, uint4 (*frag)[KS * WF_KK], float (*bs)[32],
+                                               float (*hv)[ML_THREADS], int (*hid)[ML_THREADS], int tid, int lane,
+                                               int32_t* __restrict__ leaves, float* __restrict__ margin) {
+  constexpr int HC = 8;  // hit-list capacity per lane
+  const int h = lane >> 5;
+  const int ntiles = (N + 31) / 32;
+  float m1[16], m2[16], m3[16], sm[16];
+  int i1[16], i2[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    m1[r] = -FLT_MAX;
+    m2[r] = -FLT_MAX;
+    m3[r] = -FLT_MAX;
+    sm[r] = 0.f;
+    i1[r] = 0;
+    i2[r] = 0;
+  }
+  stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float x = acc[r];
+      const bool g1 = x > m1[r], g2 = x > m2[r];
+      // exp(-|x - m1|): the new term, or the factor rescaling the old sum
+      const float e = __builtin_amdgcn_exp2f(-fabsf(x - m1[r]) * ML_LOG2E);
+      sm[r] = g1 ? fmaf(sm[r], e, 1.0f) : sm[r] + e;
+      m3[r] = __builtin_amdgcn_fmed3f(x, m2[r], m3[r]);  // m3 <= m2: max(m3, min(m2, x))
+      m2[r] = __builtin_amdgcn_fmed3f(x, m1[r], m2[r]);
+      i2[r] = g1 ? i1[r] : (g2 ? t : i2[r]);
+      i1[r] = g1 ? t : i1[r];
+      m1[r] = g1 ? x : m1[r];
+    }
+  });
+  // the largest logit M and s = sum_j exp(l_j - M) over both halves
+  float mx = m1[0];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) mx = fmaxf(mx, m1[r]);
+  mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+  float ssum = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) ssum = fmaf(sm[r], __builtin_amdgcn_exp2f((m1[r] - mx) * ML_LOG2E), ssum);
+  ssum += __shfl_xor(ssum, 32, 64);
+  // tau: the P-th largest of the query's 64 slot values m1, m2
+  float tau;
+  {
+    float v[ML_P];
+#pragma unroll
+    for (int u = 0; u < ML_P; ++u) v[u] = -FLT_MAX;
+    auto push = [&](float x) {
+#pragma unroll
+      for (int u = 0; u < ML_P; ++u) {
+        const float hi = fmaxf(v[u], x);
+        x = fminf(v[u], x);
+        v[u] = hi;
+      }
+    };
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      push(m1[r]);
+      push(m2[r]);
+    }
+    float ov[ML_P];
+#pragma unroll
+    for (int u = 0; u < ML_P; ++u) ov[u] = __shfl_xor(v[u], 32, 64);
+#pragma unroll
+    for (int u = 0; u < ML_P; ++u) push(ov[u]);
+    float tk = v[0];
+#pragma unroll
+    for (int u = 1; u < ML_P; ++u)
+      if (u < kout) tk = v[u];
+    tau = tk;
+  }
+  // the hits m1, m2 >= tau with their leaves; a slot with m3 >= tau (or a
+  // full list) leaves the query to the two-pass form
+  int cnt = 0;
+  bool fallback = false;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int off = 8 * (r >> 2) + 4 * h + (r & 3);
+    fallback = fallback || (m3[r] >= tau);
+    if (m1[r] >= tau) {
+      if (cnt < HC) {
+        hv[cnt][tid] = m1[r];
+        hid[cnt][tid] = i1[r] * 32 + off;
+        ++cnt;
+      } else {
+        fallback = true;
+      }
+    }
+    if (m2[r] >= tau) {
+      if (cnt < HC) {
+        hv[cnt][tid] = m2[r];
+        hid[cnt][tid] = i2[r] * 32 + off;
+        ++cnt;
+      } else {
+        fallback = true;
+      }
+    }
+  }
+  fallback = __shfl_xor(fallback ? 1 : 0, 32, 64) != 0 || fallback;
+  TopP<PP> top;
+  top.init();
+  for (int c = 0; c < cnt; ++c) top.insert(hv[c][tid], hid[c][tid]);
+  topp_finish<PP>(top, ssum, lane, q, nq, kout, !fallback, leaves, margin);
+  return fallback;
+}
+
 // The whole proposal network for 256 queries per block: both hidden layers,
 // then the output layer's exact top-P and margin, the hidden activations
 // never leaving the registers.  The two phases share the LDS tile buffers.
-template <int KS1, int KSH, int PP>
+// ONE: the one-pass output layer; queries it cannot settle exactly are
+// appended to (list, n_list).  Otherwise the two-pass form, over the queries
+// of (list, n_list) when list is given, else over 0 .. nq - 1.
+template <int KS1, int KSH, int PP, bool ONE>
 __global__ __launch_bounds__(ML_THREADS) void k_mlp_propose(const float* __restrict__ Qp, int ld, int64_t nq,
                                                             const float* __restrict__ scale, int n_in,
                                                             const uint16_t* __restrict__ W1b,
@@ -863,6 +999,7 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_propose(const float* __restr
                                                             const float* __restrict__ b2,
                                                             const uint16_t* __restrict__ W3b,
                                                             const float* __restrict__ b3, int N, int kout,
+                                                            int32_t* __restrict__ list, int32_t* __restrict__ n_list,
                                                             int32_t* __restrict__ leaves,
                                                             float* __restrict__ margin) {
   constexpr int KSM = KS1 > KSH ? KS1 : KSH;
@@ -871,12 +1008,23 @@ __global__ __launch_bounds__(ML_THREADS) void k_mlp_propose(const float* __restr
   __shared__ float hv[8][ML_THREADS];
   __shared__ int hid[8][ML_THREADS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t q = (int64_t)blockIdx.x * ML_QPB + wave * 32 + (lane & 31);
+  const int64_t idx = (int64_t)blockIdx.x * ML_QPB + wave * 32 + (lane & 31);
+  int64_t q = idx;
+  if (!ONE && list) {
+    const int64_t n = *n_list;
+    if ((int64_t)blockIdx.x * ML_QPB >= n) return;  // uniform per block
+    q = idx < n ? list[idx] : nq;
+  }
   bf16x8 H2[KSH];
   hidden_layers<KS1, KSH, KSM>(Qp, ld, q, q < nq, scale, n_in, W1b, b1, W2b, b2, frag, bs, tid, lane, H2);
   // the output layer streams KSH-wide tiles through the first part of each buffer
-  out_topk<KSH, PP>(H2, q, nq, W3b, b3, N, kout, reinterpret_cast<uint4(*)[KSH * WF_KK]>(&frag[0][0]), bs, hv, hid,
-                    tid, lane, leaves, margin);
+  auto fo = reinterpret_cast<uint4(*)[KSH * WF_KK]>(&frag[0][0]);
+  if constexpr (ONE) {
+    const bool fb = out_topk_1pass<KSH, PP>(H2, q, nq, W3b, b3, N, kout, fo, bs, hv, hid, tid, lane, leaves, margin);
+    if (fb && lane < 32 && q < nq) list[atomicAdd(n_list, 1)] = (int32_t)q;
+  } else {
+    out_topk<KSH, PP>(H2, q, nq, W3b, b3, N, kout, fo, bs, hv, hid, tid, lane, leaves, margin);
+  }
 }
 
 #define PTS_MLP_KIN_SWITCH(K, ...)                                                                 \
@@ -903,18 +1051,25 @@ void launch_mlp_propose(Ctx* c, const float* Qp, int ld, int64_t nq, const float
   if (nq == 0) return;
   PTS_REQUIRE(n_in >= 1 && n_in <= K1 && n_in <= ld, PTS_ERR_ARG, "mlp_propose: bad input width");
   PTS_REQUIRE(k >= 1 && k <= ML_P && k <= N, PTS_ERR_ARG, "proposals must be 1..8 and at most n_out");
+  PTS_REQUIRE(nq < INT_MAX, PTS_ERR_UNSUPPORTED, "mlp_propose: too many queries");
+  // one pass for every query, then the two-pass form for those it could not settle
+  int32_t* list = c->buf<int32_t>("mlp_fix_list", (size_t)nq);
+  int32_t* n_list = c->buf<int32_t>("mlp_fix_n", 1);
+  launch_zero_i32(c, n_list, 1);
   const dim3 grid((unsigned)ceil_div(nq, ML_QPB));
+#define PTS_MLP_PROPOSE(PPV, ONEV)                                                                                   \
+  PTS_MLP_KIN_SWITCH(K1, PTS_MLP_HID_SWITCH(hidden, hipLaunchKernelGGL((k_mlp_propose<KS1C, KSC, PPV, ONEV>), grid,   \
+                                                                       dim3(ML_THREADS), 0, c->stream, Qp, ld, nq,    \
+                                                                       scale, n_in, W1b, b1, W2b, b2, W3b, b3, N, k,  \
+                                                                       list, n_list, leaves, margin)))
   if (k <= 4) {
-    PTS_MLP_KIN_SWITCH(K1, PTS_MLP_HID_SWITCH(hidden, hipLaunchKernelGGL((k_mlp_propose<KS1C, KSC, 4>), grid,
-                                                                         dim3(ML_THREADS), 0, c->stream, Qp, ld, nq,
-                                                                         scale, n_in, W1b, b1, W2b, b2, W3b, b3, N,
-                                                                         k, leaves, margin)));
+    PTS_MLP_PROPOSE(4, true);
+    PTS_MLP_PROPOSE(4, false);
   } else {
-    PTS_MLP_KIN_SWITCH(K1, PTS_MLP_HID_SWITCH(hidden, hipLaunchKernelGGL((k_mlp_propose<KS1C, KSC, 8>), grid,
-                                                                         dim3(ML_THREADS), 0, c->stream, Qp, ld, nq,
-                                                                         scale, n_in, W1b, b1, W2b, b2, W3b, b3, N,
-                                                                         k, leaves, margin)));
+    PTS_MLP_PROPOSE(8, true);
+    PTS_MLP_PROPOSE(8, false);
   }
+#undef PTS_MLP_PROPOSE
   check_launch("k_mlp_propose");
 }
 

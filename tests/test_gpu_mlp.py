@@ -79,6 +79,37 @@ def test_mlp_forward_and_matrix_core_proposals(mlp_setup):
     assert np.abs(_np(margin) - m_o).max() <= 0.03
 
 
+def test_proposals_with_tied_and_clustered_logits(mlp_setup):
+    """Degenerate output layers.  All logits equal (W3 = 0, b3 = 0): every
+    slot holds three or more logits >= tau, so every query goes to the
+    two-pass form, whose hit lists overflow into its third pass; the top-4 is
+    leaves 0..3 (ties to the lower leaf) and the margin 0.  Then three top
+    logits in one value slot (leaves 5, 37, 69 share one: equal modulo 32),
+    which the one-pass form cannot settle either, and a spread top-4 it can."""
+    S = mlp_setup
+    ctx, (n_in, h, n_out) = S["ctx"], S["dims"]
+    theta = S["theta"]
+    n3 = n_out * h + n_out  # W3 [n_out][h] and b3 [n_out] close the packed vector
+    try:
+        th = theta.copy()
+        th[-n3:] = 0.0
+        ctx.mlp_set_weights(th.astype(np.float32))
+        leaves, margin = ctx.mlp_propose(S["qt"], 4)
+        assert (_np(leaves) == np.arange(4)[None, :]).all()
+        assert np.abs(_np(margin)).max() <= 1e-6
+        for tops in ([5, 37, 69, 101], [3, 200, 517, 1000]):
+            b3 = np.zeros(n_out)
+            b3[tops] = [9.0, 8.0, 7.0, 6.0]
+            th[-n_out:] = b3
+            ctx.mlp_set_weights(th.astype(np.float32))
+            leaves, margin = ctx.mlp_propose(S["qt"], 4)
+            assert (_np(leaves) == np.asarray(tops)[None, :]).all(), tops
+            p = np.exp(b3 - 9.0) / np.exp(b3 - 9.0).sum()
+            assert np.allclose(_np(margin), p[tops[0]] - p[tops[1]], rtol=1e-4), tops
+    finally:
+        ctx.mlp_set_weights(theta.astype(np.float32))
+
+
 def test_adam_step_matches_oracle(mlp_setup):
     import torch
 
