@@ -21,6 +21,7 @@
 // leaf) and the softmax margin, the two lanes of a query merging at the end.
 #include <algorithm>
 #include <cfloat>
+#include <utility>
 #include <type_traits>
 #include <climits>
 
@@ -473,17 +474,23 @@ __device__ __forceinline__ TileRegs wt_load(const uint16_t* __restrict__ Wb, con
 constexpr int WF_HALF = 33, WF_KK = 2 * WF_HALF;
 
 // registers -> LDS in fragment order
+// (free of branches when every thread has its chunks - KS = 8, 16 - so that
+// a step of the tile stream stays one block; every thread writes its bias,
+// the 16 threads of a row the same value)
 template <int KS>
 __device__ __forceinline__ void wt_store(const TileRegs& T, uint4* frag, float* bs, int tid) {
-#pragma unroll
-  for (int u = 0; u < WTile<KS>::PER; ++u) {
-    const int cidx = tid + u * ML_THREADS;
-    if (cidx < WTile<KS>::NCH) {
-      const int row = cidx / WTile<KS>::CH, ch = cidx - row * WTile<KS>::CH;
-      frag[(ch >> 1) * WF_KK + (ch & 1) * WF_HALF + row] = u ? T.c1 : T.c0;
-    }
+  constexpr int NCH = WTile<KS>::NCH;
+  auto put = [&](int cidx, const uint4& c) {
+    const int row = cidx / WTile<KS>::CH, ch = cidx - row * WTile<KS>::CH;
+    frag[(ch >> 1) * WF_KK + (ch & 1) * WF_HALF + row] = c;
+  };
+  if constexpr (ML_THREADS <= NCH) put(tid, T.c0);
+  else if (tid < NCH) put(tid, T.c0);
+  if constexpr (WTile<KS>::PER > 1) {
+    if constexpr (2 * ML_THREADS <= NCH) put(tid + ML_THREADS, T.c1);
+    else if (tid + ML_THREADS < NCH) put(tid + ML_THREADS, T.c1);
   }
-  if (tid < 32) bs[tid] = T.b;
+  bs[tid & 31] = T.b;
 }
 
 // acc = bias (of the lane's 16 rows) + sum_kk A[kk] B[kk]; the A fragments
@@ -519,6 +526,104 @@ __device__ __forceinline__ floatx16 tile_mfma(const uint4* frag, const float* bs
     if (kk + AH < KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
   }
   return acc;
+}
+
+// the order of tile_mfma_epi: one product, one LDS read, the vector work of
+// the slots that follow product kk (vector and transcendental instructions)
+template <int KS, int AH, int VPS, int kk>
+__device__ __forceinline__ void epi_order_step() {
+  constexpr int ns = (16 * (kk + 1)) / KS - (16 * kk) / KS;
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+  if constexpr (kk + AH < KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  if constexpr (ns > 0) __builtin_amdgcn_sched_group_barrier(0x402, VPS * ns, 0);
+}
+template <int KS, int AH, int VPS, int... KK>
+__device__ __forceinline__ void epi_order(std::integer_sequence<int, KK...>) {
+  (epi_order_step<KS, AH, VPS, KK>(), ...);
+}
+
+// tile_mfma with a per-slot epilogue of the previous tile woven in: after
+// product kk, slots (16 kk / KS) .. (16 (kk + 1) / KS) - 1 of the previous
+// accumulator, about VPS vector instructions each.  A lone wave issues
+// dependent vector work at about half the SIMD's rate, so the epilogue of a
+// wave is cheapest when the other wave of the SIMD is doing the same work at
+// the same time, its own matrix products running underneath.
+template <int KS, int VPS, class SlotFn>
+__device__ __forceinline__ floatx16 tile_mfma_epi(const uint4* frag, const float* bs, const bf16x8 (&B)[KS], int lane,
+                                                  SlotFn&& slot) {
+  constexpr int AH = KS < 4 ? KS : 4;
+  const uint4* fp = frag + (lane >> 5) * WF_HALF + (lane & 31);
+  uint4 a[AH];
+#pragma unroll
+  for (int j = 0; j < AH; ++j) a[j] = fp[j * WF_KK];
+  floatx16 acc;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float4 b4 = *reinterpret_cast<const float4*>(&bs[8 * g + 4 * (lane >> 5)]);
+    acc[4 * g + 0] = b4.x;
+    acc[4 * g + 1] = b4.y;
+    acc[4 * g + 2] = b4.z;
+    acc[4 * g + 3] = b4.w;
+  }
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(&a[kk % AH]), B[kk], acc, 0, 0, 0);
+    if (kk + AH < KS) a[kk % AH] = fp[(kk + AH) * WF_KK];
+#pragma unroll
+    for (int r = (16 * kk) / KS; r < (16 * (kk + 1)) / KS; ++r) slot(r);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x100, AH + 4, 0);
+  epi_order<KS, AH, VPS>(std::make_integer_sequence<int, KS>{});
+  return acc;
+}
+
+// stream_tiles for an epilogue made of 16 independent per-slot updates
+// (slot(acc, t, r) for register r of tile t, free of branches): every wave
+// runs the same schedule, and the steady-state step - loads of tile t + 2,
+// the products of tile t woven with the epilogue of tile t - 1, the store of
+// tile t + 1, barrier - is one straight block.  The first tile's products
+// and the last tile's epilogue are peeled.  Past the end the loads re-read
+// the last tile and the store writes it into the buffer no one reads again.
+template <int KS, int VPS, class Slot>
+__device__ __forceinline__ void stream_tiles_slots(uint4 (*frag)[KS * WF_KK], float (*bs)[32],
+                                                   const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
+                                                   int ntiles, const bf16x8 (&B)[KS], int tid, int lane, Slot&& slot) {
+  const int last = ntiles - 1;
+  TileRegs T0 = wt_load<KS>(Wb, bias, 0, tid);
+  TileRegs T1 = wt_load<KS>(Wb, bias, min(1, last) * 32, tid);
+  lds_barrier();  // earlier readers of the buffers are done
+  wt_store<KS>(T0, frag[0], bs[0], tid);
+  lds_barrier();
+  floatx16 acc[2];
+  T0 = wt_load<KS>(Wb, bias, min(2, last) * 32, tid);
+  acc[0] = tile_mfma<KS>(frag[0], bs[0], B, lane);
+  wt_store<KS>(T1, frag[1], bs[1], tid);
+  lds_barrier();
+  auto step = [&](auto U, int tt) {
+    constexpr int u = decltype(U)::value;
+    const int tn = min(tt + 2, last) * 32;
+    if constexpr (u == 0) T0 = wt_load<KS>(Wb, bias, tn, tid);
+    else T1 = wt_load<KS>(Wb, bias, tn, tid);
+    const floatx16& prev = acc[u ^ 1];
+    acc[u] = tile_mfma_epi<KS, VPS>(frag[u], bs[u], B, lane, [&](int r) { slot(prev, tt - 1, r); });
+    if constexpr (u == 0) wt_store<KS>(T1, frag[1], bs[1], tid);
+    else wt_store<KS>(T0, frag[0], bs[0], tid);
+    lds_barrier();
+    __builtin_amdgcn_sched_barrier(0);  // each step is scheduled on its own
+  };
+  int t = 1;
+  for (; t + 1 <= last; t += 2) {
+    step(std::integral_constant<int, 1>(), t);
+    step(std::integral_constant<int, 0>(), t + 1);
+  }
+  if (t <= last) step(std::integral_constant<int, 1>(), t);
+  if (last & 1) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) slot(acc[1], last, r);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) slot(acc[0], last, r);
+  }
 }
 
 __device__ __forceinline__ bf16x8 gelu_bf16x8(const floatx16& acc, int c) {
@@ -710,17 +815,14 @@ __device__ __forceinline__ void out_topk(const bf16x8 (&B)[KS], int64_t q, int64
     m2[r] = -FLT_MAX;
     i1[r] = 0;
   }
-  stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      // with m2 <= m1, max(m2, min(m1, x)) is the median of the three; a
-      // compare-select for the maximum (fmaxf would first quieten its
-      // operands, one more instruction each)
-      const bool gt = acc[r] > m1[r];
-      m2[r] = __builtin_amdgcn_fmed3f(acc[r], m1[r], m2[r]);
-      m1[r] = gt ? acc[r] : m1[r];
-      i1[r] = gt ? t : i1[r];
-    }
+  stream_tiles_slots<KS, 4>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t, int r) {
+    // with m2 <= m1, max(m2, min(m1, x)) is the median of the three; a
+    // compare-select for the maximum (fmaxf would first quieten its
+    // operands, one more instruction each)
+    const bool gt = acc[r] > m1[r];
+    m2[r] = __builtin_amdgcn_fmed3f(acc[r], m1[r], m2[r]);
+    m1[r] = gt ? acc[r] : m1[r];
+    i1[r] = gt ? t : i1[r];
   });
   // tau and m: the P-th largest and the largest of the query's 64 slot values
   // (values only: a max/min exchange network keeps v sorted descending)
@@ -885,30 +987,27 @@ __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q,
   const int h = lane >> 5;
   const int ntiles = (N + 31) / 32;
   float m1[16], m2[16], m3[16], sm[16];
-  int i1[16], i2[16];
+  uint32_t i12[16];  // tile of m1 in the low half, of m2 in the high half
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     m1[r] = -FLT_MAX;
     m2[r] = -FLT_MAX;
     m3[r] = -FLT_MAX;
     sm[r] = 0.f;
-    i1[r] = 0;
-    i2[r] = 0;
+    i12[r] = 0;
   }
-  stream_tiles<KS>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float x = acc[r];
-      const bool g1 = x > m1[r], g2 = x > m2[r];
-      // exp(-|x - m1|): the new term, or the factor rescaling the old sum
-      const float e = __builtin_amdgcn_exp2f(-fabsf(x - m1[r]) * ML_LOG2E);
-      sm[r] = g1 ? fmaf(sm[r], e, 1.0f) : sm[r] + e;
-      m3[r] = __builtin_amdgcn_fmed3f(x, m2[r], m3[r]);  // m3 <= m2: max(m3, min(m2, x))
-      m2[r] = __builtin_amdgcn_fmed3f(x, m1[r], m2[r]);
-      i2[r] = g1 ? i1[r] : (g2 ? t : i2[r]);
-      i1[r] = g1 ? t : i1[r];
-      m1[r] = g1 ? x : m1[r];
-    }
+  stream_tiles_slots<KS, 14>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t, int r) {
+    const float x = acc[r];
+    const bool g1 = x > m1[r], g2 = x > m2[r];
+    // exp(-|x - m1|): the new term, or the factor rescaling the old sum
+    const float e = __builtin_amdgcn_exp2f(-fabsf(x - m1[r]) * ML_LOG2E);
+    sm[r] = g1 ? fmaf(sm[r], e, 1.0f) : sm[r] + e;
+    m3[r] = __builtin_amdgcn_fmed3f(x, m2[r], m3[r]);  // m3 <= m2: max(m3, min(m2, x))
+    m2[r] = __builtin_amdgcn_fmed3f(x, m1[r], m2[r]);
+    const uint32_t shift1 = (i12[r] << 16) | (uint32_t)t;               // m1 -> m2, x -> m1
+    const uint32_t new2 = (i12[r] & 0xffffu) | ((uint32_t)t << 16);      // x -> m2
+    i12[r] = g1 ? shift1 : (g2 ? new2 : i12[r]);
+    m1[r] = g1 ? x : m1[r];
   });
   // the largest logit M and s = sum_j exp(l_j - M) over both halves
   float mx = m1[0];
@@ -960,7 +1059,7 @@ __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q,
     if (m1[r] >= tau) {
       if (cnt < HC) {
         hv[cnt][tid] = m1[r];
-        hid[cnt][tid] = i1[r] * 32 + off;
+        hid[cnt][tid] = (int)(i12[r] & 0xffffu) * 32 + off;
         ++cnt;
       } else {
         fallback = true;
@@ -969,7 +1068,7 @@ __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q,
     if (m2[r] >= tau) {
       if (cnt < HC) {
         hv[cnt][tid] = m2[r];
-        hid[cnt][tid] = i2[r] * 32 + off;
+        hid[cnt][tid] = (int)(i12[r] >> 16) * 32 + off;
         ++cnt;
       } else {
         fallback = true;
@@ -1052,6 +1151,8 @@ void launch_mlp_propose(Ctx* c, const float* Qp, int ld, int64_t nq, const float
   PTS_REQUIRE(n_in >= 1 && n_in <= K1 && n_in <= ld, PTS_ERR_ARG, "mlp_propose: bad input width");
   PTS_REQUIRE(k >= 1 && k <= ML_P && k <= N, PTS_ERR_ARG, "proposals must be 1..8 and at most n_out");
   PTS_REQUIRE(nq < INT_MAX, PTS_ERR_UNSUPPORTED, "mlp_propose: too many queries");
+  // the one-pass output layer keeps two tile indices (N / 32 of them) in 16 bits each
+  PTS_REQUIRE(N >= 1 && N <= 65536, PTS_ERR_UNSUPPORTED, "mlp_propose: at most 65536 outputs");
   // one pass for every query, then the two-pass form for those it could not settle
   int32_t* list = c->buf<int32_t>("mlp_fix_list", (size_t)nq);
   int32_t* n_list = c->buf<int32_t>("mlp_fix_n", 1);
