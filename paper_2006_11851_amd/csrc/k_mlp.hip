@@ -474,18 +474,26 @@ __device__ __forceinline__ TileRegs wt_load(const uint16_t* __restrict__ Wb, con
 constexpr int WF_HALF = 33, WF_KK = 2 * WF_HALF;
 
 // registers -> LDS in fragment order
-// (free of branches when every thread has its chunks - KS = 8, 16 - so that
-// a step of the tile stream stays one block; every thread writes its bias,
-// the 16 threads of a row the same value)
-template <int KS>
+// (free of branches, so that a step of the tile stream stays one block, when
+// every thread has its chunks - KS = 8, 16 - or when the buffer, of CAP
+// chunks, has room past the tile for the surplus threads' copies; every
+// thread writes its bias, the 16 threads of a row the same value)
+template <int KS, int CAP = KS * WF_KK>
 __device__ __forceinline__ void wt_store(const TileRegs& T, uint4* frag, float* bs, int tid) {
   constexpr int NCH = WTile<KS>::NCH;
-  auto put = [&](int cidx, const uint4& c) {
+  auto slot = [&](int cidx) {
     const int row = cidx / WTile<KS>::CH, ch = cidx - row * WTile<KS>::CH;
-    frag[(ch >> 1) * WF_KK + (ch & 1) * WF_HALF + row] = c;
+    return (ch >> 1) * WF_KK + (ch & 1) * WF_HALF + row;
   };
-  if constexpr (ML_THREADS <= NCH) put(tid, T.c0);
-  else if (tid < NCH) put(tid, T.c0);
+  auto put = [&](int cidx, const uint4& c) { frag[slot(cidx)] = c; };
+  if constexpr (ML_THREADS <= NCH) {
+    put(tid, T.c0);
+  } else if constexpr (KS * WF_KK + ML_THREADS - NCH <= CAP) {
+    // threads NCH.. write into the unused tail KS WF_KK .. of the buffer
+    frag[tid < NCH ? slot(tid) : KS * WF_KK + (tid - NCH)] = T.c0;
+  } else if (tid < NCH) {
+    put(tid, T.c0);
+  }
   if constexpr (WTile<KS>::PER > 1) {
     if constexpr (2 * ML_THREADS <= NCH) put(tid + ML_THREADS, T.c1);
     else if (tid + ML_THREADS < NCH) put(tid + ML_THREADS, T.c1);
@@ -530,25 +538,25 @@ __device__ __forceinline__ floatx16 tile_mfma(const uint4* frag, const float* bs
 
 // the order of tile_mfma_epi: one product, one LDS read, the vector work of
 // the slots that follow product kk (vector and transcendental instructions)
-template <int KS, int AH, int VPS, int kk>
+template <int KS, int AH, int VPS, int NS, int kk>
 __device__ __forceinline__ void epi_order_step() {
-  constexpr int ns = (16 * (kk + 1)) / KS - (16 * kk) / KS;
+  constexpr int ns = (NS * (kk + 1)) / KS - (NS * kk) / KS;
   __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
   if constexpr (kk + AH < KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
   if constexpr (ns > 0) __builtin_amdgcn_sched_group_barrier(0x402, VPS * ns, 0);
 }
-template <int KS, int AH, int VPS, int... KK>
+template <int KS, int AH, int VPS, int NS, int... KK>
 __device__ __forceinline__ void epi_order(std::integer_sequence<int, KK...>) {
-  (epi_order_step<KS, AH, VPS, KK>(), ...);
+  (epi_order_step<KS, AH, VPS, NS, KK>(), ...);
 }
 
 // tile_mfma with a per-slot epilogue of the previous tile woven in: after
-// product kk, slots (16 kk / KS) .. (16 (kk + 1) / KS) - 1 of the previous
-// accumulator, about VPS vector instructions each.  A lone wave issues
+// product kk, slots (NS kk / KS) .. (NS (kk + 1) / KS) - 1 of the previous
+// tile's epilogue, about VPS vector instructions each.  A lone wave issues
 // dependent vector work at about half the SIMD's rate, so the epilogue of a
 // wave is cheapest when the other wave of the SIMD is doing the same work at
 // the same time, its own matrix products running underneath.
-template <int KS, int VPS, class SlotFn>
+template <int KS, int VPS, int NS = 16, class SlotFn>
 __device__ __forceinline__ floatx16 tile_mfma_epi(const uint4* frag, const float* bs, const bf16x8 (&B)[KS], int lane,
                                                   SlotFn&& slot) {
   constexpr int AH = KS < 4 ? KS : 4;
@@ -570,10 +578,10 @@ __device__ __forceinline__ floatx16 tile_mfma_epi(const uint4* frag, const float
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(&a[kk % AH]), B[kk], acc, 0, 0, 0);
     if (kk + AH < KS) a[kk % AH] = fp[(kk + AH) * WF_KK];
 #pragma unroll
-    for (int r = (16 * kk) / KS; r < (16 * (kk + 1)) / KS; ++r) slot(r);
+    for (int r = (NS * kk) / KS; r < (NS * (kk + 1)) / KS; ++r) slot(r);
   }
   __builtin_amdgcn_sched_group_barrier(0x100, AH + 4, 0);
-  epi_order<KS, AH, VPS>(std::make_integer_sequence<int, KS>{});
+  epi_order<KS, AH, VPS, NS>(std::make_integer_sequence<int, KS>{});
   return acc;
 }
 
@@ -648,23 +656,27 @@ __device__ __forceinline__ void hidden_layers(const float* __restrict__ Qp, int 
   static_assert(KSM >= KS1 && KSM >= KSH, "tile buffers too small");
   constexpr int NT = KSH / 2;  // tiles of 32 hidden units per layer
   const int h = lane >> 5;
+  // every load unconditional, so that they are all in flight at once: inputs
+  // past n_in repeat the last one and meet the zero columns of W1b; a query
+  // past the end reads row 0 and its results are never written
   bf16x8 X[KS1];
+  const float* qrow = Qp + (qok ? q : 0) * (int64_t)ld;
 #pragma unroll
   for (int kk = 0; kk < KS1; ++kk) {
     const int k0 = 16 * kk + 8 * h;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = k0 + j;
-      X[kk][j] = (__bf16)((qok && k < n_in) ? Qp[q * ld + k] * scale[k] : 0.f);
+      const int kc = min(k0 + j, n_in - 1);
+      X[kk][j] = (__bf16)(qrow[kc] * scale[kc]);
     }
   }
   bf16x8 H1[KSH];
   TileRegs T0, T1;
   // Software pipelined over the 2 NT tiles (NT of each layer), loads two
   // tiles ahead: step t issues the loads of tile t + 2, the matrix products
-  // of tile t and the epilogue (bias is in the accumulator; GELU, bf16) of
-  // tile t - 1, and stores tile t + 1 into LDS.  The first layer-2 tile
-  // needs every layer-1 activation, so there the epilogue goes first.
+  // of tile t woven with the epilogue (bias is in the accumulator; GELU,
+  // bf16) of tile t - 1, and stores tile t + 1 into LDS.  The first layer-2
+  // tile needs every layer-1 activation, so there the epilogue goes first.
   auto epilogue = [&](const floatx16& acc, int t) {
     if (t < NT) {
       H1[2 * t] = gelu_bf16x8(acc, 0);
@@ -673,6 +685,12 @@ __device__ __forceinline__ void hidden_layers(const float* __restrict__ Qp, int 
       H2[2 * (t - NT)] = gelu_bf16x8(acc, 0);
       H2[2 * (t - NT) + 1] = gelu_bf16x8(acc, 1);
     }
+  };
+  // values 2 p, 2 p + 1 of tile t (one packed bf16 pair), p = 0 .. 7
+  auto epilogue_pair = [&](const floatx16& acc, int t, int p) {
+    bf16x8& o = t < NT ? H1[2 * t + (p >> 2)] : H2[2 * (t - NT) + (p >> 2)];
+    o[2 * (p & 3)] = (__bf16)gelu_poly_f(acc[2 * p]);
+    o[2 * (p & 3) + 1] = (__bf16)gelu_poly_f(acc[2 * p + 1]);
   };
   // tile k of the stream: layer-1 tile k (k < NT) or layer-2 tile k - NT
   // tile k of the stream goes through register set k % 2 (t is compile-time below)
@@ -685,8 +703,8 @@ __device__ __forceinline__ void hidden_layers(const float* __restrict__ Qp, int 
   };
   auto store = [&](int k) {
     const TileRegs T = (k & 1) ? T1 : T0;
-    if (k < NT) wt_store<KS1>(T, frag[k & 1], bs[k & 1], tid);
-    else wt_store<KSH>(T, frag[k & 1], bs[k & 1], tid);
+    if (k < NT) wt_store<KS1, KSM * WF_KK>(T, frag[k & 1], bs[k & 1], tid);
+    else wt_store<KSH, KSM * WF_KK>(T, frag[k & 1], bs[k & 1], tid);
   };
   load(0);
   load(1);
@@ -696,13 +714,23 @@ __device__ __forceinline__ void hidden_layers(const float* __restrict__ Qp, int 
 #pragma unroll
   for (int t = 0; t <= 2 * NT; ++t) {
     if (t + 2 < 2 * NT) load(t + 2);
-    if (t == NT) epilogue(acc_prev, t - 1);
     floatx16 acc_cur = {};
-    if (t < NT) acc_cur = tile_mfma<KS1>(frag[t & 1], bs[t & 1], X, lane);
-    else if (t < 2 * NT) acc_cur = tile_mfma<KSH>(frag[t & 1], bs[t & 1], H1, lane);
-    if (t >= 1 && t != NT) epilogue(acc_prev, t - 1);
+    auto pair = [&](int p) { epilogue_pair(acc_prev, t - 1, p); };
+    if (t == 0) {
+      acc_cur = tile_mfma<KS1>(frag[0], bs[0], X, lane);
+    } else if (t < NT) {
+      acc_cur = tile_mfma_epi<KS1, 25, 8>(frag[t & 1], bs[t & 1], X, lane, pair);
+    } else if (t == NT) {
+      epilogue(acc_prev, t - 1);
+      acc_cur = tile_mfma<KSH>(frag[t & 1], bs[t & 1], H1, lane);
+    } else if (t < 2 * NT) {
+      acc_cur = tile_mfma_epi<KSH, 25, 8>(frag[t & 1], bs[t & 1], H1, lane, pair);
+    } else {
+      epilogue(acc_prev, t - 1);
+    }
     if (t + 1 < 2 * NT) store(t + 1);
     lds_barrier();
+    __builtin_amdgcn_sched_barrier(0);  // each step is scheduled on its own
     acc_prev = acc_cur;
   }
 }
