@@ -11,15 +11,23 @@ struct EstepStats {
   double ms = 0.0;
 };
 
-// An exemplar image the search and blend run against.
+// An exemplar image the search and blend run against; pk / srow: its 8-bit
+// form (Ctx::ex_pk) when it has one, else null.
 struct ExView {
   const float* img;
   int Hz, Wz;
+  const uint32_t* pk = nullptr;
+  const float* srow = nullptr;
 };
 
 inline ExView ctx_exemplar(Ctx* c) {
   PTS_REQUIRE(c->Hz > 0, PTS_ERR_STATE, "no exemplar set");
-  return ExView{c->ex.as<float>(), c->Hz, c->Wz};
+  ExView v{c->ex.as<float>(), c->Hz, c->Wz};
+  if (c->ex_packed) {
+    v.pk = c->ex_pk.as<uint32_t>();
+    v.srow = c->ex_srow.as<float>();
+  }
+  return v;
 }
 
 // padded PCA width: the smallest of 16, 24, 32, 48, 64, 96, 128 >= d

@@ -124,6 +124,11 @@ struct Ctx {
   DevMem ex;  // f32 [Hz][Wz][4]
   int Hz = 0, Wz = 0;
   uint64_t ex_version = 0;
+  // an exemplar set from 8-bit RGB also keeps that form: ex_pk [Hz][Wz] =
+  // R | G << 8 | B << 16 and ex_srow [Hz] = its guidance value per row, from
+  // which the gathers rebuild exactly the floats of ex at a quarter of the bytes
+  DevMem ex_pk, ex_srow;
+  bool ex_packed = false;
 
   Index index;
   Mlp mlp;

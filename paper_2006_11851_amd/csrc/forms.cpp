@@ -18,7 +18,7 @@ bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, ix.N, ix.dk, S, pd, pi);
   if (p.rerank_full) {
     launch_select_rerank_full(c, pd, pi, nq, S, 1, nq, nullptr, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
-                              p.stride, ex.img, ex.Hz, ex.Wz, nn, dist);
+                              p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);
     return dist != nullptr;
   }
   launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
@@ -51,7 +51,7 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   int32_t* fb = count_fallbacks ? c->buf<int32_t>("ln_fallbacks", 1) : nullptr;
   if (fb) launch_zero_i32(c, fb, 1);
   launch_learned_pairs(c, prop, margin, dleaf, nq, P, p.margin, L, pair_leaf, fb);
-  const int chunk = bf16_scan ? 512 : leaf_scan_f32_chunk(ix.dp);
+  const int chunk = bf16_scan ? leaf_scan_bf16_chunk() : leaf_scan_f32_chunk(ix.dp);
   int max_tiles = 0;
   BucketBufs b = bucket_buffers(c, nq * P1, L, chunk, &max_tiles);
   launch_bucket(c, pair_leaf, nq * P1, L, chunk, b);
@@ -73,7 +73,7 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
                           pdd, pii);
     if (p.rerank_full) {
       launch_select_rerank_full(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
-                                p.stride, ex.img, ex.Hz, ex.Wz, nn, dist);
+                                p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);
       *dist_done = dist != nullptr;
     } else {
       launch_merge_rerank_pca(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,

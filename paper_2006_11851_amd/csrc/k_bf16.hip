@@ -21,6 +21,7 @@
 // one range through its own L2.  A per-query merge of the S partial lists
 // and the FP32 re-rank follow.
 #include <cfloat>
+#include <utility>
 #include <climits>
 
 #include "kernels_bf16.hpp"
@@ -99,24 +100,24 @@ __device__ __forceinline__ uint4 stage_frag(const BruteSmem<KS>& S, int buf, int
 
 // Loads one stage (rows r0 .. r0+127 of [row_begin, row_end)) from global
 // into registers: each thread owns up to 2 chunks of 16 B plus zn entries.
-template <int KS>
+template <int KS, int NTH = BB_QPB>
 struct StageRegs {
-  uint4 v[(BB_STAGE * KS * 2 + BB_QPB - 1) / BB_QPB];
+  uint4 v[(BB_STAGE * KS * 2 + NTH - 1) / NTH];
   float zn;
 };
 
 // The loads carry no lane-dependent condition (rows past the range read the
 // last row; stage_store replaces them by zero rows with norm FLT_MAX), so
 // the compiler waits for them only right before the store.
-template <int KS>
-__device__ __forceinline__ void stage_load(StageRegs<KS>& R, const uint16_t* __restrict__ Zb,
+template <int KS, int NTH = BB_QPB>
+__device__ __forceinline__ void stage_load(StageRegs<KS, NTH>& R, const uint16_t* __restrict__ Zb,
                                            const float* __restrict__ zbn, int64_t r0, int64_t row_end, int tid) {
   constexpr int CH = KS * 2;  // 16-byte chunks per row
   constexpr int NCH = BB_STAGE * CH;
-  constexpr int PER = (NCH + BB_QPB - 1) / BB_QPB;
+  constexpr int PER = (NCH + NTH - 1) / NTH;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int c = tid + u * BB_QPB;
+    const int c = tid + u * NTH;
     if (c < NCH) {  // uniform per wave
       const int row = c / CH, ch = c - row * CH;
       const int64_t gr = min(r0 + row, row_end - 1);
@@ -126,15 +127,16 @@ __device__ __forceinline__ void stage_load(StageRegs<KS>& R, const uint16_t* __r
   R.zn = zbn[min(r0 + (tid & (BB_STAGE - 1)), row_end - 1)];
 }
 
-template <int KS>
-__device__ __forceinline__ void stage_store(const StageRegs<KS>& R, BruteSmem<KS>& S, int buf, int tid, int64_t r0,
-                                            int64_t row_end) {
+template <int KS, int NTH = BB_QPB>
+__device__ __forceinline__ void stage_store(const StageRegs<KS, NTH>& R, BruteSmem<KS>& S, int buf, int tid,
+                                            int64_t r0, int64_t row_end) {
+  static_assert(NTH >= BB_STAGE, "one thread per row norm");
   constexpr int CH = KS * 2;
   constexpr int NCH = BB_STAGE * CH;
-  constexpr int PER = (NCH + BB_QPB - 1) / BB_QPB;
+  constexpr int PER = (NCH + NTH - 1) / NTH;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int c = tid + u * BB_QPB;
+    const int c = tid + u * NTH;
     if (c < NCH) {
       const int row = c / CH, ch = c - row * CH;
       const int tile = row >> 5, i = row & 31;
@@ -317,12 +319,90 @@ __device__ __forceinline__ void stage_compute_cls(const BruteSmem<KS>& S, int bu
   }
 }
 
-// BF16 scan of leaves for (query, leaf) pairs: tile = (leaf, 512 pairs of
-// the bucketed order); rows = the leaf's members (contiguous in leaf order);
+// pairs per leaf-scan tile (one block of 8 waves, 64 pairs each; blocks of
+// 4 waves, two per CU, were slower)
+constexpr int LS_QPB = 512;
+int leaf_scan_bf16_chunk() { return LS_QPB; }
+
+// The full-stage form of stage_compute_cls, software pipelined: the products
+// of tile t (two independent chains, one per query tile) are woven with the
+// class updates of tile t - 1, so that the accumulators are read long after
+// their last product; only the last tile's updates follow the products.
+template <int KS, int kk>
+__device__ __forceinline__ void cls_order_step() {
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+  __builtin_amdgcn_sched_group_barrier(0x002, 24 / KS, 0);
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+  __builtin_amdgcn_sched_group_barrier(0x002, 24 / KS, 0);
+}
+template <int KS, int... KK>
+__device__ __forceinline__ void cls_order(std::integer_sequence<int, KK...>) {
+  (cls_order_step<KS, KK>(), ...);
+}
+
+template <int KS>
+__device__ __forceinline__ void stage_compute_cls_full(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
+                                                       float (&cm)[2][8], int (&ct)[2][8], int pos0, int lane) {
+  auto update = [&](const floatx16& acc, int qt, int c, int tbase) {
+    const float m3 = __builtin_fminf(cm[qt][c], __builtin_fminf(acc[c], acc[c + 8]));
+    ct[qt][c] = (m3 < cm[qt][c]) ? tbase : ct[qt][c];
+    cm[qt][c] = m3;
+  };
+  floatx16 accp[2];
+#pragma unroll
+  for (int t = 0; t < BB_STAGE / 32; ++t) {
+    __builtin_amdgcn_sched_barrier(0);  // tile by tile
+    bf16x8 A[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
+      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+    floatx16 cinit;
+    const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
+      cinit[4 * g + 0] = z4.x;
+      cinit[4 * g + 1] = z4.y;
+      cinit[4 * g + 2] = z4.z;
+      cinit[4 * g + 3] = z4.w;
+    }
+    floatx16 accn[2] = {cinit, cinit};
+    const int tprev = pos0 + (t - 1) * 32;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+#pragma unroll
+      for (int qt = 0; qt < 2; ++qt) {
+        accn[qt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], accn[qt], 0, 0, 0);
+        if (t > 0) {
+          // the 16 class updates of the previous tile spread over the 2 KS products
+#pragma unroll
+          for (int j = (16 * (2 * kk + qt)) / (2 * KS); j < (16 * (2 * kk + qt + 1)) / (2 * KS); ++j)
+            update(accp[j >> 3], j >> 3, j & 7, tprev);
+        }
+      }
+    }
+    if (t > 0) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 2 * KS, 0);
+      cls_order<KS>(std::make_integer_sequence<int, KS>{});
+    }
+    accp[0] = accn[0];
+    accp[1] = accn[1];
+  }
+  const int tlast = pos0 + (BB_STAGE / 32 - 1) * 32;
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) update(accp[qt], qt, c, tlast);
+}
+
+// BF16 scan of leaves for (query, leaf) pairs: tile = (leaf, LS_QPB pairs
+// of the bucketed order); rows = the leaf's members (contiguous in leaf order);
 // per pair the top-8 (score, leaf position).  Waves without pairs skip the
 // matrix work but still help stage the rows.
 template <int KS>
-__global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restrict__ Qb, int P,
+__global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __restrict__ Qb, int P,
                                                         const uint16_t* __restrict__ Zb,
                                                         const float* __restrict__ zbn,
                                                         const int32_t* __restrict__ leaf_off,
@@ -338,7 +418,7 @@ __global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restri
   if (t >= *ntiles) return;  // uniform per block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int2 tile = tiles[t];
-  const int pend = min(qoff[tile.x + 1], tile.y + BB_QPB);
+  const int pend = min(qoff[tile.x + 1], tile.y + LS_QPB);
   const bool wave_active = tile.y + wave * 64 < pend;
   bf16x8 B[2][KS];
   int pr[2];
@@ -367,10 +447,10 @@ __global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restri
   if (row_begin < row_end) {
     const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
     // stages load two ahead, as in the brute-force kernel
-    StageRegs<KS> R[2];
-    stage_load<KS>(R[0], Zb, zbn, row_begin, row_end, tid);
-    stage_load<KS>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
-    stage_store<KS>(R[0], sm, 0, tid, row_begin, row_end);
+    StageRegs<KS, LS_QPB> R[2];
+    stage_load<KS, LS_QPB>(R[0], Zb, zbn, row_begin, row_end, tid);
+    stage_load<KS, LS_QPB>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
+    stage_store<KS, LS_QPB>(R[0], sm, 0, tid, row_begin, row_end);
     lds_barrier();
     for (int s0 = 0; s0 < nstages; s0 += 2) {
 #pragma unroll
@@ -379,14 +459,14 @@ __global__ __launch_bounds__(512) void k_leaf_scan_bf16(const uint16_t* __restri
         if (st >= nstages) break;
         // unconditional (past the end: the last rows again, never stored), so
         // the wait before the store covers only the older stage
-        stage_load<KS>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
+        stage_load<KS, LS_QPB>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
         if (wave_active) {
           const int nvalid = min(BB_STAGE, row_end - row_begin - st * BB_STAGE);
-          if (nvalid == BB_STAGE) stage_compute_cls<KS, true>(sm, u, B, cm, ct, row_begin + st * BB_STAGE, lane, nvalid);
+          if (nvalid == BB_STAGE) stage_compute_cls_full<KS>(sm, u, B, cm, ct, row_begin + st * BB_STAGE, lane);
           else stage_compute_cls<KS, false>(sm, u, B, cm, ct, row_begin + st * BB_STAGE, lane, nvalid);
         }
         if (st + 1 < nstages)
-          stage_store<KS>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
+          stage_store<KS, LS_QPB>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
         lds_barrier();
       }
     }
@@ -501,7 +581,7 @@ void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb
                            int32_t* pair_i) {
   ProfScope ps(c, "leaf_scan_bf16");
   if (max_tiles == 0) return;
-  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_leaf_scan_bf16<KSC>, dim3(max_tiles), dim3(BB_QPB), 0, c->stream, Qb, P, Zb,
+  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_leaf_scan_bf16<KSC>, dim3(max_tiles), dim3(LS_QPB), 0, c->stream, Qb, P, Zb,
                                        zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, pair_d, pair_i));
   check_launch("k_leaf_scan_bf16");
 }
@@ -639,11 +719,16 @@ struct Top8Lex {
 
 constexpr int SR_QPB = 256;
 
+// PK: the exemplar windows come from its 8-bit form (pk, srow), rebuilt as
+// the same floats the RGBS image holds (channel value / 255, the row's
+// guidance value), at 4 bytes a pixel instead of 16.
+template <bool PK>
 __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     const float* __restrict__ part_d, const int32_t* __restrict__ part_i, int64_t nq, int S, int64_t qs, int64_t ss,
     const int32_t* __restrict__ valid, int k, const int32_t* __restrict__ perm, int64_t npos,
-    const float4* __restrict__ x, int W, int w, int s, int cols, const float4* __restrict__ ex, int Hz, int Wz,
-    int32_t* __restrict__ nn, float* __restrict__ dist) {
+    const float4* __restrict__ x, int W, int w, int s, int cols, const float4* __restrict__ ex,
+    const uint32_t* __restrict__ pk, const float* __restrict__ srow, int Hz, int Wz, int32_t* __restrict__ nn,
+    float* __restrict__ dist) {
   __shared__ int32_t cand[BB_TOPK][SR_QPB];
   const int tid = threadIdx.x;
   const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SR_QPB;
@@ -687,12 +772,14 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     const int qi = (int)(q / cols), qj = (int)(q - (int64_t)qi * cols);
     const int v = qi * s, u = qj * s;
     int64_t eb[8];
+    int eyc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       int e = cand[c][ql];
       if (e < 0 || e >= N) e = 0;  // read an in-bounds window, result discarded below
       const int ey = e / nu;
       eb[c] = (int64_t)ey * Wz + (e - ey * nu);
+      eyc[c] = ey;
     }
     float acc[8];
 #pragma unroll
@@ -710,7 +797,20 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
       const int64_t eo = (int64_t)dy * Wz + dx;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const float4 b = ex[eb[c] + eo];
+        float4 b;
+        if constexpr (PK) {
+          // the rounded products, as stored in the RGBS image (contraction
+          // off: not fused into the subtraction below)
+#pragma clang fp contract(off)
+          const float inv = 1.0f / 255.0f;
+          const uint32_t pv = pk[eb[c] + eo];
+          b.x = (float)(pv & 255u) * inv;
+          b.y = (float)((pv >> 8) & 255u) * inv;
+          b.z = (float)((pv >> 16) & 255u) * inv;
+          b.w = srow[eyc[c] + dy];
+        } else {
+          b = ex[eb[c] + eo];
+        }
         const float t0 = a.x - b.x, t1 = a.y - b.y, t2 = a.z - b.z, t3 = a.w - b.w;
         acc[c] = fmaf(t0, t0, acc[c]);
         acc[c] = fmaf(t1, t1, acc[c]);
@@ -768,15 +868,21 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
 
 void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
                                int64_t ss, const int32_t* valid, int k, const int32_t* perm, int64_t npos,
-                               const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
-                               int32_t* nn, float* dist) {
+                               const float* x, int H, int W, int w, int s, const float* ex, const uint32_t* ex_pk,
+                               const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist) {
   ProfScope ps(c, "select_rerank_full");
   if (nq == 0) return;
   PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
   PTS_REQUIRE(w >= 1 && w <= Hz && w <= Wz && w <= H && W % s == 0, PTS_ERR_ARG, "select_rerank_full: bad geometry");
-  hipLaunchKernelGGL(k_select_rerank_full, dim3((unsigned)ceil_div(nq, SR_QPB)), dim3(SR_QPB), 0, c->stream, part_d,
-                     part_i, nq, S, qs, ss, valid, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
-                     reinterpret_cast<const float4*>(ex), Hz, Wz, nn, dist);
+  const dim3 grid((unsigned)ceil_div(nq, SR_QPB));
+  if (ex_pk && ex_srow)
+    hipLaunchKernelGGL(k_select_rerank_full<true>, grid, dim3(SR_QPB), 0, c->stream, part_d, part_i, nq, S, qs, ss,
+                       valid, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
+                       reinterpret_cast<const float4*>(ex), ex_pk, ex_srow, Hz, Wz, nn, dist);
+  else
+    hipLaunchKernelGGL(k_select_rerank_full<false>, grid, dim3(SR_QPB), 0, c->stream, part_d, part_i, nq, S, qs, ss,
+                       valid, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
+                       reinterpret_cast<const float4*>(ex), ex_pk, ex_srow, Hz, Wz, nn, dist);
   check_launch("k_select_rerank_full");
 }
 

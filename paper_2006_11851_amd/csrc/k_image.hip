@@ -89,7 +89,26 @@ __global__ __launch_bounds__(256) void k_upsample2(const float4* __restrict__ in
   out[p] = o;
 }
 
+__global__ __launch_bounds__(256) void k_pack_exemplar(const uint8_t* __restrict__ u8, int H, int W,
+                                                       const float4* __restrict__ img, uint32_t* __restrict__ pk,
+                                                       float* __restrict__ srow) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)H * W) return;
+  pk[p] = (uint32_t)u8[3 * p] | ((uint32_t)u8[3 * p + 1] << 8) | ((uint32_t)u8[3 * p + 2] << 16);
+  const int y = (int)(p / W);
+  if (p - (int64_t)y * W == 0) srow[y] = img[p].w;
+}
+
 static unsigned blocks_for(int64_t n, int per) { return (unsigned)ceil_div(n, per); }
+
+void launch_pack_exemplar(Ctx* c, const uint8_t* u8, int H, int W, const float* img, uint32_t* pk, float* srow) {
+  ProfScope ps(c, "pack_exemplar");
+  int64_t n = (int64_t)H * W;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_pack_exemplar, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, u8, H, W,
+                     reinterpret_cast<const float4*>(img), pk, srow);
+  check_launch("k_pack_exemplar");
+}
 
 void launch_rgbs_from_u8(Ctx* c, const uint8_t* u8, int H, int W, float gw, float* out) {
   ProfScope ps(c, "rgbs_from_u8");

@@ -8,6 +8,8 @@ namespace pts {
 
 // ---- images (k_image.hip)
 void launch_rgbs_from_u8(Ctx* c, const uint8_t* u8, int H, int W, float gw, float* out);
+// the 8-bit form of an exemplar (see Ctx::ex_pk): u8 [H][W][3], img its RGBS floats
+void launch_pack_exemplar(Ctx* c, const uint8_t* u8, int H, int W, const float* img, uint32_t* pk, float* srow);
 void launch_fill_guidance(Ctx* c, float* x, int H, int W, float gw);
 void launch_blur_decimate(Ctx* c, const float* in, int H, int W, float gw, float* out);
 void launch_upsample2(Ctx* c, const float* in, int H, int W, float gw, float* out);

@@ -29,6 +29,8 @@ void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16
 void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
                              int64_t ss, const int32_t* valid, int k, const float* Qp, int dp, const float* Zp,
                              const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out, int32_t* nn);
+// pairs per tile of the leaf scan (the bucketing chunk)
+int leaf_scan_bf16_chunk();
 // 8 class-minimum candidates (score, leaf position) of each bucketed (query,
 // leaf) pair over the leaf's members: pair [nq*P][8]
 void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb, const float* zbn, int dk,
@@ -36,10 +38,11 @@ void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb
                            int32_t* pair_i);
 // merge S partial lists per query as above and re-rank the best k by the
 // full-D FP32 distance gathered from the images x [H][W][4] and ex
-// [Hz][Wz][4]; nn = exemplar id, dist (optional) = its full-D distance
+// [Hz][Wz][4] (read from its 8-bit form ex_pk / ex_srow when given: the same
+// values); nn = exemplar id, dist (optional) = its full-D distance
 void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
                                int64_t ss, const int32_t* valid, int k, const int32_t* perm, int64_t npos,
-                               const float* x, int H, int W, int w, int s, const float* ex, int Hz, int Wz,
-                               int32_t* nn, float* dist);
+                               const float* x, int H, int W, int w, int s, const float* ex, const uint32_t* ex_pk,
+                               const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist);
 
 }  // namespace pts

@@ -110,6 +110,7 @@ int pts_set_exemplar(pts_ctx* c, const float* rgbs, int Hz, int Wz) {
     PTS_HIP(hipMemcpyAsync(dst, rgbs, (size_t)Hz * Wz * 16, hipMemcpyDeviceToDevice, c->stream));
     c->Hz = Hz;
     c->Wz = Wz;
+    c->ex_packed = false;
     c->ex_version++;
     c->index.valid = false;
     c->mlp.valid = false;
@@ -125,9 +126,13 @@ int pts_set_exemplar_u8(pts_ctx* c, const uint8_t* rgb_host, int Hz, int Wz, flo
     PTS_HIP(hipMemcpyAsync(tmp, rgb_host, (size_t)Hz * Wz * 3, hipMemcpyHostToDevice, c->stream));
     float* dst = static_cast<float*>(c->ex.ensure(c, (size_t)Hz * Wz * 16));
     launch_rgbs_from_u8(c, tmp, Hz, Wz, gw, dst);
+    uint32_t* pk = static_cast<uint32_t*>(c->ex_pk.ensure(c, (size_t)Hz * Wz * 4));
+    float* srow = static_cast<float*>(c->ex_srow.ensure(c, (size_t)Hz * 4));
+    launch_pack_exemplar(c, tmp, Hz, Wz, dst, pk, srow);
     PTS_HIP(hipStreamSynchronize(c->stream));  // host buffer may be released by the caller
     c->Hz = Hz;
     c->Wz = Wz;
+    c->ex_packed = true;
     c->ex_version++;
     c->index.valid = false;
     c->mlp.valid = false;

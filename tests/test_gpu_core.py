@@ -255,6 +255,30 @@ def test_ragged_and_small_shapes(gpu_ctx):
         assert np.allclose(_np(d3), np.sqrt(parity.sqdist_rows(Q, Zm, g3)), rtol=1e-5, atol=1e-6)
 
 
+def test_packed_exemplar_gathers_are_exact(gpu_ctx):
+    """An exemplar set from 8-bit RGB is also kept as 4 bytes a pixel, from
+    which the full-D re-rank rebuilds the same floats: the search through it
+    equals, bit for bit, the search through the same image set as floats
+    (same index, imported)."""
+    r = np.random.default_rng(23)
+    zu8 = r.integers(0, 256, size=(40, 44, 3)).astype(np.uint8)
+    xu8 = r.integers(0, 256, size=(48, 64, 3)).astype(np.uint8)
+    w, s = 4, 2
+    gpu_ctx.set_exemplar_u8(zu8, 0.5)
+    x = gpu_ctx.rgbs_from_u8(xu8)
+    gpu_ctx.build_index(w, 16, 4, 2, seed=3, make_bf16=True)
+    g = gpu_ctx.export_index()
+    nn1, d1 = gpu_ctx.estep(x, w, s, mode="brute_bf16", rerank_full=1)
+    nn1, d1 = _np(nn1).copy(), _np(d1).copy()
+    gpu_ctx.set_exemplar(gpu_ctx.rgbs_from_u8(zu8, 0.5))
+    gpu_ctx.import_index(g)
+    nn2, d2 = gpu_ctx.estep(x, w, s, mode="brute_bf16", rerank_full=1)
+    assert np.array_equal(nn1, _np(nn2))
+    assert np.array_equal(d1.view(np.uint32), _np(d2).view(np.uint32))
+    Q, Zm = helpers.query_and_exemplar(vectors.rgbs(xu8), vectors.rgbs(zu8), w, s)
+    assert np.allclose(d1, np.sqrt(parity.sqdist_rows(Q, Zm, nn1)), rtol=1e-5, atol=1e-6)
+
+
 def test_error_codes(gpu_ctx):
     import torch
 
