@@ -17,11 +17,14 @@ namespace pts {
 
 // Patch (a, b) of offset o: rows {2b+o, 2b+o+1} clipped to [0, H), columns
 // {2a+o, 2a+o+1} mod W.  For o = 1, b runs from -1 (the 1-row patch of row 0).
+// PK: the exemplar's RGB comes from its 8-bit form pk (channel value / 255,
+// the rounded product the RGBS image holds), 4 bytes a pixel instead of 16.
+template <bool PK>
 __global__ __launch_bounds__(256) void k_mstep_patch2x2(const int32_t* __restrict__ nn,
                                                         const float* __restrict__ dist, float4* __restrict__ x,
                                                         int H, int W, int w, int s, const float4* __restrict__ ex,
-                                                        int Hz, int Wz, float r, float delta, int o, int npx,
-                                                        int npy) {
+                                                        const uint32_t* __restrict__ pk, int Hz, int Wz, float r,
+                                                        float delta, int o, int npx, int npy) {
   const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= (int64_t)npx * npy) return;
   const int a = (int)(t % npx);
@@ -64,9 +67,22 @@ __global__ __launch_bounds__(256) void k_mstep_patch2x2(const int32_t* __restric
       for (int yy = 0; yy < 2; ++yy) {
         if (yy >= nrow) break;
         const int oy = lo + yy - v;
-        const float4* row = ex + (int64_t)(ey + oy) * Wz + exx;
-        const float4 z0 = row[tt];      // pixel c0: offset (c0 - u) mod W = tt
-        const float4 z1 = row[tt + 1];  // pixel c1: offset tt + 1
+        const int64_t rb = (int64_t)(ey + oy) * Wz + exx;
+        float4 z0, z1;  // pixel c0: offset (c0 - u) mod W = tt; pixel c1: offset tt + 1
+        if constexpr (PK) {
+#pragma clang fp contract(off)
+          const float i255 = 1.0f / 255.0f;
+          const uint32_t p0 = pk[rb + tt], p1 = pk[rb + tt + 1];
+          z0.x = (float)(p0 & 255u) * i255;
+          z0.y = (float)((p0 >> 8) & 255u) * i255;
+          z0.z = (float)((p0 >> 16) & 255u) * i255;
+          z1.x = (float)(p1 & 255u) * i255;
+          z1.y = (float)((p1 >> 8) & 255u) * i255;
+          z1.z = (float)((p1 >> 16) & 255u) * i255;
+        } else {
+          z0 = ex[rb + tt];
+          z1 = ex[rb + tt + 1];
+        }
         acc[yy][0][0] = fmaf(Wq, z0.x, acc[yy][0][0]);
         acc[yy][0][1] = fmaf(Wq, z0.y, acc[yy][0][1]);
         acc[yy][0][2] = fmaf(Wq, z0.z, acc[yy][0][2]);
@@ -97,16 +113,20 @@ __global__ __launch_bounds__(256) void k_mstep_patch2x2(const int32_t* __restric
 }
 
 void launch_mstep(Ctx* c, const int32_t* nn, const float* dist, float* x, int H, int W, int w, int s,
-                  const float* ex, int Hz, int Wz, float r, float delta, int o) {
+                  const float* ex, const uint32_t* ex_pk, int Hz, int Wz, float r, float delta, int o) {
   ProfScope ps(c, "mstep_patch2x2");
   PTS_REQUIRE(o == 0 || o == 1, PTS_ERR_ARG, "patch_offset must be 0 or 1");
   const int npx = W / 2;
   const int npy = H / 2 + o;
   const int64_t n = (int64_t)npx * npy;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_mstep_patch2x2, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, nn, dist,
-                     reinterpret_cast<float4*>(x), H, W, w, s, reinterpret_cast<const float4*>(ex), Hz, Wz, r,
-                     delta, o, npx, npy);
+  const dim3 grid((unsigned)ceil_div(n, 256));
+  if (ex_pk)
+    hipLaunchKernelGGL(k_mstep_patch2x2<true>, grid, dim3(256), 0, c->stream, nn, dist, reinterpret_cast<float4*>(x),
+                       H, W, w, s, reinterpret_cast<const float4*>(ex), ex_pk, Hz, Wz, r, delta, o, npx, npy);
+  else
+    hipLaunchKernelGGL(k_mstep_patch2x2<false>, grid, dim3(256), 0, c->stream, nn, dist, reinterpret_cast<float4*>(x),
+                       H, W, w, s, reinterpret_cast<const float4*>(ex), ex_pk, Hz, Wz, r, delta, o, npx, npy);
   check_launch("k_mstep_patch2x2");
 }
 

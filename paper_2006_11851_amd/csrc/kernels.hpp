@@ -34,8 +34,9 @@ void launch_count_diff(Ctx* c, const int32_t* a, const int32_t* b, int64_t n, in
 void launch_zero_i32(Ctx* c, int32_t* p, int64_t n);
 
 // ---- blend and energy (k_mstep.hip)
+// ex_pk (optional): the exemplar's 8-bit form (Ctx::ex_pk), read instead of ex's RGB
 void launch_mstep(Ctx* c, const int32_t* nn, const float* dist, float* x, int H, int W, int w, int s,
-                  const float* ex, int Hz, int Wz, float r, float delta, int o);
+                  const float* ex, const uint32_t* ex_pk, int Hz, int Wz, float r, float delta, int o);
 void launch_energy(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2);
 
 // ---- index (k_index.hip)

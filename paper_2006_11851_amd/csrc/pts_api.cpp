@@ -260,7 +260,8 @@ int pts_mstep(pts_ctx* c, const int32_t* nn, const float* dist, float* x, int H,
     validate_grid(H, W, p->w, p->stride);
     PTS_REQUIRE(p->w <= c->Hz && p->w <= c->Wz, PTS_ERR_ARG, "mstep: window larger than exemplar");
     PTS_REQUIRE(p->r > 0.f && p->r <= 2.f && p->delta > 0.f, PTS_ERR_ARG, "mstep: need 0 < r <= 2, delta > 0");
-    launch_mstep(c, nn, dist, x, H, W, p->w, p->stride, c->ex.as<float>(), c->Hz, c->Wz, p->r, p->delta,
+    launch_mstep(c, nn, dist, x, H, W, p->w, p->stride, c->ex.as<float>(),
+                 c->ex_packed ? c->ex_pk.as<uint32_t>() : nullptr, c->Hz, c->Wz, p->r, p->delta,
                  p->patch_offset);
   });
 }

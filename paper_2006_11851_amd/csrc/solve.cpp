@@ -110,7 +110,7 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
       launch_energy(c, dist, nq, p.r, p.delta, eo);
       launch_zero_i32(c, dcount, 1);
       if (t > 0) launch_count_diff(c, nn_cur, nn_prev, nq, dcount);
-      launch_mstep(c, nn_cur, dist, cur, h, w, lp.w, lp.stride, zimg, hz, wz, p.r, p.delta, p.patch_offset);
+      launch_mstep(c, nn_cur, dist, cur, h, w, lp.w, lp.stride, zimg, nullptr, hz, wz, p.r, p.delta, p.patch_offset);
       if (tr) {
         float eh[2];
         int32_t ch = 0;

@@ -277,6 +277,15 @@ def test_packed_exemplar_gathers_are_exact(gpu_ctx):
     assert np.array_equal(d1.view(np.uint32), _np(d2).view(np.uint32))
     Q, Zm = helpers.query_and_exemplar(vectors.rgbs(xu8), vectors.rgbs(zu8), w, s)
     assert np.allclose(d1, np.sqrt(parity.sqdist_rows(Q, Zm, nn1)), rtol=1e-5, atol=1e-6)
+    # the M-step reads the same 8-bit form: the blended image is bit-identical
+    x1 = x.clone()
+    gpu_ctx.set_exemplar_u8(zu8, 0.5)
+    gpu_ctx.mstep(nn2, d2, x1, w, s)
+    x2 = x.clone()
+    gpu_ctx.set_exemplar(gpu_ctx.rgbs_from_u8(zu8, 0.5))
+    gpu_ctx.mstep(nn2, d2, x2, w, s)
+    assert np.array_equal(_np(x1).view(np.uint32), _np(x2).view(np.uint32))
+    assert not np.array_equal(_np(x1), _np(x))
 
 
 def test_error_codes(gpu_ctx):
