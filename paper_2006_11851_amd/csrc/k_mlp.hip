@@ -856,14 +856,16 @@ __device__ __forceinline__ void out_topk(const bf16x8 (&B)[KS], int64_t q, int64
   // (values only: a max/min exchange network keeps v sorted descending)
   float tau, mxl2;
   {
-    float v[ML_P];
+    // (max / min as medians with an infinity: fmaxf / fminf would first
+    // quieten their operands)
+    float v[PP];
 #pragma unroll
-    for (int u = 0; u < ML_P; ++u) v[u] = -FLT_MAX;
+    for (int u = 0; u < PP; ++u) v[u] = -FLT_MAX;
     auto push = [&](float x) {
 #pragma unroll
-      for (int u = 0; u < ML_P; ++u) {
-        const float hi = fmaxf(v[u], x);
-        x = fminf(v[u], x);
+      for (int u = 0; u < PP; ++u) {
+        const float hi = __builtin_amdgcn_fmed3f(v[u], x, INFINITY);
+        x = __builtin_amdgcn_fmed3f(v[u], x, -INFINITY);
         v[u] = hi;
       }
     };
@@ -872,14 +874,14 @@ __device__ __forceinline__ void out_topk(const bf16x8 (&B)[KS], int64_t q, int64
       push(m1[r]);
       push(m2[r]);
     }
-    float ov[ML_P];
+    float ov[PP];
 #pragma unroll
-    for (int u = 0; u < ML_P; ++u) ov[u] = __shfl_xor(v[u], 32, 64);
+    for (int u = 0; u < PP; ++u) ov[u] = __shfl_xor(v[u], 32, 64);
 #pragma unroll
-    for (int u = 0; u < ML_P; ++u) push(ov[u]);
+    for (int u = 0; u < PP; ++u) push(ov[u]);
     float tk = v[0];
 #pragma unroll
-    for (int u = 1; u < ML_P; ++u)
+    for (int u = 1; u < PP; ++u)
       if (u < kout) tk = v[u];
     tau = tk;
     mxl2 = v[0] * ML_LOG2E;
@@ -1049,14 +1051,16 @@ __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q,
   // tau: the P-th largest of the query's 64 slot values m1, m2
   float tau;
   {
-    float v[ML_P];
+    // (max / min as medians with an infinity: fmaxf / fminf would first
+    // quieten their operands)
+    float v[PP];
 #pragma unroll
-    for (int u = 0; u < ML_P; ++u) v[u] = -FLT_MAX;
+    for (int u = 0; u < PP; ++u) v[u] = -FLT_MAX;
     auto push = [&](float x) {
 #pragma unroll
-      for (int u = 0; u < ML_P; ++u) {
-        const float hi = fmaxf(v[u], x);
-        x = fminf(v[u], x);
+      for (int u = 0; u < PP; ++u) {
+        const float hi = __builtin_amdgcn_fmed3f(v[u], x, INFINITY);
+        x = __builtin_amdgcn_fmed3f(v[u], x, -INFINITY);
         v[u] = hi;
       }
     };
@@ -1065,14 +1069,14 @@ __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q,
       push(m1[r]);
       push(m2[r]);
     }
-    float ov[ML_P];
+    float ov[PP];
 #pragma unroll
-    for (int u = 0; u < ML_P; ++u) ov[u] = __shfl_xor(v[u], 32, 64);
+    for (int u = 0; u < PP; ++u) ov[u] = __shfl_xor(v[u], 32, 64);
 #pragma unroll
-    for (int u = 0; u < ML_P; ++u) push(ov[u]);
+    for (int u = 0; u < PP; ++u) push(ov[u]);
     float tk = v[0];
 #pragma unroll
-    for (int u = 1; u < ML_P; ++u)
+    for (int u = 1; u < PP; ++u)
       if (u < kout) tk = v[u];
     tau = tk;
   }
