@@ -729,9 +729,17 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     const float4* __restrict__ x, int W, int w, int s, int cols, const float4* __restrict__ ex,
     const uint32_t* __restrict__ pk, const float* __restrict__ srow, int Hz, int Wz, int32_t* __restrict__ nn,
     float* __restrict__ dist) {
+  // per query of the block (phase 1, one thread each): the candidates, their
+  // window origins (pixel index, row) and the query window's row and column,
+  // so that the 16 lanes of a query in phase 2 do no index arithmetic of their own
   __shared__ int32_t cand[BB_TOPK][SR_QPB];
+  __shared__ int32_t cbase[BB_TOPK][SR_QPB];
+  __shared__ int32_t crow[BB_TOPK][SR_QPB];
+  __shared__ int32_t qvu[2][SR_QPB];
   const int tid = threadIdx.x;
   const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SR_QPB;
+  const int nu = Wz - w + 1;
+  const int64_t N = (int64_t)(Hz - w + 1) * nu;
   {
     const int64_t q = q0 + tid;
     Top8Lex top;
@@ -756,30 +764,35 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
 #pragma unroll
     for (int t = 0; t < BB_TOPK; ++t) {
       const int pos = top.i[t];
-      cand[t][tid] = (t < k && pos >= 0 && pos < npos) ? perm[pos] : -1;
+      const int e = (t < k && pos >= 0 && pos < npos) ? perm[pos] : -1;
+      cand[t][tid] = e;
+      const int ee = (e < 0 || e >= N) ? 0 : e;  // an in-bounds window, result discarded in phase 2
+      const int ey = ee / nu;
+      cbase[t][tid] = ey * Wz + (ee - ey * nu);
+      crow[t][tid] = ey;
     }
+    const int64_t qc = q < nq ? q : 0;
+    const int qi = (int)(qc / cols);
+    qvu[0][tid] = qi * s;
+    qvu[1][tid] = (int)(qc - (int64_t)qi * cols) * s;
   }
   __syncthreads();
   const int lane = tid & 63, g = lane & 15, grp = lane >> 4;
-  const int nu = Wz - w + 1;
-  const int64_t N = (int64_t)(Hz - w + 1) * nu;
   const int npx = w * w;
   const int ci = ((g >> 3) & 1) * 4 + ((g >> 2) & 1) * 2 + ((g >> 1) & 1);  // candidate held after the butterfly
   for (int it = 0; it < SR_QPB / 16; ++it) {
     const int ql = (tid >> 6) * 64 + it * 4 + grp;
     const int64_t q = q0 + ql;
     if (q >= nq) continue;  // uniform per 16-lane group; shuffles stay inside the group
-    const int qi = (int)(q / cols), qj = (int)(q - (int64_t)qi * cols);
-    const int v = qi * s, u = qj * s;
-    int64_t eb[8];
+    const int v = qvu[0][ql], u = qvu[1][ql];
+    // 32-bit byte offsets of the windows' origins in the 8-bit form (pixel
+    // indices below 2^26): loads from a scalar base plus a 32-bit offset
+    uint32_t eb[8];
     int eyc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      int e = cand[c][ql];
-      if (e < 0 || e >= N) e = 0;  // read an in-bounds window, result discarded below
-      const int ey = e / nu;
-      eb[c] = (int64_t)ey * Wz + (e - ey * nu);
-      eyc[c] = ey;
+      eb[c] = PK ? (uint32_t)cbase[c][ql] * 4u : (uint32_t)cbase[c][ql];
+      eyc[c] = crow[c][ql];
     }
     float acc[8];
 #pragma unroll
@@ -794,7 +807,7 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
       int xx = u + dx;
       if (xx >= W) xx -= W;
       const float4 a = x[(int64_t)(v + dy) * W + xx];
-      const int64_t eo = (int64_t)dy * Wz + dx;
+      const uint32_t eo = (uint32_t)(dy * Wz + dx) * (PK ? 4u : 1u);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         float4 b;
@@ -803,11 +816,11 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
           // off: not fused into the subtraction below)
 #pragma clang fp contract(off)
           const float inv = 1.0f / 255.0f;
-          const uint32_t pv = pk[eb[c] + eo];
+          const uint32_t pv = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(pk) + (eb[c] + eo));
           b.x = (float)(pv & 255u) * inv;
           b.y = (float)((pv >> 8) & 255u) * inv;
           b.z = (float)((pv >> 16) & 255u) * inv;
-          b.w = srow[eyc[c] + dy];
+          b.w = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(srow) + (uint32_t)(eyc[c] + dy) * 4u);
         } else {
           b = ex[eb[c] + eo];
         }
