@@ -20,6 +20,7 @@
 // with the round-robin placement of blocks over the 8 XCDs every XCD streams
 // one range through its own L2.  A per-query merge of the S partial lists
 // and the FP32 re-rank follow.
+#include <algorithm>
 #include <cfloat>
 #include <utility>
 #include <climits>
@@ -402,20 +403,12 @@ __device__ __forceinline__ void stage_compute_cls_full(const BruteSmem<KS>& S, i
 // per pair the top-8 (score, leaf position).  Waves without pairs skip the
 // matrix work but still help stage the rows.
 template <int KS>
-__global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __restrict__ Qb, int P,
-                                                        const uint16_t* __restrict__ Zb,
-                                                        const float* __restrict__ zbn,
-                                                        const int32_t* __restrict__ leaf_off,
-                                                        const int32_t* __restrict__ qoff,
-                                                        const int32_t* __restrict__ order,
-                                                        const int2* __restrict__ tiles,
-                                                        const int32_t* __restrict__ ntiles,
-                                                        float* __restrict__ pair_d, int32_t* __restrict__ pair_i) {
-  __shared__ BruteSmem<KS> sm;
-  // plain hardware order: the tile costs vary with the leaf size and cluster
-  // along the list, so a contiguous range per XCD would be unbalanced
-  const int t = blockIdx.x;
-  if (t >= *ntiles) return;  // uniform per block
+__device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const uint16_t* __restrict__ Qb, int P,
+                                               const uint16_t* __restrict__ Zb, const float* __restrict__ zbn,
+                                               const int32_t* __restrict__ leaf_off,
+                                               const int32_t* __restrict__ qoff, const int32_t* __restrict__ order,
+                                               const int2* __restrict__ tiles, float* __restrict__ pair_d,
+                                               int32_t* __restrict__ pair_i) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int2 tile = tiles[t];
   const int pend = min(qoff[tile.x + 1], tile.y + LS_QPB);
@@ -546,6 +539,34 @@ __global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __res
   }
 }
 
+
+// Persistent form: one block per compute unit takes tiles from a counter
+// (zeroed before the launch) until the list is done, so no block waits for
+// the dispatcher between tiles of very different cost.
+template <int KS>
+__global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __restrict__ Qb, int P,
+                                                        const uint16_t* __restrict__ Zb,
+                                                        const float* __restrict__ zbn,
+                                                        const int32_t* __restrict__ leaf_off,
+                                                        const int32_t* __restrict__ qoff,
+                                                        const int32_t* __restrict__ order,
+                                                        const int2* __restrict__ tiles,
+                                                        const int32_t* __restrict__ ntiles,
+                                                        int32_t* __restrict__ next, float* __restrict__ pair_d,
+                                                        int32_t* __restrict__ pair_i) {
+  __shared__ BruteSmem<KS> sm;
+  __shared__ int s_t;
+  const int nt = *ntiles;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = atomicAdd(next, 1);
+    __syncthreads();
+    const int t = s_t;
+    if (t >= nt) break;  // uniform per block; the counter only grows, so every block gets here
+    leaf_scan_tile<KS>(t, sm, Qb, P, Zb, zbn, leaf_off, qoff, order, tiles, pair_d, pair_i);
+    __syncthreads();  // LDS buffers and s_t free for the next tile
+  }
+}
+
 #define PTS_KS_SWITCH(dk, ...)                                                                     \
   switch (dk) {                                                                                    \
     case 32: { constexpr int KSC = 2; __VA_ARGS__; } break;                                        \
@@ -581,8 +602,11 @@ void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb
                            int32_t* pair_i) {
   ProfScope ps(c, "leaf_scan_bf16");
   if (max_tiles == 0) return;
-  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_leaf_scan_bf16<KSC>, dim3(max_tiles), dim3(LS_QPB), 0, c->stream, Qb, P, Zb,
-                                       zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, pair_d, pair_i));
+  int32_t* next = c->buf<int32_t>("ls_next_tile", 1);
+  launch_zero_i32(c, next, 1);
+  const int grid = std::min(max_tiles, c->n_cu);
+  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_leaf_scan_bf16<KSC>, dim3(grid), dim3(LS_QPB), 0, c->stream, Qb, P, Zb, zbn,
+                                       leaf_off, b.off, b.order, b.tiles, b.ntiles, next, pair_d, pair_i));
   check_launch("k_leaf_scan_bf16");
 }
 
