@@ -373,18 +373,30 @@ __global__ __launch_bounds__(PR_WAVES * 64) void k_project_res(WinGeom g, int64_
     for (int wt = 0; wt < PM_WT; ++wt)
 #pragma unroll
       for (int kt = 0; kt < NKT; ++kt) acc[wt][kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int pg = 0; pg < ngroups; ++pg) {
+    // the pixels of group pg + 1 are loaded while group pg's products run
+    float4 xn[PM_WT];
+    auto load_group = [&](int pg) {
       const int px = 4 * pg + kq;  // this lane's pixel of the group
       const int dy = px / g.w, dx = px - dy * g.w;
-      const float4 m = mus4[px];
-      float4 xv[PM_WT];
 #pragma unroll
       for (int wt = 0; wt < PM_WT; ++wt) {
         int xx = ucol[wt] + dx;
         if (g.wrap && xx >= g.W) xx -= g.W;
-        const float4 v = ok[wt] ? img[(int64_t)(vrow[wt] + dy) * g.W + xx] : m;
+        // windows past the end read the first one's pixel; their results are not stored
+        xn[wt] = img[(int64_t)((ok[wt] ? vrow[wt] : 0) + dy) * g.W + (ok[wt] ? xx : dx)];
+      }
+    };
+    load_group(0);
+    for (int pg = 0; pg < ngroups; ++pg) {
+      const int px = 4 * pg + kq;
+      const float4 m = mus4[px];
+      float4 xv[PM_WT];
+#pragma unroll
+      for (int wt = 0; wt < PM_WT; ++wt) {
+        const float4 v = xn[wt];
         xv[wt] = make_float4(v.x - m.x, v.y - m.y, v.z - m.z, v.w - m.w);
       }
+      if (pg + 1 < ngroups) load_group(pg + 1);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
 #pragma unroll
