@@ -89,6 +89,7 @@ struct Index {
   DevMem perm;                 // i32 [N] leaf position -> exemplar id
   DevMem leaf_of_ex;           // i32 [N] exemplar id -> leaf
   DevMem leaf_off;             // i32 [n_leaves + 1]
+  DevMem leaf_by_rows;         // i32 [n_leaves] leaves by member count, largest first (ties: lower id)
   DevMem cent;                 // f32 [n_nodes][dp]
   DevMem first_child, n_children, leaf_of_node;  // i32 [n_nodes]
 };

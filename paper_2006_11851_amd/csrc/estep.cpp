@@ -81,6 +81,7 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       int max_tiles = 0;
       const int chunk = leaf_scan_f32_chunk(ix->dp);
       BucketBufs b = bucket_buffers(c, nq, ix->tree.n_leaves(), chunk, &max_tiles);
+      b.tile_order = ix->leaf_by_rows.as<int32_t>();
       launch_bucket(c, leaf, nq, ix->tree.n_leaves(), chunk, b);
       launch_leaf_scan_f32(c, qp, ix->dp, ix->zproj.as<float>(), ix->perm.as<int32_t>(), ix->leaf_off.as<int32_t>(),
                            b, max_tiles, 1, p.residual ? ix->zres.as<float>() : nullptr, nn, nullptr);

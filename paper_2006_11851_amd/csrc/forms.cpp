@@ -54,6 +54,7 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   const int chunk = bf16_scan ? leaf_scan_bf16_chunk() : leaf_scan_f32_chunk(ix.dp);
   int max_tiles = 0;
   BucketBufs b = bucket_buffers(c, nq * P1, L, chunk, &max_tiles);
+  b.tile_order = ix.leaf_by_rows.as<int32_t>();
   launch_bucket(c, pair_leaf, nq * P1, L, chunk, b);
   if (!bf16_scan) {
     int32_t* pid = c->buf<int32_t>("ln_pair_id", (size_t)nq * P1);

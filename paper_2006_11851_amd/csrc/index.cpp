@@ -297,6 +297,12 @@ void finalize_device(Ctx* c, Index& ix, ExView ex, const float* zorig, bool make
   upload(c, ix.leaf_of_node, t.leaf_of_node);
   std::vector<int32_t> lo32(t.leaf_off.begin(), t.leaf_off.end());
   upload(c, ix.leaf_off, lo32);
+  std::vector<int32_t> by_rows(t.n_leaves());
+  for (int l = 0; l < t.n_leaves(); ++l) by_rows[l] = l;
+  std::stable_sort(by_rows.begin(), by_rows.end(), [&](int a, int b) {
+    return t.leaf_off[a + 1] - t.leaf_off[a] > t.leaf_off[b + 1] - t.leaf_off[b];
+  });
+  upload(c, ix.leaf_by_rows, by_rows);
   upload(c, ix.perm, t.perm);
   std::vector<int32_t> leaf_of(N, -1);
   for (int l = 0; l < t.n_leaves(); ++l)

@@ -221,7 +221,8 @@ __global__ __launch_bounds__(1024) void k_leaf_scan_offsets(const int32_t* __res
                                                             int chunk, int32_t* __restrict__ off,
                                                             int32_t* __restrict__ cursor,
                                                             int32_t* __restrict__ tile_off,
-                                                            int32_t* __restrict__ ntiles) {
+                                                            int32_t* __restrict__ ntiles,
+                                                            const int32_t* __restrict__ tile_order) {
   __shared__ int s_a[1024], s_b[1024];
   __shared__ int carry_a, carry_b;
   if (threadIdx.x == 0) {
@@ -266,6 +267,28 @@ __global__ __launch_bounds__(1024) void k_leaf_scan_offsets(const int32_t* __res
     tile_off[n_leaves] = carry_b;
     *ntiles = carry_b;
   }
+  if (!tile_order) return;  // uniform
+  // tile offsets again, the leaves taken in tile_order (same total)
+  __syncthreads();
+  if (threadIdx.x == 0) carry_b = 0;
+  __syncthreads();
+  for (int base = 0; base < n_leaves; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int l = (i < n_leaves) ? tile_order[i] : -1;
+    const int cb = (l >= 0) ? (counts[l] + chunk - 1) / chunk : 0;
+    s_b[threadIdx.x] = cb;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int vb = (threadIdx.x >= o) ? s_b[threadIdx.x - o] : 0;
+      __syncthreads();
+      s_b[threadIdx.x] += vb;
+      __syncthreads();
+    }
+    if (l >= 0) tile_off[l] = carry_b + s_b[threadIdx.x] - cb;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry_b += s_b[1023];
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(256) void k_leaf_scatter(const int32_t* __restrict__ leaf, int64_t n, int n_leaves,
@@ -282,7 +305,8 @@ __global__ __launch_bounds__(256) void k_leaf_tiles(const int32_t* __restrict__ 
                                                     int n_leaves, int chunk, int2* __restrict__ tiles) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= n_leaves) return;
-  const int t0 = tile_off[l], t1 = tile_off[l + 1];
+  // the leaf's tiles: tile_off[l] .. + its tile count (tile_off need not follow leaf order)
+  const int t0 = tile_off[l], t1 = t0 + (off[l + 1] - off[l] + chunk - 1) / chunk;
   for (int t = t0; t < t1; ++t) tiles[t] = make_int2(l, off[l] + (t - t0) * chunk);
 }
 
@@ -352,7 +376,7 @@ static void bucket_core(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, in
     check_launch("k_leaf_hist");
   }
   hipLaunchKernelGGL(k_leaf_scan_offsets, dim3(1), dim3(1024), 0, c->stream, b.counts, n_leaves, chunk, b.off,
-                     b.cursor, b.tile_off, b.ntiles);
+                     b.cursor, b.tile_off, b.ntiles, b.tile_order);
   check_launch("k_leaf_scan_offsets");
   if (n > 0 && lds) {
     hipLaunchKernelGGL(k_leaf_scatter_lds, dim3((unsigned)ceil_div(n, BK_PER_BLOCK)), dim3(256), 0, c->stream, leaf, n,

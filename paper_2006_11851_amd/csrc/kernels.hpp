@@ -72,6 +72,9 @@ struct BucketBufs {
   int32_t* ntiles;    // [1]
   int32_t* order;     // [n] query ids grouped by leaf
   int2* tiles;        // [max_tiles] (leaf, first position in order)
+  // optional [n_leaves]: the order of the leaves in the tile list (largest
+  // leaves first, so that persistent scans end on short tiles); null: leaf order
+  const int32_t* tile_order = nullptr;
 };
 void launch_descend(Ctx* c, const float* Qp, int64_t nq, int dp, const float* cent, const int32_t* first_child,
                     const int32_t* n_children, const int32_t* leaf_of_node, int n_nodes, int32_t* leaf);
