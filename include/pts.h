@@ -188,7 +188,7 @@ int pts_estep(pts_ctx* ctx, const float* x_rgbs, int H, int W, const pts_estep_p
 /* Exhaustive full-D search (the exact reference of Eq. 4's z_q) for the
  * listed output windows only: qids int32 [n] (window ids, each < nq of the
  * grid); nn int32 [n] and dist float32 [n] (||x_q - z_nn||, FP32), ties to
- * the lowest exemplar id.  Used to judge approximate searches on a sample. */
+ * the lowest exemplar id.  Used to evaluate approximate searches on a sample. */
 int pts_exact_search(pts_ctx* ctx, const float* x_rgbs, int H, int W, int w, int stride, const int32_t* qids,
                      int64_t n, int32_t* nn, float* dist);
 
