@@ -411,6 +411,15 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
                                                int32_t* __restrict__ pair_i) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int2 tile = tiles[t];
+  const int row_begin = leaf_off[tile.x], row_end = leaf_off[tile.x + 1];
+  const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
+  // the first two stages' rows are requested before the pairs' query
+  // operands (a chain of two dependent loads), so that both are in flight
+  StageRegs<KS, LS_QPB> R[2];
+  if (row_begin < row_end) {
+    stage_load<KS, LS_QPB>(R[0], Zb, zbn, row_begin, row_end, tid);
+    stage_load<KS, LS_QPB>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
+  }
   const int pend = min(qoff[tile.x + 1], tile.y + LS_QPB);
   const bool wave_active = tile.y + wave * 64 < pend;
   bf16x8 B[2][KS];
@@ -419,11 +428,11 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
   for (int qt = 0; qt < 2; ++qt) {
     const int pos = tile.y + wave * 64 + qt * 32 + (lane & 31);
     pr[qt] = pos < pend ? order[pos] : -1;
-    const int64_t q = pr[qt] >= 0 ? pr[qt] / P : -1;
+    // a lane without a pair reads query 0: its results are never written
+    const int64_t q = pr[qt] >= 0 ? pr[qt] / P : 0;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      uint4 u = make_uint4(0, 0, 0, 0);
-      if (q >= 0) u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + (lane >> 5)];
+      const uint4 u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + (lane >> 5)];
       B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
   }
@@ -436,13 +445,8 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       cm[qt][c] = FLT_MAX;
       ct[qt][c] = -1;
     }
-  const int row_begin = leaf_off[tile.x], row_end = leaf_off[tile.x + 1];
   if (row_begin < row_end) {
-    const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
     // stages load two ahead, as in the brute-force kernel
-    StageRegs<KS, LS_QPB> R[2];
-    stage_load<KS, LS_QPB>(R[0], Zb, zbn, row_begin, row_end, tid);
-    stage_load<KS, LS_QPB>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
     stage_store<KS, LS_QPB>(R[0], sm, 0, tid, row_begin, row_end);
     lds_barrier();
     for (int s0 = 0; s0 < nstages; s0 += 2) {
