@@ -169,12 +169,16 @@ typedef struct pts_estep_params {
                       i.e. also charge each exemplar window its energy outside the PCA
                       subspace (leaf scans, BF16 scans and the PCA-space re-rank); 0: plain
                       PCA-space distance */
+  int scan_slots;  /* LEARNED_BF16: rows the second scan pass may collect per (query, leaf)
+                      pair and half-wave before the query is redone by its exact per-query
+                      pass (0 = 16; 0..16).  Results do not depend on it. */
 } pts_estep_params;
 
 typedef struct pts_estep_stats {
-  int64_t nq;        /* queries searched */
-  int64_t fallbacks; /* learned modes: queries that fell back to the tree */
-  double ms;         /* wall time of the call on the stream (hipEvent) */
+  int64_t nq;             /* queries searched */
+  int64_t fallbacks;      /* learned modes: queries that fell back to the tree */
+  int64_t scan_overflows; /* LEARNED_BF16: queries redone by the exact per-query pass */
+  double ms;              /* wall time of the call on the stream (hipEvent) */
 } pts_estep_stats;
 
 /* For every output window q of x_rgbs [H][W][4]: nn[q] = id of the chosen

@@ -1,10 +1,13 @@
 """BF16 distance form with top-k re-rank (oracle, FP64).  Test infra only.
 
 The precision form of the search: the PCA-space vectors are rounded to
-bfloat16 (round to nearest, ties to even, from their float32 values), all
+bfloat16 (round to nearest, ties to even, from their float32 values), the
 exemplar distances are ranked on the rounded vectors, the k best candidates
 (k = 8) are kept, and those k are re-ranked with the unrounded vectors; the
-winner is the re-ranked minimum (ties to the lowest exemplar id).
+winner is the re-ranked minimum (ties to the lowest exemplar id).  The
+brute-force form ranks every exemplar window (``brute_topk``); the learned
+form ranks only the members of the leaves it scans (``scan_topk``): the same
+definition over a smaller set.
 
 The oracle evaluates the distances of the rounded vectors exactly in FP64,
 i.e. the value the BF16 computation approximates; the GPU accumulates the
@@ -70,40 +73,56 @@ def brute_nn(Qp, Zp, k: int = 8, Q_full=None, Z_full=None, offset=None):
     return rerank(Qp, Zp, cand, offset=offset)[0], cand
 
 
-def class_candidates(q, Zrows, offset=None):
-    """Candidate rule of a BF16 scan over an ordered list of rows (a leaf's
-    members in leaf order): with i the position of a row in the scan, the
-    rows fall into 16 classes by i % 16 and into 32-row tiles by i // 32;
-    each class's score is its minimum over the rows (ties to the earliest
-    tile), the 4 classes with the smallest scores are kept, and each
-    contributes the two rows of its tile in that class (i and i + 16 within
-    the tile).  Scores are exact distances of the bf16-rounded vectors (plus
-    the optional per-row offset).  Returns (positions into Zrows [<=8],
-    scores [<=8]) with both rows of a class sharing the class score.
-    """
+def scan_topk(Qp, Zp, members, k: int = 8, offset=None):
+    """The k best exemplar ids of each query among ``members[i]`` (the union
+    of the members of the leaves scanned for query i; repeated ids count
+    once), ranked like :func:`brute_topk`: squared distance of the
+    bf16-rounded vectors plus the optional per-exemplar offset, ties to the
+    lowest id.  Returns (list of id arrays [<= k], list of score arrays)."""
+    Qb = round_bf16(Qp)
+    Zb = round_bf16(Zp)
+    off = None if offset is None else np.asarray(offset, dtype=np.float64)
+    ids_out, sc_out = [], []
+    for i in range(Qb.shape[0]):
+        ids = np.unique(np.asarray(members[i], dtype=np.int64))
+        diff = Zb[ids] - Qb[i][None, :]
+        d = np.einsum("ij,ij->i", diff, diff)
+        if off is not None:
+            d = d + off[ids]
+        o = np.lexsort((ids, d))[:k]
+        ids_out.append(ids[o])
+        sc_out.append(d[o])
+    return ids_out, sc_out
+
+
+def scan_scores(q, Zp_rows, offset_rows=None):
+    """Scores of one query against listed exemplar rows, as ranked by
+    :func:`scan_topk` (bf16-rounded vectors, FP64 arithmetic)."""
     qb = round_bf16(np.asarray(q)[None, :])[0]
-    Zb = round_bf16(Zrows)
-    d = np.einsum("ij,ij->i", Zb - qb[None, :], Zb - qb[None, :])
-    if offset is not None:
-        d = d + np.asarray(offset, dtype=np.float64)
-    m = d.size
-    best = []
-    for b in range(16):
-        bv, bt = np.inf, -1
-        for t in range((m + 31) // 32):
-            rows = [i for i in (32 * t + b, 32 * t + b + 16) if i < m]
-            if not rows:
-                continue
-            v = min(d[i] for i in rows)
-            if v < bv:
-                bv, bt = v, t
-        if bt >= 0:
-            best.append((bv, b, bt))
-    best.sort(key=lambda e: (e[0], e[1]))
-    pos, sc = [], []
-    for v, b, t in best[:4]:
-        for i in (32 * t + b, 32 * t + b + 16):
-            if i < m:
-                pos.append(i)
-                sc.append(v)
-    return np.asarray(pos, dtype=np.int64), np.asarray(sc)
+    diff = round_bf16(Zp_rows) - qb[None, :]
+    d = np.einsum("ij,ij->i", diff, diff)
+    if offset_rows is not None:
+        d = d + np.asarray(offset_rows, dtype=np.float64)
+    return d
+
+
+def fp32_score_tolerance(q, Zp_rows, d: int, offset_rows=None, Zm_rows=None, mu=None) -> float:
+    """Bound on how far two scores of one query can be reordered when the
+    score ||z||^2 - 2 q.z (+ offset) of bf16 operands is evaluated in FP32
+    instead of exactly: each evaluation errs by at most
+    gamma * (||z||^2 + 2 |q.z|) <= gamma * (||q||^2 + 3 ||z||^2) with
+    gamma = (d + 4) u, u = 2^-24 (the standard bound for a length-d sum
+    started at the norm, plus the norm's own rounding), and an offset computed
+    in FP32 from the D full-dimension entries errs by at most
+    (D + d + 4) u ||z - mu||^2; two scores together by twice the largest.
+    The rows are the ones the query scans."""
+    u = 2.0 ** -24
+    qb = round_bf16(np.asarray(q)[None, :])[0]
+    zb = round_bf16(Zp_rows)
+    zn = np.einsum("ij,ij->i", zb, zb)
+    t = (d + 4) * u * (float(qb @ qb) + 3.0 * float(zn.max(initial=0.0)))
+    if offset_rows is not None and Zm_rows is not None:
+        A = np.asarray(Zm_rows, dtype=np.float64) - np.asarray(mu, dtype=np.float64)[None, :]
+        D = A.shape[1]
+        t += (D + d + 4) * u * float(np.einsum("ij,ij->i", A, A).max(initial=0.0))
+    return 2.0 * t

@@ -8,6 +8,7 @@ namespace pts {
 struct EstepStats {
   int64_t nq = 0;
   int64_t fallbacks = 0;
+  int64_t scan_overflows = 0;
   double ms = 0.0;
 };
 

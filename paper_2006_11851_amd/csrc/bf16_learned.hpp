@@ -12,9 +12,10 @@ namespace pts {
 bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
                        const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist);
 // returns the number of queries that fell back to the tree; *dist_done as
-// the return value above
+// the return value above; *scan_overflows (if non-null) receives the device
+// counter of queries the BF16 scan sent to its per-query pass (null if none ran)
 int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
                        const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist, bool* dist_done,
-                       bool bf16_scan, bool count_fallbacks);
+                       bool bf16_scan, bool count_fallbacks, int32_t** scan_overflows);
 
 }  // namespace pts

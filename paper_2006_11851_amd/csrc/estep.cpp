@@ -107,7 +107,14 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       PTS_REQUIRE(!bf || ix->has_bf16, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
       uint16_t* qb = bf ? c->buf<uint16_t>("qbf16", (size_t)nq * ix->dk) : nullptr;
       project_on(c, *ix, x, H, W, p.stride, qp, qb);
-      st.fallbacks = search_learned(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist, &dist_done, bf, timing);
+      int32_t* novf = nullptr;
+      st.fallbacks = search_learned(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist, &dist_done, bf, timing, &novf);
+      if (timing && novf) {
+        int32_t h = 0;
+        PTS_HIP(hipMemcpyAsync(&h, novf, 4, hipMemcpyDeviceToHost, c->stream));
+        PTS_HIP(hipStreamSynchronize(c->stream));
+        st.scan_overflows = h;
+      }
       break;
     }
     default:

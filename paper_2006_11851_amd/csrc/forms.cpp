@@ -17,19 +17,20 @@ bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
   launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, ix.N, ix.dk, S, pd, pi);
   if (p.rerank_full) {
-    launch_select_rerank_full(c, pd, pi, nq, S, 1, nq, nullptr, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
+    launch_select_rerank_full(c, pd, pi, nq, S, 1, nq, nullptr, nullptr, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
                               p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);
     return dist != nullptr;
   }
-  launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
+  launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
                           ix.perm.as<int32_t>(), ix.N, nullptr, nn);
   return false;
 }
 
 int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
                        const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist, bool* dist_done,
-                       bool bf16_scan, bool count_fallbacks) {
+                       bool bf16_scan, bool count_fallbacks, int32_t** scan_overflows) {
   *dist_done = false;
+  if (scan_overflows) *scan_overflows = nullptr;
   const int P = p.n_proposals <= 0 ? 4 : p.n_proposals;
   PTS_REQUIRE(P >= 1 && P <= 8 && P <= ix.tree.n_leaves(), PTS_ERR_ARG, "n_proposals must be 1..8 (and <= leaves)");
   const int L = ix.tree.n_leaves();
@@ -66,19 +67,21 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     PTS_REQUIRE(ix.has_bf16 && qb, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
     const int k = p.topk <= 0 ? 8 : p.topk;
     PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
-    float* pdd = c->buf<float>("ln_pair_cd", (size_t)nq * P1 * 8);
-    int32_t* pii = c->buf<int32_t>("ln_pair_ci", (size_t)nq * P1 * 8);
     const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();
     const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
-    launch_leaf_scan_bf16(c, qb, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b, max_tiles,
-                          pdd, pii);
+    const int hc = p.scan_slots <= 0 ? 16 : p.scan_slots;
+    ScanHits sh;
+    int32_t* novf = c->buf<int32_t>("ln_scan_overflow", 1);
+    launch_leaf_scan_bf16_exact(c, qb, nq, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b,
+                                max_tiles, pair_leaf, hc, &sh, novf);
+    if (scan_overflows) *scan_overflows = novf;
     if (p.rerank_full) {
-      launch_select_rerank_full(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
-                                p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);
+      launch_select_rerank_full(c, nullptr, nullptr, nq, 0, 0, 0, nullptr, &sh, k, ix.perm.as<int32_t>(), ix.N, x, H,
+                                W, ix.w, p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);
       *dist_done = dist != nullptr;
     } else {
-      launch_merge_rerank_pca(c, pdd, pii, nq, P1, P1, 1, pair_leaf, k, qp, ix.dp, ix.zproj.as<float>(), zres,
-                              ix.perm.as<int32_t>(), ix.N, nullptr, nn);
+      launch_merge_rerank_pca(c, nullptr, nullptr, nq, 0, 0, 0, nullptr, &sh, k, qp, ix.dp, ix.zproj.as<float>(),
+                              zres, ix.perm.as<int32_t>(), ix.N, nullptr, nn);
     }
   }
   int32_t fbh = 0;

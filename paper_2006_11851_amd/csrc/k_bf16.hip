@@ -63,6 +63,33 @@ struct TopK {
   }
 };
 
+// (score, id) order: ties to the lower id
+__device__ __forceinline__ bool lex_lt(float a, int ia, float b, int ib) { return a < b || (a == b && ia < ib); }
+
+struct Top8Lex {
+  float d[8];
+  int i[8];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      d[t] = FLT_MAX;
+      i[t] = INT_MAX;
+    }
+  }
+  __device__ __forceinline__ void insert(float v, int id) {
+    bool lt[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) lt[t] = lex_lt(v, id, d[t], i[t]);
+#pragma unroll
+    for (int t = 7; t > 0; --t) {
+      d[t] = lt[t - 1] ? d[t - 1] : (lt[t] ? v : d[t]);
+      i[t] = lt[t - 1] ? i[t - 1] : (lt[t] ? id : i[t]);
+    }
+    d[0] = lt[0] ? v : d[0];
+    i[0] = lt[0] ? id : i[0];
+  }
+};
+
 constexpr int BB_WAVES = 8;
 constexpr int BB_QPB = BB_WAVES * 64;  // queries per block
 constexpr int BB_STAGE = 128;          // exemplar rows per LDS stage
@@ -398,18 +425,160 @@ __device__ __forceinline__ void stage_compute_cls_full(const BruteSmem<KS>& S, i
     for (int c = 0; c < 8; ++c) update(accp[qt], qt, c, tlast);
 }
 
-// BF16 scan of leaves for (query, leaf) pairs: tile = (leaf, LS_QPB pairs
-// of the bucketed order); rows = the leaf's members (contiguous in leaf order);
-// per pair the top-8 (score, leaf position).  Waves without pairs skip the
-// matrix work but still help stage the rows.
-template <int KS>
+// ---------------------------------------------------------------------------
+// Exact BF16 top-8 of the learned form's leaf scans, in two passes over the
+// bucketed (query, leaf) pairs.  Scores order lexicographically by (score,
+// leaf position); the position breaks exact ties (flat texels repeat whole
+// windows), and leaves keep their members in ascending exemplar id.
+//
+// Pass 1 (bound): each pair keeps its 16 class minima (rows i % 16 fixed,
+// each with the 32-row tile of its first occurrence).  The classes are
+// disjoint, so the 8th smallest class key is an upper bound on the pair's
+// 8th smallest key; the query's bound tau is the smallest over its pairs.
+// Pass 2 (collect): the same products again; every row whose key is at most
+// tau is written to the lane's own slots of its (pair, half) - on average
+// about ten rows per query in all.  At least 8 rows qualify, so the 8
+// smallest collected keys are the exact top-8 of the scanned members.  A
+// (pair, half) with more rows than slots sends its query to a per-query
+// pass with the same matrix products (identical scores) and a full sort.
+
+// order-preserving 64-bit key of (score, position): the score's bits mapped
+// so that unsigned order is float order, the position below them
+__device__ __forceinline__ uint64_t score_key(float v, int pos) {
+  uint32_t u = __float_as_uint(v);
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)u << 32) | (uint32_t)pos;
+}
+__device__ __forceinline__ float key_score(uint64_t k) {
+  uint32_t u = (uint32_t)(k >> 32);
+  u = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+  return __uint_as_float(u);
+}
+__device__ __forceinline__ int key_pos(uint64_t k) { return (int)(uint32_t)k; }
+__device__ __forceinline__ void cmp_swap(uint64_t& a, uint64_t& b) {
+  const bool s = b < a;
+  const uint64_t lo = s ? b : a;
+  b = s ? a : b;
+  a = lo;
+}
+// the 19-comparator sorting network for 8 keys (ascending)
+__device__ __forceinline__ void sort8(uint64_t (&k)[8]) {
+  cmp_swap(k[0], k[2]); cmp_swap(k[1], k[3]); cmp_swap(k[4], k[6]); cmp_swap(k[5], k[7]);
+  cmp_swap(k[0], k[4]); cmp_swap(k[1], k[5]); cmp_swap(k[2], k[6]); cmp_swap(k[3], k[7]);
+  cmp_swap(k[0], k[1]); cmp_swap(k[2], k[3]); cmp_swap(k[4], k[5]); cmp_swap(k[6], k[7]);
+  cmp_swap(k[2], k[4]); cmp_swap(k[3], k[5]);
+  cmp_swap(k[1], k[4]); cmp_swap(k[3], k[6]);
+  cmp_swap(k[1], k[2]); cmp_swap(k[3], k[4]); cmp_swap(k[5], k[6]);
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const int lo = __shfl_xor((int)(uint32_t)v, m, 64);
+  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+constexpr int LS_HC_MAX = 16;  // collect slots per (pair, half-lane)
+
+struct LeafScanOut {
+  // pass 1
+  uint64_t* pair_tau;  // [pairs] upper bound on the pair's 8th smallest key
+  // pass 2
+  const uint64_t* tau_q;  // [nq] smallest bound over the query's pairs
+  int2* hits;             // [pairs][2][hs] (score bits, leaf position)
+  int32_t* hit_cnt;       // [pairs][2] rows collected (may exceed hc: overflow)
+  int hc;                 // slots the pass may fill per (pair, half), <= hs
+  int hs;                 // slot stride, >= 8 (the per-query pass writes 8)
+};
+
+// The collected rows of a query, as the re-rank kernels read them.
+struct HitLists {
+  const int2* hits;         // null: the kernels read sorted part lists instead
+  const int32_t* hit_cnt;
+  const int32_t* pair_leaf; // [nq * P]; pairs with a negative leaf were not scanned
+  int P, hs;
+};
+
+// top <- the 8 smallest (score, position) keys among the query's collected rows
+__device__ __forceinline__ void top8_from_hits(Top8Lex& top, const HitLists& L, int64_t q) {
+  for (int j = 0; j < L.P; ++j) {
+    const int64_t p = q * L.P + j;
+    if (L.pair_leaf[p] < 0) continue;
+    for (int hh = 0; hh < 2; ++hh) {
+      const int n = L.hit_cnt[2 * p + hh];
+      const int2* hp = L.hits + (2 * p + hh) * L.hs;
+      for (int e = 0; e < n; ++e) {
+        const int2 v = hp[e];
+        const float sv = __int_as_float(v.x);
+        if (lex_lt(sv, v.y, top.d[7], top.i[7])) top.insert(sv, v.y);
+      }
+    }
+  }
+}
+
+// Pass 2 over one stage: products, then every row at or below the query's
+// bound goes to the lane's slots.  A wave rarely holds such a row in a tile
+// (the tile minimum is tested first).
+template <int KS, bool FULL>
+__device__ __forceinline__ void stage_collect(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
+                                              const float (&tv)[2], const int (&tp)[2], int (&cnt)[2],
+                                              int2* const (&hb)[2], int hc, int pos0, int lane, int nvalid,
+                                              int row_end) {
+#pragma unroll
+  for (int t = 0; t < BB_STAGE / 32; ++t) {
+    if (!FULL && t * 32 >= nvalid) break;
+    bf16x8 A[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
+      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+    floatx16 cinit;
+    const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
+      cinit[4 * g + 0] = z4.x;
+      cinit[4 * g + 1] = z4.y;
+      cinit[4 * g + 2] = z4.z;
+      cinit[4 * g + 3] = z4.w;
+    }
+    floatx16 acc[2] = {cinit, cinit};
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+      for (int qt = 0; qt < 2; ++qt)
+        acc[qt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc[qt], 0, 0, 0);
+    const int tpos = pos0 + t * 32 + 4 * (lane >> 5);
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt) {
+      float m = acc[qt][0];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) m = __builtin_fminf(m, acc[qt][r]);
+      if (__any(m <= tv[qt])) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float v = acc[qt][r];
+          const int pos = tpos + 8 * (r >> 2) + (r & 3);
+          if (v <= tv[qt] && pos < row_end && (v < tv[qt] || pos <= tp[qt])) {
+            if (cnt[qt] < hc) hb[qt][cnt[qt]] = make_int2(__float_as_int(v), pos);
+            ++cnt[qt];
+          }
+        }
+      }
+    }
+  }
+}
+
+// One tile = (leaf, LS_QPB pairs of the bucketed order); rows = the leaf's
+// members (contiguous in leaf order).  Waves without pairs skip the matrix
+// work but still help stage the rows.
+template <int KS, int PASS>
 __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const uint16_t* __restrict__ Qb, int P,
                                                const uint16_t* __restrict__ Zb, const float* __restrict__ zbn,
                                                const int32_t* __restrict__ leaf_off,
                                                const int32_t* __restrict__ qoff, const int32_t* __restrict__ order,
-                                               const int2* __restrict__ tiles, float* __restrict__ pair_d,
-                                               int32_t* __restrict__ pair_i) {
+                                               const int2* __restrict__ tiles, const LeafScanOut& o) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5;
   const int2 tile = tiles[t];
   const int row_begin = leaf_off[tile.x], row_end = leaf_off[tile.x + 1];
   const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
@@ -424,27 +593,48 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
   const bool wave_active = tile.y + wave * 64 < pend;
   bf16x8 B[2][KS];
   int pr[2];
+  int64_t qid[2];
 #pragma unroll
   for (int qt = 0; qt < 2; ++qt) {
     const int pos = tile.y + wave * 64 + qt * 32 + (lane & 31);
     pr[qt] = pos < pend ? order[pos] : -1;
     // a lane without a pair reads query 0: its results are never written
-    const int64_t q = pr[qt] >= 0 ? pr[qt] / P : 0;
+    qid[qt] = pr[qt] >= 0 ? pr[qt] / P : 0;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      const uint4 u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + (lane >> 5)];
+      const uint4 u = reinterpret_cast<const uint4*>(Qb + qid[qt] * (KS * 16))[2 * kk + (lane >> 5)];
       B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
   }
   float cm[2][8];
   int ct[2][8];
+  float tv[2];
+  int tp[2], cnt[2];
+  int2* hb[2];
+  if constexpr (PASS == 1) {
 #pragma unroll
-  for (int qt = 0; qt < 2; ++qt)
+    for (int qt = 0; qt < 2; ++qt)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      cm[qt][c] = FLT_MAX;
-      ct[qt][c] = -1;
+      for (int c = 0; c < 8; ++c) {
+        cm[qt][c] = FLT_MAX;
+        ct[qt][c] = -1;
+      }
+  } else {
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt) {
+      cnt[qt] = 0;
+      if (pr[qt] >= 0) {
+        const uint64_t k = o.tau_q[qid[qt]];
+        tv[qt] = key_score(k);
+        tp[qt] = key_pos(k);
+        hb[qt] = o.hits + ((int64_t)pr[qt] * 2 + h) * o.hs;
+      } else {  // nothing is ever collected for a lane without a pair
+        tv[qt] = -INFINITY;
+        tp[qt] = -1;
+        hb[qt] = o.hits;
+      }
     }
+  }
   if (row_begin < row_end) {
     // stages load two ahead, as in the brute-force kernel
     stage_store<KS, LS_QPB>(R[0], sm, 0, tid, row_begin, row_end);
@@ -459,8 +649,14 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
         stage_load<KS, LS_QPB>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
         if (wave_active) {
           const int nvalid = min(BB_STAGE, row_end - row_begin - st * BB_STAGE);
-          if (nvalid == BB_STAGE) stage_compute_cls_full<KS>(sm, u, B, cm, ct, row_begin + st * BB_STAGE, lane);
-          else stage_compute_cls<KS, false>(sm, u, B, cm, ct, row_begin + st * BB_STAGE, lane, nvalid);
+          const int p0 = row_begin + st * BB_STAGE;
+          if constexpr (PASS == 1) {
+            if (nvalid == BB_STAGE) stage_compute_cls_full<KS>(sm, u, B, cm, ct, p0, lane);
+            else stage_compute_cls<KS, false>(sm, u, B, cm, ct, p0, lane, nvalid);
+          } else {
+            if (nvalid == BB_STAGE) stage_collect<KS, true>(sm, u, B, tv, tp, cnt, hb, o.hc, p0, lane, nvalid, row_end);
+            else stage_collect<KS, false>(sm, u, B, tv, tp, cnt, hb, o.hc, p0, lane, nvalid, row_end);
+          }
         }
         if (st + 1 < nstages)
           stage_store<KS, LS_QPB>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
@@ -468,86 +664,46 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       }
     }
   }
-  // rows of class c in half h of a tile: i = 8 (c / 4) + 4 h + (c % 4), and i + 16
-  const int h = lane >> 5;
+  if constexpr (PASS == 1) {
+    // rows of class c in half h of a tile: i = 8 (c / 4) + 4 h + (c % 4) and
+    // i + 16; a class's key takes the later of the two rows of its tile (an
+    // upper bound on the position of its minimum) unless that row is past
+    // the leaf.  The pair's bound: the 8th smallest of its 16 class keys.
 #pragma unroll
-  for (int qt = 0; qt < 2; ++qt) {
-    // the 4 best of this lane's 8 classes, then the 4 best of the two halves
-    float bv[4];
-    int bt[4], bc[4];
+    for (int qt = 0; qt < 2; ++qt) {
+      uint64_t k[8];
 #pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) {
-      bv[k2] = FLT_MAX;
-      bt[k2] = -1;
-      bc[k2] = 0;
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      float v = cm[qt][c];
-      int tt = ct[qt][c], cc = c;
-#pragma unroll
-      for (int k2 = 0; k2 < 4; ++k2) {  // insertion into a sorted list of 4
-        const bool sw = v < bv[k2];
-        const float fv = sw ? bv[k2] : v;
-        const int ft = sw ? bt[k2] : tt, fc = sw ? bc[k2] : cc;
-        bv[k2] = sw ? v : bv[k2];
-        bt[k2] = sw ? tt : bt[k2];
-        bc[k2] = sw ? cc : bc[k2];
-        v = fv;
-        tt = ft;
-        cc = fc;
+      for (int c = 0; c < 8; ++c) {
+        const int ra = ct[qt][c] + 8 * (c >> 2) + 4 * h + (c & 3);
+        const int rk = ra + 16 < row_end ? ra + 16 : ra;
+        k[c] = ct[qt][c] < 0 ? score_key(FLT_MAX, INT_MAX) : score_key(cm[qt][c], rk);
       }
-    }
-    int rowa[4];
+      sort8(k);
+      uint64_t ok[8];
 #pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) rowa[k2] = bt[k2] < 0 ? -1 : bt[k2] + 8 * (bc[k2] >> 2) + 4 * h + (bc[k2] & 3);
-    float ov[4];
-    int orow[4];
+      for (int c = 0; c < 8; ++c) ok[c] = shfl_xor_u64(k[c], 32);
+      // the 8th smallest of two sorted lists: min over splits of the larger ends
+      uint64_t best = ~0ull;
 #pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) {
-      ov[k2] = __shfl_xor(bv[k2], 32, 64);
-      orow[k2] = __shfl_xor(rowa[k2], 32, 64);
-    }
-    if (lane < 32 && pr[qt] >= 0) {
-      float* pd = pair_d + (int64_t)pr[qt] * BB_TOPK;
-      int32_t* pi = pair_i + (int64_t)pr[qt] * BB_TOPK;
-      int a = 0, b = 0;
-#pragma unroll
-      for (int k2 = 0; k2 < 4; ++k2) {  // merge two sorted lists of 4, keep 4
-        float va = FLT_MAX, vb = FLT_MAX;
-        int ra = -1, rb = -1;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (u == a) {
-            va = bv[u];
-            ra = rowa[u];
-          }
-          if (u == b) {
-            vb = ov[u];
-            rb = orow[u];
-          }
-        }
-        const bool take_a = va < vb || (va == vb && ra < rb);
-        const float v = take_a ? va : vb;
-        const int r = take_a ? ra : rb;
-        if (take_a) ++a;
-        else ++b;
-        const bool ok = r >= 0;
-        const bool ok2 = ok && r + 16 < row_end;
-        pd[2 * k2] = ok ? v : FLT_MAX;
-        pi[2 * k2] = ok ? r : INT_MAX;
-        pd[2 * k2 + 1] = ok2 ? v : FLT_MAX;
-        pi[2 * k2 + 1] = ok2 ? r + 16 : INT_MAX;
+      for (int i = 0; i <= 8; ++i) {
+        const uint64_t a = i > 0 ? k[i - 1] : 0ull;
+        const uint64_t b = i < 8 ? ok[7 - i] : 0ull;
+        const uint64_t m = a > b ? a : b;
+        best = m < best ? m : best;
       }
+      if (h == 0 && pr[qt] >= 0) o.pair_tau[pr[qt]] = best;
     }
+  } else {
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt)
+      if (pr[qt] >= 0) o.hit_cnt[(int64_t)pr[qt] * 2 + h] = cnt[qt];
   }
 }
-
 
 // Persistent form: one block per compute unit takes tiles from a counter
 // (zeroed before the launch) until the list is done, so no block waits for
 // the dispatcher between tiles of very different cost.
-template <int KS>
+template <int KS, int PASS>
 __global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __restrict__ Qb, int P,
                                                         const uint16_t* __restrict__ Zb,
                                                         const float* __restrict__ zbn,
@@ -556,8 +712,7 @@ __global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __res
                                                         const int32_t* __restrict__ order,
                                                         const int2* __restrict__ tiles,
                                                         const int32_t* __restrict__ ntiles,
-                                                        int32_t* __restrict__ next, float* __restrict__ pair_d,
-                                                        int32_t* __restrict__ pair_i) {
+                                                        int32_t* __restrict__ next, LeafScanOut o) {
   __shared__ BruteSmem<KS> sm;
   __shared__ int s_t;
   const int nt = *ntiles;
@@ -566,8 +721,123 @@ __global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __res
     __syncthreads();
     const int t = s_t;
     if (t >= nt) break;  // uniform per block; the counter only grows, so every block gets here
-    leaf_scan_tile<KS>(t, sm, Qb, P, Zb, zbn, leaf_off, qoff, order, tiles, pair_d, pair_i);
+    leaf_scan_tile<KS, PASS>(t, sm, Qb, P, Zb, zbn, leaf_off, qoff, order, tiles, o);
     __syncthreads();  // LDS buffers and s_t free for the next tile
+  }
+}
+
+// tau[q] = the smallest pass-1 bound over the query's scanned pairs
+__global__ __launch_bounds__(256) void k_pair_tau_min(const int32_t* __restrict__ pair_leaf,
+                                                      const uint64_t* __restrict__ pair_tau, int64_t nq, int P,
+                                                      uint64_t* __restrict__ tau) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  uint64_t b = ~0ull;
+  for (int j = 0; j < P; ++j) {
+    const int64_t p = q * P + j;
+    if (pair_leaf[p] < 0) continue;
+    const uint64_t v = pair_tau[p];
+    b = v < b ? v : b;
+  }
+  tau[q] = b;
+}
+
+// queries with a (pair, half) that collected more rows than it has slots
+__global__ __launch_bounds__(256) void k_hit_overflow(const int32_t* __restrict__ pair_leaf,
+                                                      const int32_t* __restrict__ hit_cnt, int64_t nq, int P, int hc,
+                                                      int32_t* __restrict__ list, int32_t* __restrict__ n) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  bool over = false;
+  for (int j = 0; j < P; ++j) {
+    const int64_t p = q * P + j;
+    if (pair_leaf[p] < 0) continue;
+    over = over || hit_cnt[2 * p] > hc || hit_cnt[2 * p + 1] > hc;
+  }
+  if (over) list[atomicAdd(n, 1)] = (int32_t)q;
+}
+
+// The per-query exact top-8 for the overflowed queries: one wave per query
+// runs the same matrix products over every member of its scanned leaves (the
+// query in all 32 columns, so each half of the wave holds the same 16 rows
+// of a tile: identical scores to the tile kernels, whose products see the
+// same operands in the same order), keeps a sorted top-8 of (score,
+// position) per lane, merges the two halves and writes the 8 to the slots of
+// the query's first pair (count 8; the other counts 0).  Waves loop over the
+// list, whose length is read on the device.
+template <int KS>
+__global__ __launch_bounds__(256) void k_scan_top8_exact(const uint16_t* __restrict__ Qb, int P,
+                                                         const uint16_t* __restrict__ Zb,
+                                                         const float* __restrict__ zbn,
+                                                         const int32_t* __restrict__ leaf_off,
+                                                         const int32_t* __restrict__ pair_leaf,
+                                                         const int32_t* __restrict__ list,
+                                                         const int32_t* __restrict__ n, int2* __restrict__ hits,
+                                                         int32_t* __restrict__ hit_cnt, int hs) {
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int nw = gridDim.x * (blockDim.x >> 6);
+  const int h = lane >> 5;
+  const int cnt = *n;
+  for (int i = gw; i < cnt; i += nw) {
+    const int64_t q = list[i];
+    bf16x8 B[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const uint4 u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + h];
+      B[kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+    Top8Lex top;
+    top.init();
+    for (int j = 0; j < P; ++j) {
+      const int l = pair_leaf[q * P + j];
+      if (l < 0) continue;
+      const int rb = leaf_off[l], re = leaf_off[l + 1];
+      for (int t0 = rb; t0 < re; t0 += 32) {
+        const int64_t row = min(t0 + (lane & 31), re - 1);
+        bf16x8 A[KS];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+          const uint4 u = reinterpret_cast<const uint4*>(Zb + row * (KS * 16))[2 * kk + h];
+          A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+        }
+        floatx16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int pr = t0 + 8 * (r >> 2) + 4 * h + (r & 3);
+          acc[r] = pr < re ? zbn[pr] : FLT_MAX;
+        }
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[kk], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int pr = t0 + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (pr < re && lex_lt(acc[r], pr, top.d[7], top.i[7])) top.insert(acc[r], pr);
+        }
+      }
+    }
+    // lane 0 merges the other half's list (lane 32) into its own
+    float od[8];
+    int oi[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      od[t] = __shfl_xor(top.d[t], 32, 64);
+      oi[t] = __shfl_xor(top.i[t], 32, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (lex_lt(od[t], oi[t], top.d[7], top.i[7])) top.insert(od[t], oi[t]);
+      const int64_t p0 = q * P;  // the first proposal: always a scanned pair
+      int m = 0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (top.i[t] != INT_MAX) hits[(p0 * 2) * hs + m++] = make_int2(__float_as_int(top.d[t]), top.i[t]);
+      for (int j = 0; j < P; ++j) {
+        hit_cnt[(q * P + j) * 2] = j == 0 ? m : 0;
+        hit_cnt[(q * P + j) * 2 + 1] = 0;
+      }
+    }
   }
 }
 
@@ -601,17 +871,72 @@ void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16
   check_launch("k_brute_bf16_topk");
 }
 
-void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb, const float* zbn, int dk,
-                           const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* pair_d,
-                           int32_t* pair_i) {
-  ProfScope ps(c, "leaf_scan_bf16");
-  if (max_tiles == 0) return;
+static HitLists hit_lists(const ScanHits* sh) {
+  HitLists h{};
+  if (sh) {
+    h.hits = sh->hits;
+    h.hit_cnt = sh->hit_cnt;
+    h.pair_leaf = sh->pair_leaf;
+    h.P = sh->P;
+    h.hs = sh->hs;
+  }
+  return h;
+}
+
+void launch_leaf_scan_bf16_exact(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
+                                 int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles,
+                                 const int32_t* pair_leaf, int hc, ScanHits* sh, int32_t* n_overflow) {
+  PTS_REQUIRE(hc >= 0 && hc <= LS_HC_MAX, PTS_ERR_ARG, "collect slots must be 0..16");
+  const int hs = std::max(hc, 8);
+  const int64_t npairs = nq * P;
+  LeafScanOut o{};
+  o.pair_tau = c->buf<uint64_t>("ls_pair_tau", (size_t)std::max<int64_t>(1, npairs));
+  uint64_t* tau_q = c->buf<uint64_t>("ls_tau_q", (size_t)std::max<int64_t>(1, nq));
+  o.tau_q = tau_q;
+  o.hits = c->buf<int2>("ls_hits", (size_t)std::max<int64_t>(1, npairs * 2 * hs));
+  o.hit_cnt = c->buf<int32_t>("ls_hit_cnt", (size_t)std::max<int64_t>(1, npairs * 2));
+  o.hc = hc;
+  o.hs = hs;
+  sh->hits = o.hits;
+  sh->hit_cnt = o.hit_cnt;
+  sh->pair_leaf = pair_leaf;
+  sh->P = P;
+  sh->hs = hs;
+  if (nq == 0 || max_tiles == 0) return;
   int32_t* next = c->buf<int32_t>("ls_next_tile", 1);
-  launch_zero_i32(c, next, 1);
   const int grid = std::min(max_tiles, c->n_cu);
-  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_leaf_scan_bf16<KSC>, dim3(grid), dim3(LS_QPB), 0, c->stream, Qb, P, Zb, zbn,
-                                       leaf_off, b.off, b.order, b.tiles, b.ntiles, next, pair_d, pair_i));
-  check_launch("k_leaf_scan_bf16");
+  {
+    ProfScope ps(c, "leaf_scan_bf16");
+    launch_zero_i32(c, next, 1);
+    PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_leaf_scan_bf16<KSC, 1>), dim3(grid), dim3(LS_QPB), 0, c->stream, Qb, P,
+                                         Zb, zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, next, o));
+    check_launch("k_leaf_scan_bf16 (bound)");
+  }
+  {
+    ProfScope ps(c, "scan_tau_min");
+    hipLaunchKernelGGL(k_pair_tau_min, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf,
+                       o.pair_tau, nq, P, tau_q);
+    check_launch("k_pair_tau_min");
+  }
+  {
+    ProfScope ps(c, "leaf_scan_bf16_collect");
+    launch_zero_i32(c, next, 1);
+    PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_leaf_scan_bf16<KSC, 2>), dim3(grid), dim3(LS_QPB), 0, c->stream, Qb, P,
+                                         Zb, zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, next, o));
+    check_launch("k_leaf_scan_bf16 (collect)");
+  }
+  {
+    ProfScope ps(c, "scan_overflow");
+    int32_t* list = c->buf<int32_t>("ls_ovf_list", (size_t)nq);
+    launch_zero_i32(c, n_overflow, 1);
+    hipLaunchKernelGGL(k_hit_overflow, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf,
+                       o.hit_cnt, nq, P, hc, list, n_overflow);
+    check_launch("k_hit_overflow");
+    // waves loop over the list (its length is only known on the device)
+    PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_scan_top8_exact<KSC>, dim3(c->n_cu), dim3(256), 0, c->stream, Qb, P, Zb,
+                                         zbn, leaf_off, pair_leaf, list, n_overflow, o.hits, o.hit_cnt, hs));
+    check_launch("k_scan_top8_exact");
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -624,7 +949,7 @@ template <int DP>
 __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restrict__ part_d,
                                                           const int32_t* __restrict__ part_i, int64_t nq, int S,
                                                           int64_t qs, int64_t ss, const int32_t* __restrict__ valid,
-                                                          int k, const float* __restrict__ Qp,
+                                                          HitLists hl, int k, const float* __restrict__ Qp,
                                                           const float* __restrict__ Zp,
                                                           const float* __restrict__ zres,
                                                           const int32_t* __restrict__ perm, int64_t N,
@@ -632,24 +957,18 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
                                                           int32_t* __restrict__ nn) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  TopK<BB_TOPK> top;
+  Top8Lex top;
   top.init();
-  for (int s = 0; s < S; ++s) {
-    const int64_t row = q * qs + (int64_t)s * ss;
-    if (valid && valid[row] < 0) continue;
-    const float* pd = part_d + row * BB_TOPK;
-    const int32_t* pi = part_i + row * BB_TOPK;
-    for (int t = 0; t < BB_TOPK; ++t) {
-      const float v = pd[t];
-      const int id = pi[t];
-      // keep (v, id) order: equal distances keep the lower position
-      if (v < top.d[BB_TOPK - 1] || (v == top.d[BB_TOPK - 1] && id < top.i[BB_TOPK - 1])) {
-        if (v == top.d[BB_TOPK - 1]) {
-          top.d[BB_TOPK - 1] = FLT_MAX;  // make room, re-insert below
-          top.i[BB_TOPK - 1] = INT_MAX;
-        }
-        top.insert(v, id);
-      }
+  if (hl.hits) {
+    top8_from_hits(top, hl, q);
+  } else {
+    for (int s = 0; s < S; ++s) {
+      const int64_t row = q * qs + (int64_t)s * ss;
+      if (valid && valid[row] < 0) continue;
+      const float* pd = part_d + row * BB_TOPK;
+      const int32_t* pi = part_i + row * BB_TOPK;
+      for (int t = 0; t < BB_TOPK; ++t)
+        if (lex_lt(pd[t], pi[t], top.d[7], top.i[7])) top.insert(pd[t], pi[t]);
     }
   }
   if (!nn) {  // candidates only (a full-D re-rank follows)
@@ -698,13 +1017,15 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
 }
 
 void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
-                             int64_t ss, const int32_t* valid, int k, const float* Qp, int dp, const float* Zp,
-                             const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out, int32_t* nn) {
+                             int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const float* Qp, int dp,
+                             const float* Zp, const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out,
+                             int32_t* nn) {
   ProfScope ps(c, "merge_rerank");
   if (nq == 0) return;
   PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
+  const HitLists hl = hit_lists(sh);
   PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_merge_rerank_pca<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
-                                       c->stream, part_d, part_i, nq, S, qs, ss, valid, k, Qp, Zp, zres, perm, N,
+                                       c->stream, part_d, part_i, nq, S, qs, ss, valid, hl, k, Qp, Zp, zres, perm, N,
                                        cand_out, nn));
   check_launch("k_merge_rerank_pca");
 }
@@ -719,32 +1040,6 @@ void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i,
 // lower exemplar id).  Writes nn and, if dist is given, the full-D distance
 // of the winner.
 
-__device__ __forceinline__ bool lex_lt(float a, int ia, float b, int ib) { return a < b || (a == b && ia < ib); }
-
-struct Top8Lex {
-  float d[8];
-  int i[8];
-  __device__ __forceinline__ void init() {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      d[t] = FLT_MAX;
-      i[t] = INT_MAX;
-    }
-  }
-  __device__ __forceinline__ void insert(float v, int id) {
-    bool lt[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) lt[t] = lex_lt(v, id, d[t], i[t]);
-#pragma unroll
-    for (int t = 7; t > 0; --t) {
-      d[t] = lt[t - 1] ? d[t - 1] : (lt[t] ? v : d[t]);
-      i[t] = lt[t - 1] ? i[t - 1] : (lt[t] ? id : i[t]);
-    }
-    d[0] = lt[0] ? v : d[0];
-    i[0] = lt[0] ? id : i[0];
-  }
-};
-
 constexpr int SR_QPB = 256;
 
 // PK: the exemplar windows come from its 8-bit form (pk, srow), rebuilt as
@@ -753,7 +1048,7 @@ constexpr int SR_QPB = 256;
 template <bool PK>
 __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     const float* __restrict__ part_d, const int32_t* __restrict__ part_i, int64_t nq, int S, int64_t qs, int64_t ss,
-    const int32_t* __restrict__ valid, int k, const int32_t* __restrict__ perm, int64_t npos,
+    const int32_t* __restrict__ valid, HitLists hl, int k, const int32_t* __restrict__ perm, int64_t npos,
     const float4* __restrict__ x, int W, int w, int s, int cols, const float4* __restrict__ ex,
     const uint32_t* __restrict__ pk, const float* __restrict__ srow, int Hz, int Wz, int32_t* __restrict__ nn,
     float* __restrict__ dist) {
@@ -772,7 +1067,9 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     const int64_t q = q0 + tid;
     Top8Lex top;
     top.init();
-    if (q < nq) {
+    if (q < nq && hl.hits) {
+      top8_from_hits(top, hl, q);
+    } else if (q < nq) {
       for (int li = 0; li < S; ++li) {
         const int64_t row = q * qs + (int64_t)li * ss;
         if (valid && valid[row] < 0) continue;
@@ -908,7 +1205,8 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
 }
 
 void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
-                               int64_t ss, const int32_t* valid, int k, const int32_t* perm, int64_t npos,
+                               int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const int32_t* perm,
+                               int64_t npos,
                                const float* x, int H, int W, int w, int s, const float* ex, const uint32_t* ex_pk,
                                const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist) {
   ProfScope ps(c, "select_rerank_full");
@@ -916,13 +1214,14 @@ void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_
   PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
   PTS_REQUIRE(w >= 1 && w <= Hz && w <= Wz && w <= H && W % s == 0, PTS_ERR_ARG, "select_rerank_full: bad geometry");
   const dim3 grid((unsigned)ceil_div(nq, SR_QPB));
+  const HitLists hl = hit_lists(sh);
   if (ex_pk && ex_srow)
     hipLaunchKernelGGL(k_select_rerank_full<true>, grid, dim3(SR_QPB), 0, c->stream, part_d, part_i, nq, S, qs, ss,
-                       valid, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
+                       valid, hl, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
                        reinterpret_cast<const float4*>(ex), ex_pk, ex_srow, Hz, Wz, nn, dist);
   else
     hipLaunchKernelGGL(k_select_rerank_full<false>, grid, dim3(SR_QPB), 0, c->stream, part_d, part_i, nq, S, qs, ss,
-                       valid, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
+                       valid, hl, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
                        reinterpret_cast<const float4*>(ex), ex_pk, ex_srow, Hz, Wz, nn, dist);
   check_launch("k_select_rerank_full");
 }

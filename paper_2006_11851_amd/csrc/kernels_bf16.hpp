@@ -17,6 +17,16 @@ namespace pts {
     default: ::pts::fail(PTS_ERR_UNSUPPORTED, "padded PCA width must be 16/24/32/48/64/96/128");   \
   }
 
+// The rows the learned form's exact BF16 leaf scan collects per (query, leaf)
+// pair and half-wave: hits [pairs][2][hs] (score bits, leaf position),
+// hit_cnt [pairs][2]; a query's 8 smallest (score, position) keys among them
+// are the exact BF16 top-8 over its scanned leaves.
+struct ScanHits {
+  const int2* hits = nullptr;
+  const int32_t* hit_cnt = nullptr;
+  const int32_t* pair_leaf = nullptr;
+  int P = 0, hs = 0;
+};
 // number of exemplar splits for the brute-force kernel
 int brute_splits(int64_t nq);
 // partial top-8 (score, leaf position) per (split, query): part [S][nq][8]
@@ -26,22 +36,28 @@ void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16
 // part [..][8]; lists with valid[row] < 0 skipped), re-rank the best k in
 // FP32 PCA space; nn = exemplar id.  cand_out (optional) [nq][8]: the k
 // candidates as exemplar ids (-1 beyond k)
+// (sh non-null: the candidates are the 8 smallest keys of the collected rows instead)
 void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
-                             int64_t ss, const int32_t* valid, int k, const float* Qp, int dp, const float* Zp,
-                             const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out, int32_t* nn);
+                             int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const float* Qp, int dp,
+                             const float* Zp, const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out,
+                             int32_t* nn);
 // pairs per tile of the leaf scan (the bucketing chunk)
 int leaf_scan_bf16_chunk();
-// 8 class-minimum candidates (score, leaf position) of each bucketed (query,
-// leaf) pair over the leaf's members: pair [nq*P][8]
-void launch_leaf_scan_bf16(Ctx* c, const uint16_t* Qb, int P, const uint16_t* Zb, const float* zbn, int dk,
-                           const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* pair_d,
-                           int32_t* pair_i);
+// Exact BF16 top-8 of every query over the members of its bucketed leaves
+// (pair_leaf [nq*P], negative = not scanned): pass 1 bounds the 8th key per
+// pair, pass 2 collects the rows within the query's bound (hc slots per
+// pair and half, 0..16), queries with more rows go to a per-query pass.
+// n_overflow: device int32, the number of such queries.
+void launch_leaf_scan_bf16_exact(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
+                                 int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles,
+                                 const int32_t* pair_leaf, int hc, ScanHits* sh, int32_t* n_overflow);
 // merge S partial lists per query as above and re-rank the best k by the
 // full-D FP32 distance gathered from the images x [H][W][4] and ex
 // [Hz][Wz][4] (read from its 8-bit form ex_pk / ex_srow when given: the same
 // values); nn = exemplar id, dist (optional) = its full-D distance
 void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
-                               int64_t ss, const int32_t* valid, int k, const int32_t* perm, int64_t npos,
+                               int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const int32_t* perm,
+                               int64_t npos,
                                const float* x, int H, int W, int w, int s, const float* ex, const uint32_t* ex_pk,
                                const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist);
 

@@ -199,6 +199,7 @@ int pts_estep(pts_ctx* c, const float* x, int H, int W, const pts_estep_params* 
     if (st) {
       st->nq = s.nq;
       st->fallbacks = s.fallbacks;
+      st->scan_overflows = s.scan_overflows;
       st->ms = s.ms;
     }
   });

@@ -107,11 +107,12 @@ class pts_estep_params(C.Structure):
         ("n_proposals", C.c_int),
         ("margin", C.c_float),
         ("residual", C.c_int),
+        ("scan_slots", C.c_int),
     ]
 
 
 class pts_estep_stats(C.Structure):
-    _fields_ = [("nq", C.c_int64), ("fallbacks", C.c_int64), ("ms", C.c_double)]
+    _fields_ = [("nq", C.c_int64), ("fallbacks", C.c_int64), ("scan_overflows", C.c_int64), ("ms", C.c_double)]
 
 
 class pts_mstep_params(C.Structure):
@@ -405,13 +406,13 @@ class Context:
         return ((H - w) // s + 1) * (W // s)
 
     def estep(self, x, w, stride, mode="tree", topk=8, rerank_full=0, n_proposals=4, margin=0.2, residual=0,
-              stats=False, nn=None, dist=None):
+              stats=False, nn=None, dist=None, scan_slots=0):
         H, W = x.shape[:2]
         nq = self.nq(H, W, w, stride)
         nn = self._i32(nq) if nn is None else nn
         dist = self._f32(nq) if dist is None else dist
         p = pts_estep_params(MODES[mode] if isinstance(mode, str) else mode, w, stride, topk, rerank_full,
-                             n_proposals, margin, int(residual))
+                             n_proposals, margin, int(residual), int(scan_slots))
         st = pts_estep_stats()
         self._ok(lib().pts_estep(self._h, _ptr(x), H, W, C.byref(p), _ptr(nn), _ptr(dist),
                                  C.byref(st) if stats else None))

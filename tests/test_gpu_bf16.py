@@ -82,12 +82,13 @@ def test_brute_bf16_ragged_and_rerank_full(gpu_ctx):
     nn_o, _ = bf16.rerank(Q, Zm, cand)
     ok, same, _ = parity.nn_agreement(Q, Zm, _np(nn), nn_o)
     assert ok >= 0.999, (ok, same)
+    # fewer candidates: the winner must be the outcome of some top-k that FP32
+    # evaluation of the scores can produce (scores within its error bound swap)
+    allz = [np.arange(Zp.shape[0])] * Qp.shape[0]
     for k in (1, 3):
         nnk, _ = gpu_ctx.estep(x, w, s, mode="brute_bf16", topk=k)
-        cand_k = cand[:, :k]
-        nn_ok, _ = bf16.rerank(Qp, Zp, cand_k)
-        ok, same, _ = parity.nn_agreement(Qp, Zp, _np(nnk), nn_ok)
-        assert ok >= 0.995, (k, ok, same)
+        valid = helpers.topk_rerank_validity(Qp, Zp, None, allz, _np(nnk), k)
+        assert valid.mean() >= 0.999, (k, valid.mean())
 
 
 def test_brute_bf16_energy_gap_ex512_w16(gpu_ctx):
@@ -135,7 +136,7 @@ def test_brute_bf16_energy_gap_ex512_w16(gpu_ctx):
     # sampled parity against the oracle's BF16 form
     Qp = _np(gpu_ctx.project(x, s)).astype(np.float64)
     Zp = _np(gpu_ctx.exemplar_projection()).astype(np.float64)
-    sample = np.sort(np.random.default_rng(1).choice(Qp.shape[0], 128, replace=False))
-    nn_o, _ = bf16.brute_nn(Qp[sample], Zp, 8)
-    ok, same, _ = parity.nn_agreement(Qp[sample], Zp, _np(nn_b)[sample], nn_o)
-    assert ok >= 0.99, (ok, same)
+    sample = np.sort(np.random.default_rng(1).choice(Qp.shape[0], 512, replace=False))
+    valid = helpers.topk_rerank_validity(Qp[sample], Zp, None, [np.arange(Zp.shape[0])] * sample.size,
+                                         _np(nn_b)[sample], 8)
+    assert valid.mean() >= 0.999, valid.mean()

@@ -10,8 +10,12 @@ elsewhere), in FP64:
   within the tie tolerance, descent near-ties excused, winner distances from
   the images;
 * BF16 + learned (residual ranking, full-D re-rank of 8 candidates): the
-  candidate rule over the proposed leaves (plus the tree's leaf below margin
-  0.2), then the full-D re-rank."""
+  exact BF16 top-8 over the members of the proposed leaves (plus the tree's
+  leaf below margin 0.2), then the full-D re-rank; an id is accepted when
+  it is the outcome of some top-8 that FP32 evaluation of the scores can
+  produce (scores within their FP32 error bound may swap), with a network
+  trained like the benchmark's, so that about a fifth of the queries add
+  the tree's leaf."""
 import numpy as np
 import pytest
 
@@ -42,10 +46,10 @@ def headline(gpu_ctx):
     x = ctx.rgbs_from_u8(init, 0.5)
     nq = ctx.nq(H, H, w, s)
     assert nq == 1045504
-    # a briefly trained network: the parity below does not depend on its quality
-    q, lab = training.collect_pairs_sampled(ctx, x, w, s, 1, 65536, seed=1)
+    # trained like the benchmark's network (pairs from six plain iterations)
+    q, lab = training.collect_pairs_sampled(ctx, x, w, s, 6, 65536, seed=1)
     ctx.mlp_init(info.d, 256, info.n_leaves, seed=0)
-    training.train(ctx, q, lab, epochs=2, batch=4096, lr=2e-3, log_every=0)
+    training.train(ctx, q, lab, epochs=6, batch=4096, lr=2e-3, log_every=0)
     sample = np.sort(np.random.default_rng(11).choice(nq, 1024, replace=False))
     g = ctx.export_index()
     Z = vectors.rgbs(ex, 0.5)
@@ -83,21 +87,14 @@ def test_headline_learned_bf16_sampled(headline):
     L, M, DL = _np(leaves)[sample], _np(margin)[sample], _np(dleaf)[sample]
     Zp, Qp = S["Zp"], S["Qp"]
     off = obf16.residual(S["Zm"], S["g"]["mu"], Zp)  # residual ranking offsets, every window
-    cand = []
-    for i in range(len(sample)):
-        ls = list(L[i]) + ([int(DL[i])] if not (M[i] >= 0.2) and DL[i] not in L[i] else [])
-        pos, sc = [], []
-        for l in ls:
-            mem = t.leaf_members(l)
-            p_, s_ = obf16.class_candidates(Qp[i], Zp[mem], off[mem])
-            pos.append(mem[p_])
-            sc.append(s_)
-        pos, sc = np.concatenate(pos), np.concatenate(sc)
-        cand.append(pos[np.lexsort((pos, sc))[:8]])
-    nn_o, _ = obf16.rerank(S["Q"], S["Zm"], cand)
+    lists = [list(L[i]) + ([int(DL[i])] if not (M[i] >= 0.2) and DL[i] not in L[i] else [])
+             for i in range(len(sample))]
     got = _np(nn)[sample]
-    ok, same, _ = parity.nn_agreement(S["Q"], S["Zm"], got, nn_o)
-    print(f"learned bf16: agreement {ok:.4f} (exact {same:.4f}), fallbacks {np.mean(~(M >= 0.2)):.3f}", flush=True)
-    assert ok >= 0.995, (ok, same)
+    valid = helpers.topk_rerank_validity(Qp, Zp, t, lists, got, 8, offset=off, Q_full=S["Q"], Zm=S["Zm"],
+                                         mu=S["g"]["mu"])
+    fb = float(np.mean(~(M >= 0.2)))
+    print(f"learned bf16: valid outcomes {valid.mean():.4f}, fallbacks {fb:.3f}", flush=True)
+    assert valid.mean() >= 0.999, valid.mean()
+    assert 0.05 <= fb <= 0.5, fb
     dg = parity.sqdist_rows(S["Q"], S["Zm"], got)
     assert np.allclose(_np(dist)[sample], np.sqrt(dg), rtol=1e-5, atol=1e-6)

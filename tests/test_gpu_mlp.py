@@ -182,18 +182,19 @@ def test_learned_search_teacher_forced(learned_c1, mode):
     if mode == "learned":
         nn_o, _ = tree.search_leaves(Qp, Zp, t, lists)
     else:
-        cand = []
-        for i, ls in enumerate(lists):
-            pos, sc = [], []
-            for l in ls:
-                mem = t.leaf_members(l)
-                p_, s_ = obf16.class_candidates(Qp[i], Zp[mem])
-                pos.append(mem[p_])
-                sc.append(s_)
-            pos, sc = np.concatenate(pos), np.concatenate(sc)
-            o = np.lexsort((pos, sc))[:8]
-            cand.append(pos[o])
-        nn_o, _ = obf16.rerank(Qp, Zp, cand)
+        # the exact BF16 top-8 over the scanned members, re-ranked in FP32 PCA space
+        valid = helpers.topk_rerank_validity(Qp, Zp, t, lists, _np(nn), 8)
+        print(f"learned_bf16: valid outcomes {valid.mean():.4f}", flush=True)
+        assert valid.mean() >= 0.999, valid.mean()
+        # the per-query exact pass gives the same results (identical scores)
+        assert st.scan_overflows < 0.01 * st.nq, st.scan_overflows
+        for slots in (1, 3):
+            nn1, d1, st1 = ctx.estep(x, 8, 4, mode=mode, stats=True, scan_slots=slots)
+            print(f"scan_slots={slots}: {st1.scan_overflows} of {st1.nq} queries redone per query", flush=True)
+            assert st1.scan_overflows > 0
+            assert np.array_equal(_np(nn1), _np(nn)), slots
+            assert np.array_equal(_np(d1), _np(dist)), slots
+        return
     ok, same, _ = parity.nn_agreement(Qp, Zp, _np(nn), nn_o)
     assert ok >= 0.999, (ok, same)
 

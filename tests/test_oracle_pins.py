@@ -7,7 +7,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import bf16, exact, irls, mlp, mstep, pca, solve, tree, vectors
+from oracle import bf16, exact, irls, mlp, mstep, parity, pca, solve, tree, vectors
 from paper_2006_11851_amd import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -509,21 +509,101 @@ def test_residual_offset_ranks_by_full_distance_estimate():
     assert np.array_equal(ids_direct, ids_pca)
 
 
-def test_class_candidates_contain_the_minimum_and_follow_the_layout():
+def test_scan_topk_over_every_window_is_brute_topk():
+    # the learned form's ranking over a scanned set is the precision form's
+    # definition restricted to that set: over all windows the two coincide
     r = np.random.default_rng(22)
-    for m in (1, 7, 16, 33, 100, 257):
-        Z = r.normal(size=(m, 8)).astype(np.float32).astype(np.float64)
-        q = r.normal(size=8).astype(np.float32).astype(np.float64)
-        pos, sc = bf16.class_candidates(q, Z)
-        d = ((bf16.round_bf16(Z) - bf16.round_bf16(q[None]))**2).sum(1)
-        assert int(np.argmin(d)) in set(pos.tolist())
-        assert len(pos) <= 8 and len(pos) == len(set(pos.tolist()))
-        # pairs: every kept row's partner (i +- 16 inside its 32-row tile) is kept when it exists
-        for i in pos:
-            j = i + 16 if (i % 32) < 16 else i - 16
-            if j < m:
-                assert j in set(pos.tolist())
-        # scores are class minima: no row of a kept class beats its score
-        for i, v in zip(pos, sc):
-            cls = [k for k in range(m) if k % 16 == i % 16]
-            assert v == min(d[k] for k in cls)
+    Zp = r.normal(size=(700, 12)).astype(np.float32).astype(np.float64)
+    Qp = (Zp[r.integers(0, 700, 40)] + 0.1 * r.normal(size=(40, 12))).astype(np.float32).astype(np.float64)
+    off = r.uniform(0, 0.5, 700)
+    for o in (None, off):
+        ids_b, d_b = bf16.brute_topk(Qp, Zp, 8, offset=o)
+        ids_s, d_s = bf16.scan_topk(Qp, Zp, [np.arange(700)] * 40, 8, offset=o)
+        assert np.array_equal(np.stack(ids_s), ids_b)
+        assert np.allclose(np.stack(d_s), d_b, rtol=1e-12, atol=1e-12)
+
+
+def test_scan_topk_literal_loop_with_ties_and_repeats():
+    # a literal loop over the listed ids (repeated ids once), bf16 rounding of
+    # every coordinate, ties to the lowest id; duplicated rows make exact ties
+    r = np.random.default_rng(23)
+    Zp = r.normal(size=(60, 5)).astype(np.float32).astype(np.float64)
+    Zp[30:40] = Zp[20]  # ten copies of row 20: equal scores
+    Qp = (Zp[[20, 3, 55]] + 0.01 * r.normal(size=(3, 5))).astype(np.float32).astype(np.float64)
+    members = [np.array([45, 20, 31, 3, 39, 20, 32, 33, 34, 35, 36, 37, 38, 30, 59, 1]),
+               np.array([7, 3, 2, 9, 3, 11]), np.arange(60)[::-1]]
+    ids, sc = bf16.scan_topk(Qp, Zp, members, 8)
+    for i in range(3):
+        qb = [bf16.round_bf16(np.array([v]))[0] for v in Qp[i]]
+        rows = []
+        for e in sorted(set(int(m) for m in members[i])):
+            zb = [bf16.round_bf16(np.array([v]))[0] for v in Zp[e]]
+            rows.append((sum((a - b) ** 2 for a, b in zip(zb, qb)), e))
+        rows.sort()
+        assert [e for _, e in rows[:8]] == list(ids[i])
+        assert np.allclose([v for v, _ in rows[:8]], sc[i], rtol=1e-12, atol=0)
+    # query 0 sits on the copies: the eight lowest ids among the equal rows
+    assert list(ids[0]) == [20, 30, 31, 32, 33, 34, 35, 36]
+
+
+def test_scan_rerank_invariant():
+    # whenever the FP64 nearest scanned window is among the bf16 top 8, the
+    # re-ranked winner is that window
+    r = np.random.default_rng(24)
+    Zp = r.normal(size=(2000, 16)).astype(np.float32).astype(np.float64)
+    Qp = (Zp[r.integers(0, 2000, 150)] + 0.05 * r.normal(size=(150, 16))).astype(np.float32).astype(np.float64)
+    members = [r.choice(2000, 400, replace=False) for _ in range(150)]
+    ids, _ = bf16.scan_topk(Qp, Zp, members, 8)
+    nn_bf, _ = bf16.rerank(Qp, Zp, ids)
+    inside = 0
+    for i in range(150):
+        m = np.sort(members[i])
+        d = ((Zp[m] - Qp[i]) ** 2).sum(1)
+        best = int(m[np.lexsort((m, d))[0]])
+        if best in set(ids[i].tolist()):
+            inside += 1
+            assert nn_bf[i] == best
+    assert inside >= 140
+
+
+def test_topk_rerank_validity_rule():
+    ids = np.arange(20)
+    score = np.arange(20, dtype=np.float64)  # well separated
+    rd = np.array([5.0, 4, 3, 9, 9, 9, 9, 2.5, 1.0] + [9.0] * 11)
+    # exact scores: the top 8 are ids 0..7, their re-rank minimum is id 7
+    assert parity.topk_rerank_valid(ids, score, rd, 7, 8, tol_score=0.0)
+    assert not parity.topk_rerank_valid(ids, score, rd, 8, 8, tol_score=0.0)  # ninth: outside the set
+    assert not parity.topk_rerank_valid(ids, score, rd, 2, 8, tol_score=0.0)  # beaten by id 7
+    assert not parity.topk_rerank_valid(ids, score, rd, 99, 8, tol_score=0.0)  # not scanned
+    # the 8th and 9th within the tolerance: either may complete the set, so id 8
+    # (re-rank minimum when chosen) and id 7 are both valid
+    score2 = score.copy()
+    score2[8] = 7.0 + 1e-9
+    assert parity.topk_rerank_valid(ids, score2, rd, 8, 8, tol_score=1e-6)
+    assert parity.topk_rerank_valid(ids, score2, rd, 7, 8, tol_score=1e-6)
+    assert not parity.topk_rerank_valid(ids, score2, rd, 8, 8, tol_score=0.0)
+    # re-rank near-tie: a winner within rel of the true minimum is a tie
+    rd3 = rd.copy()
+    rd3[2] = 2.5 * (1 + 1e-6)
+    assert parity.topk_rerank_valid(ids, score, rd3, 2, 8, tol_score=0.0)
+    # fewer scanned ids than k: the re-rank minimum over all of them
+    assert parity.topk_rerank_valid(ids[:5], score[:5], rd[:5], 2, 8)
+    assert not parity.topk_rerank_valid(ids[:5], score[:5], rd[:5], 0, 8)
+
+
+def test_fp32_score_tolerance_covers_float32_evaluation():
+    # the bound admits the reorderings that evaluating the score in float32
+    # (norm first, then the products in order) can make
+    r = np.random.default_rng(25)
+    for trial in range(5):
+        Zp = (r.normal(size=(500, 64)) * 2).astype(np.float32).astype(np.float64)
+        q = (Zp[7] + 1e-3 * r.normal(size=64)).astype(np.float32).astype(np.float64)
+        Zb = bf16.round_bf16(Zp)
+        qb = bf16.round_bf16(q[None])[0]
+        exact_s = (Zb * Zb).sum(1) - 2 * Zb @ qb
+        zn32 = (Zb.astype(np.float32) ** 2).sum(1, dtype=np.float32)
+        acc = zn32.copy()
+        for k in range(64):
+            acc = (acc + np.float32(-2.0) * qb[k].astype(np.float32) * Zb[:, k].astype(np.float32)).astype(np.float32)
+        tol = bf16.fp32_score_tolerance(q, Zp, 64)
+        assert np.abs(acc.astype(np.float64) - exact_s).max() <= tol / 2
