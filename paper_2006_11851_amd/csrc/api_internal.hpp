@@ -49,7 +49,7 @@ void project_queries(Ctx* c, const float* x, int H, int W, int stride, float* qp
 void exemplar_projection(Ctx* c, float* zproj);
 void descend_unpadded(Ctx* c, const float* qproj, int64_t n, int32_t* leaf);
 
-BucketBufs bucket_buffers(Ctx* c, int64_t n, int n_leaves, int chunk, int* max_tiles);
+BucketBufs bucket_buffers(Ctx* c, int64_t n, int n_leaves, int chunk, int* max_tiles, const char* tag = "bk");
 
 // solve.cpp
 const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int* w);

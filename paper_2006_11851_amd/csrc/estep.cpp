@@ -3,6 +3,7 @@
 // form, then its full-dimension distance (used by the weights and the
 // energy whatever space the search ran in).
 #include <algorithm>
+#include <string>
 
 #include "api_internal.hpp"
 #include "bf16_learned.hpp"
@@ -19,16 +20,17 @@ void require_index(Ctx* c, Index* ix, int w) {
 
 }  // namespace
 
-BucketBufs bucket_buffers(Ctx* c, int64_t n, int n_leaves, int chunk, int* max_tiles) {
+BucketBufs bucket_buffers(Ctx* c, int64_t n, int n_leaves, int chunk, int* max_tiles, const char* tag) {
+  const std::string t(tag);
   BucketBufs b;
-  b.counts = c->buf<int32_t>("bk_counts", n_leaves);
-  b.off = c->buf<int32_t>("bk_off", n_leaves + 1);
-  b.cursor = c->buf<int32_t>("bk_cursor", n_leaves);
-  b.tile_off = c->buf<int32_t>("bk_tile_off", n_leaves + 1);
-  b.ntiles = c->buf<int32_t>("bk_ntiles", 1);
-  b.order = c->buf<int32_t>("bk_order", std::max<int64_t>(1, n));
+  b.counts = c->buf<int32_t>((t + "_counts").c_str(), n_leaves);
+  b.off = c->buf<int32_t>((t + "_off").c_str(), n_leaves + 1);
+  b.cursor = c->buf<int32_t>((t + "_cursor").c_str(), n_leaves);
+  b.tile_off = c->buf<int32_t>((t + "_tile_off").c_str(), n_leaves + 1);
+  b.ntiles = c->buf<int32_t>((t + "_ntiles").c_str(), 1);
+  b.order = c->buf<int32_t>((t + "_order").c_str(), std::max<int64_t>(1, n));
   *max_tiles = (int)(ceil_div(n, chunk) + n_leaves);
-  b.tiles = c->buf<int2>("bk_tiles", *max_tiles);
+  b.tiles = c->buf<int2>((t + "_tiles").c_str(), *max_tiles);
   return b;
 }
 

@@ -72,8 +72,17 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     const int hc = p.scan_slots <= 0 ? 16 : p.scan_slots;
     ScanHits sh;
     int32_t* novf = c->buf<int32_t>("ln_scan_overflow", 1);
-    launch_leaf_scan_bf16_exact(c, qb, nq, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b,
-                                max_tiles, pair_leaf, hc, &sh, novf);
+    // bound pass over every pair, then the collect pass over the pairs that
+    // can hold a row within the query's bound (bucketed again)
+    int32_t* pair_leaf2 = c->buf<int32_t>("ln_pair_leaf2", (size_t)nq * P1);
+    launch_leaf_scan_bf16_bound(c, qb, nq, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b,
+                                max_tiles, pair_leaf, pair_leaf2);
+    int max_tiles2 = 0;
+    BucketBufs b2 = bucket_buffers(c, nq * P1, L, chunk, &max_tiles2, "bk2");
+    b2.tile_order = ix.leaf_by_rows.as<int32_t>();
+    launch_bucket(c, pair_leaf2, nq * P1, L, chunk, b2);
+    launch_leaf_scan_bf16_collect(c, qb, nq, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b2,
+                                  max_tiles2, pair_leaf2, hc, &sh, novf);
     if (scan_overflows) *scan_overflows = novf;
     if (p.rerank_full) {
       launch_select_rerank_full(c, nullptr, nullptr, nq, 0, 0, 0, nullptr, &sh, k, ix.perm.as<int32_t>(), ix.N, x, H,

@@ -481,12 +481,13 @@ constexpr int LS_HC_MAX = 16;  // collect slots per (pair, half-lane)
 struct LeafScanOut {
   // pass 1
   uint64_t* pair_tau;  // [pairs] upper bound on the pair's 8th smallest key
+  float* pair_vmin;    // [pairs] the pair's smallest score
   // pass 2
   const uint64_t* tau_q;  // [nq] smallest bound over the query's pairs
   int2* hits;             // [pairs][2][hs] (score bits, leaf position)
   int32_t* hit_cnt;       // [pairs][2] rows collected (may exceed hc: overflow)
   int hc;                 // slots the pass may fill per (pair, half), <= hs
-  int hs;                 // slot stride, >= 8 (the per-query pass writes 8)
+  int hs;                 // slot stride (the per-query pass needs P * 2 * hs >= 8 * FB_CHUNKS)
 };
 
 // The collected rows of a query, as the re-rank kernels read them.
@@ -497,34 +498,92 @@ struct HitLists {
   int P, hs;
 };
 
-// top <- the 8 smallest (score, position) keys among the query's collected rows
+// top <- the 8 smallest (score, position) keys among the query's collected
+// rows (the pair leaves and counts are loaded together, then the rows)
+constexpr int HL_PMAX = 9;  // pairs per query: up to 8 proposals + the tree's leaf
 __device__ __forceinline__ void top8_from_hits(Top8Lex& top, const HitLists& L, int64_t q) {
-  for (int j = 0; j < L.P; ++j) {
+  int n[2 * HL_PMAX];
+#pragma unroll
+  for (int j = 0; j < HL_PMAX; ++j) {
+    const bool ok = j < L.P && L.pair_leaf[q * L.P + j] >= 0;
     const int64_t p = q * L.P + j;
-    if (L.pair_leaf[p] < 0) continue;
-    for (int hh = 0; hh < 2; ++hh) {
-      const int n = L.hit_cnt[2 * p + hh];
-      const int2* hp = L.hits + (2 * p + hh) * L.hs;
-      for (int e = 0; e < n; ++e) {
-        const int2 v = hp[e];
-        const float sv = __int_as_float(v.x);
-        if (lex_lt(sv, v.y, top.d[7], top.i[7])) top.insert(sv, v.y);
+    n[2 * j] = ok ? L.hit_cnt[2 * p] : 0;
+    n[2 * j + 1] = ok ? L.hit_cnt[2 * p + 1] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < 2 * HL_PMAX; ++j) {
+    const int2* hp = L.hits + (2 * (q * L.P) + j) * L.hs;
+    for (int e = 0; e < n[j]; ++e) {
+      const int2 v = hp[e];
+      const float sv = __int_as_float(v.x);
+      if (lex_lt(sv, v.y, top.d[7], top.i[7])) top.insert(sv, v.y);
+    }
+  }
+}
+
+// Collected rows of a lane for one query tile: slot cnt is the next free
+// one.  Rows found during a stage go to the lane's few LDS slots and are
+// written to their global slots after the stage's row loads have been
+// consumed (flush): a global store issued between a load and its use would
+// make that use wait for the store too (loads and stores share one
+// completion counter), undoing the two-stage prefetch.  Rows beyond the LDS
+// slots in one stage are written at once.
+constexpr int HB_STAGE = 4;  // LDS slots per lane and query tile
+struct HitLane {
+  float tv;    // the query's bound: score
+  int tp;      // and position
+  int2* dst;   // the (pair, half) slots
+  int cnt, done;
+  int lds;     // first LDS slot of the lane
+};
+
+__device__ __forceinline__ void hit_push(HitLane& L, int2* lbuf, int hc, int2 e) {
+  const int i = L.cnt;
+  if (i < hc) {
+    const int k = i - L.done;
+    if (k < HB_STAGE) lbuf[L.lds + k] = e;
+    else L.dst[i] = e;
+  }
+  L.cnt = i + 1;
+}
+
+__device__ __forceinline__ void hit_flush(HitLane& L, const int2* lbuf, int hc) {
+  const int e = min(L.cnt, hc), n = min(e - L.done, HB_STAGE);
+  for (int k = 0; k < n; ++k) L.dst[L.done + k] = lbuf[L.lds + k];
+  L.done = e;
+}
+
+// rows of a tile (accumulator acc, first row tpos) at or below the query's
+// bound, tested in pairs (values r and r + 8: rows i and i + 16)
+__device__ __forceinline__ void collect_rows(const floatx16& acc, HitLane& L, int2* lbuf, int hc, int tpos,
+                                             int row_end) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (__builtin_fminf(acc[c], acc[c + 8]) <= L.tv) {
+#pragma unroll
+      for (int r = c; r < 16; r += 8) {
+        const float v = acc[r];
+        const int pos = tpos + 8 * (r >> 2) + (r & 3);
+        if (v <= L.tv && pos < row_end && (v < L.tv || pos <= L.tp))
+          hit_push(L, lbuf, hc, make_int2(__float_as_int(v), pos));
       }
     }
   }
 }
 
-// Pass 2 over one stage: products, then every row at or below the query's
-// bound goes to the lane's slots.  A wave rarely holds such a row in a tile
-// (the tile minimum is tested first).
-template <int KS, bool FULL>
+// Pass 2 over one stage, software pipelined: tile t's fragments are read,
+// tile t - 1's rows are collected while they arrive, then tile t's products
+// are issued (read only at step t + 1).  Every stage takes all 4 tiles: rows
+// past the leaf are zero rows with norm FLT_MAX in LDS, so they score
+// FLT_MAX and are never collected (one code path keeps the kernel small).
+template <int KS>
 __device__ __forceinline__ void stage_collect(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
-                                              const float (&tv)[2], const int (&tp)[2], int (&cnt)[2],
-                                              int2* const (&hb)[2], int hc, int pos0, int lane, int nvalid,
+                                              HitLane& L0, HitLane& L1, int2* lbuf, int hc, int pos0, int lane,
                                               int row_end) {
+  floatx16 accp[2];
+  const int hofs = 4 * (lane >> 5);
 #pragma unroll
   for (int t = 0; t < BB_STAGE / 32; ++t) {
-    if (!FULL && t * 32 >= nvalid) break;
     bf16x8 A[KS];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
@@ -532,7 +591,7 @@ __device__ __forceinline__ void stage_collect(const BruteSmem<KS>& S, int buf, c
       A[kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
     floatx16 cinit;
-    const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
+    const float* zr = &S.zn[buf][t * 32 + hofs];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
@@ -541,31 +600,21 @@ __device__ __forceinline__ void stage_collect(const BruteSmem<KS>& S, int buf, c
       cinit[4 * g + 2] = z4.z;
       cinit[4 * g + 3] = z4.w;
     }
-    floatx16 acc[2] = {cinit, cinit};
+    if (t > 0) {
+      collect_rows(accp[0], L0, lbuf, hc, pos0 + (t - 1) * 32 + hofs, row_end);
+      collect_rows(accp[1], L1, lbuf, hc, pos0 + (t - 1) * 32 + hofs, row_end);
+    }
+    floatx16 accn[2] = {cinit, cinit};
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
       for (int qt = 0; qt < 2; ++qt)
-        acc[qt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc[qt], 0, 0, 0);
-    const int tpos = pos0 + t * 32 + 4 * (lane >> 5);
-#pragma unroll
-    for (int qt = 0; qt < 2; ++qt) {
-      float m = acc[qt][0];
-#pragma unroll
-      for (int r = 1; r < 16; ++r) m = __builtin_fminf(m, acc[qt][r]);
-      if (__any(m <= tv[qt])) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float v = acc[qt][r];
-          const int pos = tpos + 8 * (r >> 2) + (r & 3);
-          if (v <= tv[qt] && pos < row_end && (v < tv[qt] || pos <= tp[qt])) {
-            if (cnt[qt] < hc) hb[qt][cnt[qt]] = make_int2(__float_as_int(v), pos);
-            ++cnt[qt];
-          }
-        }
-      }
-    }
+        accn[qt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], accn[qt], 0, 0, 0);
+    accp[0] = accn[0];
+    accp[1] = accn[1];
   }
+  collect_rows(accp[0], L0, lbuf, hc, pos0 + (BB_STAGE / 32 - 1) * 32 + hofs, row_end);
+  collect_rows(accp[1], L1, lbuf, hc, pos0 + (BB_STAGE / 32 - 1) * 32 + hofs, row_end);
 }
 
 // One tile = (leaf, LS_QPB pairs of the bucketed order); rows = the leaf's
@@ -576,7 +625,7 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
                                                const uint16_t* __restrict__ Zb, const float* __restrict__ zbn,
                                                const int32_t* __restrict__ leaf_off,
                                                const int32_t* __restrict__ qoff, const int32_t* __restrict__ order,
-                                               const int2* __restrict__ tiles, const LeafScanOut& o) {
+                                               const int2* __restrict__ tiles, const LeafScanOut& o, int2* lbuf) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5;
   const int2 tile = tiles[t];
@@ -584,10 +633,10 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
   const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
   // the first two stages' rows are requested before the pairs' query
   // operands (a chain of two dependent loads), so that both are in flight
-  StageRegs<KS, LS_QPB> R[2];
+  StageRegs<KS, LS_QPB> R0, R1;
   if (row_begin < row_end) {
-    stage_load<KS, LS_QPB>(R[0], Zb, zbn, row_begin, row_end, tid);
-    stage_load<KS, LS_QPB>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
+    stage_load<KS, LS_QPB>(R0, Zb, zbn, row_begin, row_end, tid);
+    stage_load<KS, LS_QPB>(R1, Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
   }
   const int pend = min(qoff[tile.x + 1], tile.y + LS_QPB);
   const bool wave_active = tile.y + wave * 64 < pend;
@@ -608,9 +657,7 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
   }
   float cm[2][8];
   int ct[2][8];
-  float tv[2];
-  int tp[2], cnt[2];
-  int2* hb[2];
+  HitLane L0, L1;
   if constexpr (PASS == 1) {
 #pragma unroll
     for (int qt = 0; qt < 2; ++qt)
@@ -620,48 +667,60 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
         ct[qt][c] = -1;
       }
   } else {
-#pragma unroll
-    for (int qt = 0; qt < 2; ++qt) {
-      cnt[qt] = 0;
+    auto init_lane = [&](HitLane& L, int qt) {
+      L.cnt = L.done = 0;
+      L.lds = (tid * 2 + qt) * HB_STAGE;
       if (pr[qt] >= 0) {
         const uint64_t k = o.tau_q[qid[qt]];
-        tv[qt] = key_score(k);
-        tp[qt] = key_pos(k);
-        hb[qt] = o.hits + ((int64_t)pr[qt] * 2 + h) * o.hs;
+        L.tv = key_score(k);
+        L.tp = key_pos(k);
+        L.dst = o.hits + ((int64_t)pr[qt] * 2 + h) * o.hs;
       } else {  // nothing is ever collected for a lane without a pair
-        tv[qt] = -INFINITY;
-        tp[qt] = -1;
-        hb[qt] = o.hits;
+        L.tv = -INFINITY;
+        L.tp = -1;
+        L.dst = o.hits;
       }
-    }
+    };
+    init_lane(L0, 0);
+    init_lane(L1, 1);
   }
   if (row_begin < row_end) {
-    // stages load two ahead, as in the brute-force kernel
-    stage_store<KS, LS_QPB>(R[0], sm, 0, tid, row_begin, row_end);
-    lds_barrier();
-    for (int s0 = 0; s0 < nstages; s0 += 2) {
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int st = s0 + u;
-        if (st >= nstages) break;
-        // unconditional (past the end: the last rows again, never stored), so
-        // the wait before the store covers only the older stage
-        stage_load<KS, LS_QPB>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
-        if (wave_active) {
-          const int nvalid = min(BB_STAGE, row_end - row_begin - st * BB_STAGE);
-          const int p0 = row_begin + st * BB_STAGE;
-          if constexpr (PASS == 1) {
-            if (nvalid == BB_STAGE) stage_compute_cls_full<KS>(sm, u, B, cm, ct, p0, lane);
-            else stage_compute_cls<KS, false>(sm, u, B, cm, ct, p0, lane, nvalid);
-          } else {
-            if (nvalid == BB_STAGE) stage_collect<KS, true>(sm, u, B, tv, tp, cnt, hb, o.hc, p0, lane, nvalid, row_end);
-            else stage_collect<KS, false>(sm, u, B, tv, tp, cnt, hb, o.hc, p0, lane, nvalid, row_end);
-          }
+    // stages load two ahead, as in the brute-force kernel: step st loads
+    // stage st + 2 into the registers it frees, computes on LDS buffer st % 2
+    // and stores stage st + 1 (loaded two steps earlier) into the other
+    // buffer.  The two register sets are named, not indexed, and swapped
+    // after each step, so that they stay in registers and the step's code
+    // appears once.
+    auto step = [&](StageRegs<KS, LS_QPB>& Rcur, StageRegs<KS, LS_QPB>& Rnext, int st,
+                    int buf) __attribute__((always_inline)) {
+      // unconditional (past the end: the last rows again, never stored), so
+      // the wait before the store covers only the older stage
+      stage_load<KS, LS_QPB>(Rcur, Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
+      if (wave_active) {
+        const int nvalid = min(BB_STAGE, row_end - row_begin - st * BB_STAGE);
+        const int p0 = row_begin + st * BB_STAGE;
+        if constexpr (PASS == 1) {
+          if (nvalid == BB_STAGE) stage_compute_cls_full<KS>(sm, buf, B, cm, ct, p0, lane);
+          else stage_compute_cls<KS, false>(sm, buf, B, cm, ct, p0, lane, nvalid);
+        } else {
+          stage_collect<KS>(sm, buf, B, L0, L1, lbuf, o.hc, p0, lane, row_end);
         }
-        if (st + 1 < nstages)
-          stage_store<KS, LS_QPB>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
-        lds_barrier();
       }
+      if (st + 1 < nstages)
+        stage_store<KS, LS_QPB>(Rnext, sm, buf ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
+      if constexpr (PASS == 2) {  // the loaded rows are in LDS now
+        hit_flush(L0, lbuf, o.hc);
+        hit_flush(L1, lbuf, o.hc);
+      }
+      lds_barrier();
+    };
+    stage_store<KS, LS_QPB>(R0, sm, 0, tid, row_begin, row_end);
+    lds_barrier();
+    for (int st = 0; st < nstages; ++st) {
+      step(R0, R1, st, st & 1);
+      const StageRegs<KS, LS_QPB> tmp = R0;  // the set just loaded is stored next
+      R0 = R1;
+      R1 = tmp;
     }
   }
   if constexpr (PASS == 1) {
@@ -691,12 +750,14 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
         const uint64_t m = a > b ? a : b;
         best = m < best ? m : best;
       }
-      if (h == 0 && pr[qt] >= 0) o.pair_tau[pr[qt]] = best;
+      if (h == 0 && pr[qt] >= 0) {
+        o.pair_tau[pr[qt]] = best;
+        o.pair_vmin[pr[qt]] = key_score(k[0] < ok[0] ? k[0] : ok[0]);
+      }
     }
   } else {
-#pragma unroll
-    for (int qt = 0; qt < 2; ++qt)
-      if (pr[qt] >= 0) o.hit_cnt[(int64_t)pr[qt] * 2 + h] = cnt[qt];
+    if (pr[0] >= 0) o.hit_cnt[(int64_t)pr[0] * 2 + h] = L0.cnt;
+    if (pr[1] >= 0) o.hit_cnt[(int64_t)pr[1] * 2 + h] = L1.cnt;
   }
 }
 
@@ -714,6 +775,7 @@ __global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __res
                                                         const int32_t* __restrict__ ntiles,
                                                         int32_t* __restrict__ next, LeafScanOut o) {
   __shared__ BruteSmem<KS> sm;
+  __shared__ int2 s_hits[PASS == 2 ? LS_QPB * 2 * HB_STAGE : 1];
   __shared__ int s_t;
   const int nt = *ntiles;
   for (;;) {
@@ -721,15 +783,18 @@ __global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __res
     __syncthreads();
     const int t = s_t;
     if (t >= nt) break;  // uniform per block; the counter only grows, so every block gets here
-    leaf_scan_tile<KS, PASS>(t, sm, Qb, P, Zb, zbn, leaf_off, qoff, order, tiles, o);
+    leaf_scan_tile<KS, PASS>(t, sm, Qb, P, Zb, zbn, leaf_off, qoff, order, tiles, o, s_hits);
     __syncthreads();  // LDS buffers and s_t free for the next tile
   }
 }
 
-// tau[q] = the smallest pass-1 bound over the query's scanned pairs
+// tau[q] = the smallest pass-1 bound over the query's scanned pairs; a pair
+// whose smallest score exceeds the bound's score holds no row within it and
+// is left out of the collect pass (pair_leaf2 = -1), the others keep their leaf
 __global__ __launch_bounds__(256) void k_pair_tau_min(const int32_t* __restrict__ pair_leaf,
-                                                      const uint64_t* __restrict__ pair_tau, int64_t nq, int P,
-                                                      uint64_t* __restrict__ tau) {
+                                                      const uint64_t* __restrict__ pair_tau,
+                                                      const float* __restrict__ pair_vmin, int64_t nq, int P,
+                                                      uint64_t* __restrict__ tau, int32_t* __restrict__ pair_leaf2) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   uint64_t b = ~0ull;
@@ -740,6 +805,12 @@ __global__ __launch_bounds__(256) void k_pair_tau_min(const int32_t* __restrict_
     b = v < b ? v : b;
   }
   tau[q] = b;
+  const float bv = key_score(b);
+  for (int j = 0; j < P; ++j) {
+    const int64_t p = q * P + j;
+    const int l = pair_leaf[p];
+    pair_leaf2[p] = (l >= 0 && pair_vmin[p] <= bv) ? l : -1;
+  }
 }
 
 // queries with a (pair, half) that collected more rows than it has slots
@@ -757,30 +828,36 @@ __global__ __launch_bounds__(256) void k_hit_overflow(const int32_t* __restrict_
   if (over) list[atomicAdd(n, 1)] = (int32_t)q;
 }
 
-// The per-query exact top-8 for the overflowed queries: one wave per query
-// runs the same matrix products over every member of its scanned leaves (the
-// query in all 32 columns, so each half of the wave holds the same 16 rows
-// of a tile: identical scores to the tile kernels, whose products see the
-// same operands in the same order), keeps a sorted top-8 of (score,
-// position) per lane, merges the two halves and writes the 8 to the slots of
-// the query's first pair (count 8; the other counts 0).  Waves loop over the
-// list, whose length is read on the device.
+// The per-query exact top-8 for the overflowed queries, in two kernels.
+// Chunks: the query's 32-row tiles (its collect pairs' leaves, pair after
+// pair) are dealt to FB_CHUNKS waves in turn; each wave runs the same matrix
+// products as the tile kernels (the query in all 32 columns, so each half of
+// the wave holds the same 16 rows of a tile: identical scores, the products
+// seeing the same operands in the same order), keeps a sorted top-8 of
+// (score, position) per lane, merges its two halves and writes the 8 into
+// the query's own slots (chunk c at 8 c: the query owns P * 2 * hs >= 8 *
+// FB_CHUNKS slots).  Merge: one thread per query takes the 8 best of the
+// chunk lists and leaves them in the slots of its first collect pair (count
+// 8, the other counts 0).  Waves and threads loop over the list, whose length
+// is read on the device.
+constexpr int FB_CHUNKS = 16;
 template <int KS>
-__global__ __launch_bounds__(256) void k_scan_top8_exact(const uint16_t* __restrict__ Qb, int P,
-                                                         const uint16_t* __restrict__ Zb,
-                                                         const float* __restrict__ zbn,
-                                                         const int32_t* __restrict__ leaf_off,
-                                                         const int32_t* __restrict__ pair_leaf,
-                                                         const int32_t* __restrict__ list,
-                                                         const int32_t* __restrict__ n, int2* __restrict__ hits,
-                                                         int32_t* __restrict__ hit_cnt, int hs) {
+__global__ __launch_bounds__(256) void k_scan_top8_chunks(const uint16_t* __restrict__ Qb, int P,
+                                                          const uint16_t* __restrict__ Zb,
+                                                          const float* __restrict__ zbn,
+                                                          const int32_t* __restrict__ leaf_off,
+                                                          const int32_t* __restrict__ pair_leaf,
+                                                          const int32_t* __restrict__ list,
+                                                          const int32_t* __restrict__ n, int2* __restrict__ hits,
+                                                          int hs) {
   const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int nw = gridDim.x * (blockDim.x >> 6);
-  const int h = lane >> 5;
-  const int cnt = *n;
-  for (int i = gw; i < cnt; i += nw) {
-    const int64_t q = list[i];
+  const int64_t items = (int64_t)(*n) * FB_CHUNKS;
+  for (int64_t it = gw; it < items; it += nw) {
+    const int64_t q = list[it / FB_CHUNKS];
+    const int c = (int)(it % FB_CHUNKS);
     bf16x8 B[KS];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
@@ -789,11 +866,14 @@ __global__ __launch_bounds__(256) void k_scan_top8_exact(const uint16_t* __restr
     }
     Top8Lex top;
     top.init();
+    int g0 = 0;  // tiles of the earlier pairs
     for (int j = 0; j < P; ++j) {
       const int l = pair_leaf[q * P + j];
       if (l < 0) continue;
       const int rb = leaf_off[l], re = leaf_off[l + 1];
-      for (int t0 = rb; t0 < re; t0 += 32) {
+      const int nt = (int)ceil_div(re - rb, 32);
+      for (int t = (c - g0 % FB_CHUNKS + FB_CHUNKS) % FB_CHUNKS; t < nt; t += FB_CHUNKS) {
+        const int t0 = rb + 32 * t;
         const int64_t row = min(t0 + (lane & 31), re - 1);
         bf16x8 A[KS];
 #pragma unroll
@@ -803,10 +883,7 @@ __global__ __launch_bounds__(256) void k_scan_top8_exact(const uint16_t* __restr
         }
         floatx16 acc;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int pr = t0 + 8 * (r >> 2) + 4 * h + (r & 3);
-          acc[r] = pr < re ? zbn[pr] : FLT_MAX;
-        }
+        for (int r = 0; r < 16; ++r) acc[r] = zbn[min(t0 + 8 * (r >> 2) + 4 * h + (r & 3), re - 1)];
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[kk], acc, 0, 0, 0);
 #pragma unroll
@@ -815,8 +892,8 @@ __global__ __launch_bounds__(256) void k_scan_top8_exact(const uint16_t* __restr
           if (pr < re && lex_lt(acc[r], pr, top.d[7], top.i[7])) top.insert(acc[r], pr);
         }
       }
+      g0 += nt;
     }
-    // lane 0 merges the other half's list (lane 32) into its own
     float od[8];
     int oi[8];
 #pragma unroll
@@ -828,15 +905,37 @@ __global__ __launch_bounds__(256) void k_scan_top8_exact(const uint16_t* __restr
 #pragma unroll
       for (int t = 0; t < 8; ++t)
         if (lex_lt(od[t], oi[t], top.d[7], top.i[7])) top.insert(od[t], oi[t]);
-      const int64_t p0 = q * P;  // the first proposal: always a scanned pair
-      int m = 0;
+      int2* dst = hits + (q * P) * 2 * hs + 8 * c;
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (top.i[t] != INT_MAX) hits[(p0 * 2) * hs + m++] = make_int2(__float_as_int(top.d[t]), top.i[t]);
-      for (int j = 0; j < P; ++j) {
-        hit_cnt[(q * P + j) * 2] = j == 0 ? m : 0;
-        hit_cnt[(q * P + j) * 2 + 1] = 0;
-      }
+      for (int t = 0; t < 8; ++t) dst[t] = make_int2(__float_as_int(top.d[t]), top.i[t]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_top8_merge(int P, const int32_t* __restrict__ pair_leaf,
+                                                         const int32_t* __restrict__ list,
+                                                         const int32_t* __restrict__ n, int2* __restrict__ hits,
+                                                         int32_t* __restrict__ hit_cnt, int hs) {
+  const int cnt = *n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const int64_t q = list[i];
+    const int2* src = hits + (q * P) * 2 * hs;
+    Top8Lex top;
+    top.init();
+    for (int e = 0; e < 8 * FB_CHUNKS; ++e) {
+      const int2 v = src[e];
+      const float sv = __int_as_float(v.x);
+      if (lex_lt(sv, v.y, top.d[7], top.i[7])) top.insert(sv, v.y);
+    }
+    int j0 = 0;  // the first pair the query scans (it has at least one)
+    while (j0 + 1 < P && pair_leaf[q * P + j0] < 0) ++j0;
+    int2* dst = hits + (q * P + j0) * 2 * hs;
+    int m = 0;
+    for (int t = 0; t < 8; ++t)
+      if (top.i[t] != INT_MAX) dst[m++] = make_int2(__float_as_int(top.d[t]), top.i[t]);
+    for (int jj = 0; jj < P; ++jj) {
+      hit_cnt[(q * P + jj) * 2] = jj == j0 ? m : 0;
+      hit_cnt[(q * P + jj) * 2 + 1] = 0;
     }
   }
 }
@@ -883,60 +982,74 @@ static HitLists hit_lists(const ScanHits* sh) {
   return h;
 }
 
-void launch_leaf_scan_bf16_exact(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
+void launch_leaf_scan_bf16_bound(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
                                  int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles,
-                                 const int32_t* pair_leaf, int hc, ScanHits* sh, int32_t* n_overflow) {
-  PTS_REQUIRE(hc >= 0 && hc <= LS_HC_MAX, PTS_ERR_ARG, "collect slots must be 0..16");
-  const int hs = std::max(hc, 8);
+                                 const int32_t* pair_leaf, int32_t* pair_leaf2) {
   const int64_t npairs = nq * P;
   LeafScanOut o{};
   o.pair_tau = c->buf<uint64_t>("ls_pair_tau", (size_t)std::max<int64_t>(1, npairs));
+  o.pair_vmin = c->buf<float>("ls_pair_vmin", (size_t)std::max<int64_t>(1, npairs));
   uint64_t* tau_q = c->buf<uint64_t>("ls_tau_q", (size_t)std::max<int64_t>(1, nq));
-  o.tau_q = tau_q;
+  if (nq == 0) return;
+  if (max_tiles > 0) {
+    ProfScope ps(c, "leaf_scan_bf16");
+    int32_t* next = c->buf<int32_t>("ls_next_tile", 1);
+    launch_zero_i32(c, next, 1);
+    const int grid = std::min(max_tiles, c->n_cu);
+    PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_leaf_scan_bf16<KSC, 1>), dim3(grid), dim3(LS_QPB), 0, c->stream, Qb, P,
+                                         Zb, zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, next, o));
+    check_launch("k_leaf_scan_bf16 (bound)");
+  }
+  ProfScope ps(c, "scan_tau_min");
+  hipLaunchKernelGGL(k_pair_tau_min, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf, o.pair_tau,
+                     o.pair_vmin, nq, P, tau_q, pair_leaf2);
+  check_launch("k_pair_tau_min");
+}
+
+void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb,
+                                   const float* zbn, int dk, const int32_t* leaf_off, const BucketBufs& b,
+                                   int max_tiles, const int32_t* pair_leaf2, int hc, ScanHits* sh,
+                                   int32_t* n_overflow) {
+  PTS_REQUIRE(hc >= 0 && hc <= LS_HC_MAX, PTS_ERR_ARG, "collect slots must be 0..16");
+  PTS_REQUIRE(P >= 1 && P <= HL_PMAX, PTS_ERR_ARG, "at most 9 scanned leaves per query");
+  // slot stride: hc, but room for the per-query pass's chunk lists too
+  const int hs = std::max(hc, (int)ceil_div(8 * FB_CHUNKS, 2 * P));
+  const int64_t npairs = nq * P;
+  LeafScanOut o{};
+  o.tau_q = c->buf<uint64_t>("ls_tau_q", (size_t)std::max<int64_t>(1, nq));
   o.hits = c->buf<int2>("ls_hits", (size_t)std::max<int64_t>(1, npairs * 2 * hs));
   o.hit_cnt = c->buf<int32_t>("ls_hit_cnt", (size_t)std::max<int64_t>(1, npairs * 2));
   o.hc = hc;
   o.hs = hs;
   sh->hits = o.hits;
   sh->hit_cnt = o.hit_cnt;
-  sh->pair_leaf = pair_leaf;
+  sh->pair_leaf = pair_leaf2;
   sh->P = P;
   sh->hs = hs;
-  if (nq == 0 || max_tiles == 0) return;
-  int32_t* next = c->buf<int32_t>("ls_next_tile", 1);
-  const int grid = std::min(max_tiles, c->n_cu);
-  {
-    ProfScope ps(c, "leaf_scan_bf16");
-    launch_zero_i32(c, next, 1);
-    PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_leaf_scan_bf16<KSC, 1>), dim3(grid), dim3(LS_QPB), 0, c->stream, Qb, P,
-                                         Zb, zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, next, o));
-    check_launch("k_leaf_scan_bf16 (bound)");
-  }
-  {
-    ProfScope ps(c, "scan_tau_min");
-    hipLaunchKernelGGL(k_pair_tau_min, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf,
-                       o.pair_tau, nq, P, tau_q);
-    check_launch("k_pair_tau_min");
-  }
-  {
+  if (nq == 0) return;
+  if (max_tiles > 0) {
     ProfScope ps(c, "leaf_scan_bf16_collect");
+    int32_t* next = c->buf<int32_t>("ls_next_tile", 1);
     launch_zero_i32(c, next, 1);
+    const int grid = std::min(max_tiles, c->n_cu);
     PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_leaf_scan_bf16<KSC, 2>), dim3(grid), dim3(LS_QPB), 0, c->stream, Qb, P,
                                          Zb, zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, next, o));
     check_launch("k_leaf_scan_bf16 (collect)");
   }
-  {
-    ProfScope ps(c, "scan_overflow");
-    int32_t* list = c->buf<int32_t>("ls_ovf_list", (size_t)nq);
-    launch_zero_i32(c, n_overflow, 1);
-    hipLaunchKernelGGL(k_hit_overflow, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf,
-                       o.hit_cnt, nq, P, hc, list, n_overflow);
-    check_launch("k_hit_overflow");
-    // waves loop over the list (its length is only known on the device)
-    PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_scan_top8_exact<KSC>, dim3(c->n_cu), dim3(256), 0, c->stream, Qb, P, Zb,
-                                         zbn, leaf_off, pair_leaf, list, n_overflow, o.hits, o.hit_cnt, hs));
-    check_launch("k_scan_top8_exact");
-  }
+  ProfScope ps(c, "scan_overflow");
+  int32_t* list = c->buf<int32_t>("ls_ovf_list", (size_t)nq);
+  launch_zero_i32(c, n_overflow, 1);
+  hipLaunchKernelGGL(k_hit_overflow, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf2,
+                     o.hit_cnt, nq, P, hc, list, n_overflow);
+  check_launch("k_hit_overflow");
+  // waves and threads loop over the list (its length is only known on the device)
+  PTS_REQUIRE((int64_t)P * 2 * hs >= 8 * FB_CHUNKS, PTS_ERR_ARG, "too few collect slots per query");
+  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_scan_top8_chunks<KSC>, dim3(4 * c->n_cu), dim3(256), 0, c->stream, Qb, P,
+                                       Zb, zbn, leaf_off, pair_leaf2, list, n_overflow, o.hits, hs));
+  check_launch("k_scan_top8_chunks");
+  hipLaunchKernelGGL(k_scan_top8_merge, dim3(64), dim3(256), 0, c->stream, P, pair_leaf2, list, n_overflow, o.hits,
+                     o.hit_cnt, hs);
+  check_launch("k_scan_top8_merge");
 }
 
 // ---------------------------------------------------------------------------
