@@ -87,7 +87,9 @@ int pts_set_stream(pts_ctx* ctx, void* hip_stream);
 
 /* Set the exemplar Z from a device image rgbs [Hz][Wz][4] (guidance already
  * in channel 3).  The library keeps its own copy.  Invalidates the index and
- * the MLP.  Section 4: the scale map enters as a channel beside R, G, B. */
+ * the MLP.  Section 4: the scale map enters as a channel beside R, G, B.
+ * An image holding a non-finite value is refused (PTS_ERR_ARG; the previous
+ * exemplar stays).  Synchronous. */
 int pts_set_exemplar(pts_ctx* ctx, const float* rgbs, int Hz, int Wz);
 /* Convenience: host uint8 RGB [Hz][Wz][3]; R,G,B = u8 / 255 and
  * S = guidance_weight * (y + 0.5) / Hz. */
@@ -178,14 +180,21 @@ typedef struct pts_estep_stats {
   int64_t nq;             /* queries searched */
   int64_t fallbacks;      /* learned modes: queries that fell back to the tree */
   int64_t scan_overflows; /* LEARNED_BF16: queries redone by the exact per-query pass */
-  double ms;              /* wall time of the call on the stream (hipEvent) */
+  int64_t scan_rows;      /* learned modes: (query, exemplar) scores of the leaf scan
+                             (LEARNED_BF16: its first, bounding pass) */
+  int64_t collect_rows;   /* LEARNED_BF16: (query, exemplar) scores of its second pass */
+  double ms;              /* wall time of the call on the stream (hipEvent); with statistics
+                             asked for, the counts above add synchronisations to it */
 } pts_estep_stats;
 
 /* For every output window q of x_rgbs [H][W][4]: nn[q] = id of the chosen
  * exemplar window (the original window id e), dist[q] = ||x_q - z_nn|| over
  * the full D in FP32, whatever space the search ran in.  Ties go to the
  * lowest e (exact modes) / lowest child index (tree descent).  nn: int32
- * [nq]; dist: float32 [nq].  st_host may be NULL (then no synchronisation). */
+ * [nq]; dist: float32 [nq].  st_host may be NULL (then no synchronisation).
+ * With st_host given, x_rgbs is first checked: a non-finite value returns
+ * PTS_ERR_ARG (without statistics the call does not wait for the stream,
+ * and a non-finite window gets a non-finite distance). */
 int pts_estep(pts_ctx* ctx, const float* x_rgbs, int H, int W, const pts_estep_params* p, int32_t* nn,
               float* dist, pts_estep_stats* st_host);
 
@@ -258,10 +267,16 @@ typedef struct pts_solve_params {
   int residual;
   float r, delta;
   int patch_offset;
-  float guidance_weight;
+  float guidance_weight;          /* >= 0: every level's guidance is recomputed as
+                                     weight * (y + 0.5) / H (exemplar pyramid and upsampled
+                                     outputs); < 0: the exemplar's own guidance channel and
+                                     x0's are carried through the pyramid and the upsampling
+                                     by the same filters as the colours (a scale map) */
   uint64_t seed;                  /* k-means seed for indexes built by the solve */
   int kmeans_max_iter;
-  int reuse_finest_index;         /* 1: use the context's current index at the finest level */
+  int reuse_finest_index;         /* 1: use the context's current index (and MLP) at the finest
+                                     level; that index must have been built from an exemplar
+                                     whose guidance channel is the one the solve uses there */
 } pts_solve_params;
 
 typedef struct pts_solve_trace {
@@ -276,7 +291,8 @@ typedef struct pts_solve_trace {
   int64_t* fallbacks;
 } pts_solve_trace;
 
-/* Coarse-to-fine solve on the context's exemplar.  The exemplar pyramid
+/* Coarse-to-fine solve on the context's exemplar (x0 holding a non-finite
+ * value: PTS_ERR_ARG).  The exemplar pyramid
  * (separable [1 4 6 4 1]/16 blur, mirrored borders, 2x decimation; guidance
  * recomputed per level) is built on the GPU.  x0_rgbs [H0][W0][4] is the
  * initial output at the coarsest level; each finer level starts from the

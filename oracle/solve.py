@@ -47,9 +47,16 @@ def blur_decimate(rgb: np.ndarray) -> np.ndarray:
 
 
 def exemplar_pyramid(Z: np.ndarray, levels: int, weight: float = 0.5):
-    """Coarse-to-fine list of RGBS exemplars; the last is Z itself."""
+    """Coarse-to-fine list of RGBS exemplars; the last is Z itself.  A
+    negative weight keeps Z's own guidance channel (a scale map) and blurs
+    it like the colours; otherwise each level's guidance is recomputed."""
     out = [np.array(Z, dtype=np.float64)]
+    if weight >= 0:
+        out[0][..., 3] = guidance(Z.shape[0], Z.shape[1], weight)
     for _ in range(levels - 1):
+        if weight < 0:
+            out.insert(0, blur_decimate(out[0]))
+            continue
         rgb = blur_decimate(out[0][..., :3])
         img = np.empty(rgb.shape[:2] + (4,))
         img[..., :3] = rgb
@@ -69,12 +76,13 @@ def upsample2(X: np.ndarray, weight: float = 0.5) -> np.ndarray:
     fx = (xc - x0)[None, :, None]
     ya, yb = np.clip(y0, 0, Hc - 1), np.clip(y0 + 1, 0, Hc - 1)
     xa, xb = np.mod(x0, Wc), np.mod(x0 + 1, Wc)
-    rgb = X[..., :3]
-    top = (1 - fx) * rgb[ya][:, xa] + fx * rgb[ya][:, xb]
-    bot = (1 - fx) * rgb[yb][:, xa] + fx * rgb[yb][:, xb]
+    ch = X if weight < 0 else X[..., :3]  # a negative weight interpolates the guidance too
+    top = (1 - fx) * ch[ya][:, xa] + fx * ch[ya][:, xb]
+    bot = (1 - fx) * ch[yb][:, xa] + fx * ch[yb][:, xb]
     out = np.empty((H, W, 4))
-    out[..., :3] = (1 - fy) * top + fy * bot
-    out[..., 3] = guidance(H, W, weight)
+    out[..., : ch.shape[2]] = (1 - fy) * top + fy * bot
+    if weight >= 0:
+        out[..., 3] = guidance(H, W, weight)
     return out
 
 

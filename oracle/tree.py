@@ -195,6 +195,27 @@ def search_leaves(Qp: np.ndarray, Zp: np.ndarray, tree: Tree, leaves_per_query):
     return nn, dd
 
 
+def search_leaves_topk(Qp: np.ndarray, Zp: np.ndarray, tree: Tree, leaves_per_query, k: int = 8, offset=None):
+    """The k best members of the given leaves (a list of leaf ids per query;
+    a repeated leaf counts once) by squared PCA distance plus the optional
+    per-exemplar offset, ties to the lowest id: the candidates the learned
+    form re-ranks in full dimension.  Returns (list of id arrays, list of
+    distance arrays)."""
+    Qp = np.asarray(Qp, dtype=np.float64)
+    off = None if offset is None else np.asarray(offset, dtype=np.float64)
+    ids_out, d_out = [], []
+    for q in range(Qp.shape[0]):
+        cand = np.unique(np.concatenate([tree.leaf_members(int(l)) for l in np.atleast_1d(leaves_per_query[q])]))
+        diff = Zp[cand] - Qp[q][None, :]
+        d2 = np.einsum("ij,ij->i", diff, diff)
+        if off is not None:
+            d2 = d2 + off[cand]
+        o = np.lexsort((cand, d2))[:k]
+        ids_out.append(cand[o])
+        d_out.append(d2[o])
+    return ids_out, d_out
+
+
 def tree_nn(Qp: np.ndarray, Zp: np.ndarray, tree: Tree):
     """Tree search: greedy descent to one leaf, then exhaustive leaf scan."""
     leaves, gaps = descend(tree, Qp)

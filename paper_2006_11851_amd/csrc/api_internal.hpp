@@ -9,6 +9,7 @@ struct EstepStats {
   int64_t nq = 0;
   int64_t fallbacks = 0;
   int64_t scan_overflows = 0;
+  int64_t scan_rows = 0, collect_rows = 0;
   double ms = 0.0;
 };
 
@@ -40,8 +41,10 @@ void export_index(Ctx* c, const Index& ix, pts_index_host* out);
 void import_index(Ctx* c, ExView ex, const pts_index_host& in, int make_bf16, Index& ix);
 
 // estep.cpp
+// timing: record the call's time, fallbacks and per-query passes; count_work:
+// also the scan counts (extra synchronisations)
 EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, const pts_estep_params& p,
-                    int32_t* nn, float* dist, bool timing);
+                    int32_t* nn, float* dist, bool timing, bool count_work = false);
 EstepStats run_estep(Ctx* c, const float* x, int H, int W, const pts_estep_params& p, int32_t* nn, float* dist,
                      bool timing);
 // projected queries; padded_out: rows of ix.dp floats, else rows of ix.d

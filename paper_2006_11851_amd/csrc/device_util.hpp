@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+#include <climits>
+
 namespace pts {
 
 // XCD-aware block order.  The chip's 8 XCDs (each with its own L2) receive
@@ -15,5 +18,32 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
   const int q = G >> 3, r = G & 7, x = b & 7;
   return x * q + min(x, r) + (b >> 3);
 }
+
+// (score, id) order: ties to the lower id
+__device__ __forceinline__ bool lex_lt(float a, int ia, float b, int ib) { return a < b || (a == b && ia < ib); }
+
+struct Top8Lex {
+  float d[8];
+  int i[8];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      d[t] = FLT_MAX;
+      i[t] = INT_MAX;
+    }
+  }
+  __device__ __forceinline__ void insert(float v, int id) {
+    bool lt[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) lt[t] = lex_lt(v, id, d[t], i[t]);
+#pragma unroll
+    for (int t = 7; t > 0; --t) {
+      d[t] = lt[t - 1] ? d[t - 1] : (lt[t] ? v : d[t]);
+      i[t] = lt[t - 1] ? i[t - 1] : (lt[t] ? id : i[t]);
+    }
+    d[0] = lt[0] ? v : d[0];
+    i[0] = lt[0] ? id : i[0];
+  }
+};
 
 }  // namespace pts

@@ -40,7 +40,7 @@ void project_on(Ctx* c, const Index& ix, const float* x, int H, int W, int strid
 }
 
 EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, const pts_estep_params& p,
-                    int32_t* nn, float* dist, bool timing) {
+                    int32_t* nn, float* dist, bool timing, bool count_work) {
   validate_grid(H, W, p.w, p.stride);
   PTS_REQUIRE(p.w <= ex.Hz && p.w <= ex.Wz, PTS_ERR_ARG, "estep: window larger than the exemplar");
   const Grid g{H, W, p.w, p.stride};
@@ -110,7 +110,12 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       uint16_t* qb = bf ? c->buf<uint16_t>("qbf16", (size_t)nq * ix->dk) : nullptr;
       project_on(c, *ix, x, H, W, p.stride, qp, qb);
       int32_t* novf = nullptr;
-      st.fallbacks = search_learned(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist, &dist_done, bf, timing, &novf);
+      int64_t work[2] = {0, 0};
+      st.fallbacks =
+          search_learned(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist, &dist_done, bf, timing, &novf,
+                         count_work ? work : nullptr);
+      st.scan_rows = work[0];
+      st.collect_rows = work[1];
       if (timing && novf) {
         int32_t h = 0;
         PTS_HIP(hipMemcpyAsync(&h, novf, 4, hipMemcpyDeviceToHost, c->stream));
@@ -139,7 +144,7 @@ EstepStats run_estep(Ctx* c, const float* x, int H, int W, const pts_estep_param
                      bool timing) {
   ExView ex = ctx_exemplar(c);
   Index* ix = c->index.valid ? &c->index : nullptr;
-  return estep_on(c, ex, ix, x, H, W, p, nn, dist, timing);
+  return estep_on(c, ex, ix, x, H, W, p, nn, dist, timing, timing);
 }
 
 void project_queries(Ctx* c, const float* x, int H, int W, int stride, float* qproj, bool padded_out) {

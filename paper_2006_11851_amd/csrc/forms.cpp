@@ -28,7 +28,7 @@ bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H
 
 int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
                        const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist, bool* dist_done,
-                       bool bf16_scan, bool count_fallbacks, int32_t** scan_overflows) {
+                       bool bf16_scan, bool count_fallbacks, int32_t** scan_overflows, int64_t* work) {
   *dist_done = false;
   if (scan_overflows) *scan_overflows = nullptr;
   const int P = p.n_proposals <= 0 ? 4 : p.n_proposals;
@@ -57,12 +57,26 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
   BucketBufs b = bucket_buffers(c, nq * P1, L, chunk, &max_tiles);
   b.tile_order = ix.leaf_by_rows.as<int32_t>();
   launch_bucket(c, pair_leaf, nq * P1, L, chunk, b);
-  if (!bf16_scan) {
+  if (!bf16_scan && p.rerank_full) {
+    // the exact FP32 top-k over the members of the scanned leaves (PCA space),
+    // re-ranked by the full-dimension FP32 distance
+    const int k = p.topk <= 0 ? 8 : p.topk;
+    PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
+    float* pdd = c->buf<float>("ln_pair_cd", (size_t)nq * P1 * 8);
+    int32_t* pii = c->buf<int32_t>("ln_pair_ci", (size_t)nq * P1 * 8);
+    launch_leaf_scan_f32(c, qp, ix.dp, ix.zproj.as<float>(), ix.perm.as<int32_t>(), ix.leaf_off.as<int32_t>(), b,
+                         max_tiles, P1, p.residual ? ix.zres.as<float>() : nullptr, nullptr, nullptr, pdd, pii);
+    launch_select_rerank_full(c, pdd, pii, nq, P1, P1, 1, pair_leaf, nullptr, k, ix.perm.as<int32_t>(), ix.N, x, H, W,
+                              ix.w, p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);
+    *dist_done = dist != nullptr;
+    if (work) work[0] = count_scan_rows(c, pair_leaf, nq * P1, ix.leaf_off.as<int32_t>());
+  } else if (!bf16_scan) {
     int32_t* pid = c->buf<int32_t>("ln_pair_id", (size_t)nq * P1);
     float* pdd = c->buf<float>("ln_pair_d", (size_t)nq * P1);
     launch_leaf_scan_f32(c, qp, ix.dp, ix.zproj.as<float>(), ix.perm.as<int32_t>(), ix.leaf_off.as<int32_t>(), b,
                          max_tiles, P1, p.residual ? ix.zres.as<float>() : nullptr, pid, pdd);
     launch_merge_pairs_f32(c, pair_leaf, pid, pdd, nq, P1, nn);
+    if (work) work[0] = count_scan_rows(c, pair_leaf, nq * P1, ix.leaf_off.as<int32_t>());
   } else {
     PTS_REQUIRE(ix.has_bf16 && qb, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
     const int k = p.topk <= 0 ? 8 : p.topk;
@@ -83,6 +97,10 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     launch_bucket(c, pair_leaf2, nq * P1, L, chunk, b2);
     launch_leaf_scan_bf16_collect(c, qb, nq, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b2,
                                   max_tiles2, pair_leaf2, hc, &sh, novf);
+    if (work) {
+      work[0] = count_scan_rows(c, pair_leaf, nq * P1, ix.leaf_off.as<int32_t>());
+      work[1] = count_scan_rows(c, pair_leaf2, nq * P1, ix.leaf_off.as<int32_t>());
+    }
     if (scan_overflows) *scan_overflows = novf;
     if (p.rerank_full) {
       launch_select_rerank_full(c, nullptr, nullptr, nq, 0, 0, 0, nullptr, &sh, k, ix.perm.as<int32_t>(), ix.N, x, H,

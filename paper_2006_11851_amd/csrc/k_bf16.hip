@@ -63,33 +63,6 @@ struct TopK {
   }
 };
 
-// (score, id) order: ties to the lower id
-__device__ __forceinline__ bool lex_lt(float a, int ia, float b, int ib) { return a < b || (a == b && ia < ib); }
-
-struct Top8Lex {
-  float d[8];
-  int i[8];
-  __device__ __forceinline__ void init() {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      d[t] = FLT_MAX;
-      i[t] = INT_MAX;
-    }
-  }
-  __device__ __forceinline__ void insert(float v, int id) {
-    bool lt[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) lt[t] = lex_lt(v, id, d[t], i[t]);
-#pragma unroll
-    for (int t = 7; t > 0; --t) {
-      d[t] = lt[t - 1] ? d[t - 1] : (lt[t] ? v : d[t]);
-      i[t] = lt[t - 1] ? i[t - 1] : (lt[t] ? id : i[t]);
-    }
-    d[0] = lt[0] ? v : d[0];
-    i[0] = lt[0] ? id : i[0];
-  }
-};
-
 constexpr int BB_WAVES = 8;
 constexpr int BB_QPB = BB_WAVES * 64;  // queries per block
 constexpr int BB_STAGE = 128;          // exemplar rows per LDS stage
@@ -980,6 +953,35 @@ static HitLists hit_lists(const ScanHits* sh) {
     h.hs = sh->hs;
   }
   return h;
+}
+
+// rows[0] += the leaf sizes of the scanned pairs (pair_leaf >= 0): the
+// (query, exemplar) score count of a scan over them
+__global__ __launch_bounds__(256) void k_scan_rows(const int32_t* __restrict__ pair_leaf, int64_t n,
+                                                   const int32_t* __restrict__ leaf_off,
+                                                   unsigned long long* __restrict__ rows) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = 0;
+  if (p < n) {
+    const int l = pair_leaf[p];
+    if (l >= 0) v = (unsigned long long)(leaf_off[l + 1] - leaf_off[l]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(rows, v);
+}
+
+int64_t count_scan_rows(Ctx* c, const int32_t* pair_leaf, int64_t n, const int32_t* leaf_off) {
+  if (n == 0) return 0;
+  unsigned long long* d = c->buf<unsigned long long>("ls_rows_count", 1);
+  launch_zero_i32(c, reinterpret_cast<int32_t*>(d), 2);
+  hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, pair_leaf, n, leaf_off,
+                     d);
+  check_launch("k_scan_rows");
+  unsigned long long h = 0;
+  PTS_HIP(hipMemcpyAsync(&h, d, 8, hipMemcpyDeviceToHost, c->stream));
+  PTS_HIP(hipStreamSynchronize(c->stream));
+  return (int64_t)h;
 }
 
 void launch_leaf_scan_bf16_bound(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,

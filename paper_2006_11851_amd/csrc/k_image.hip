@@ -39,7 +39,9 @@ __device__ __forceinline__ int mirror(int i, int n) {
 }
 
 // [1 4 6 4 1] / 16 separable blur evaluated at the even samples (2xo, 2yo):
-// rows first, then columns, as a 5x5 tensor-product sum.
+// rows first, then columns, as a 5x5 tensor-product sum.  gw >= 0: the
+// guidance is recomputed at the coarse size; gw < 0: the image's own
+// guidance channel (a scale map) is blurred like the colours.
 __global__ __launch_bounds__(256) void k_blur_decimate(const float4* __restrict__ in, int H, int W, float gw,
                                                        float4* __restrict__ out) {
   const int Ho = H / 2, Wo = W / 2;
@@ -47,26 +49,29 @@ __global__ __launch_bounds__(256) void k_blur_decimate(const float4* __restrict_
   if (p >= (int64_t)Ho * Wo) return;
   const int yo = (int)(p / Wo), xo = (int)(p % Wo);
   const float k5[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
-  float r = 0.f, g = 0.f, b = 0.f;
+  float r = 0.f, g = 0.f, b = 0.f, sg = 0.f;
   for (int kx = 0; kx < 5; ++kx) {
     const int xx = mirror(2 * xo + kx - 2, W);
-    float cr = 0.f, cg = 0.f, cb = 0.f;
+    float cr = 0.f, cg = 0.f, cb = 0.f, cs = 0.f;
     for (int ky = 0; ky < 5; ++ky) {
       const int yy = mirror(2 * yo + ky - 2, H);
       const float4 v = in[(int64_t)yy * W + xx];
       cr = fmaf(k5[ky], v.x, cr);
       cg = fmaf(k5[ky], v.y, cg);
       cb = fmaf(k5[ky], v.z, cb);
+      cs = fmaf(k5[ky], v.w, cs);
     }
     r = fmaf(k5[kx], cr, r);
     g = fmaf(k5[kx], cg, g);
     b = fmaf(k5[kx], cb, b);
+    sg = fmaf(k5[kx], cs, sg);
   }
-  out[p] = make_float4(r, g, b, gw * ((float)yo + 0.5f) / (float)Ho);
+  out[p] = make_float4(r, g, b, gw < 0.f ? sg : gw * ((float)yo + 0.5f) / (float)Ho);
 }
 
 // Bilinear at coarse position ((x + 0.5) / 2 - 0.5, (y + 0.5) / 2 - 0.5),
-// x wraps, y clamps; guidance recomputed at the fine size.
+// x wraps, y clamps; guidance recomputed at the fine size (gw >= 0) or
+// interpolated like the colours (gw < 0: the image's own scale map).
 __global__ __launch_bounds__(256) void k_upsample2(const float4* __restrict__ in, int Hc, int Wc, float gw,
                                                    float4* __restrict__ out) {
   const int H = 2 * Hc, W = 2 * Wc;
@@ -85,7 +90,8 @@ __global__ __launch_bounds__(256) void k_upsample2(const float4* __restrict__ in
   o.x = (1.f - fy) * ((1.f - fx) * a.x + fx * b.x) + fy * ((1.f - fx) * c.x + fx * d.x);
   o.y = (1.f - fy) * ((1.f - fx) * a.y + fx * b.y) + fy * ((1.f - fx) * c.y + fx * d.y);
   o.z = (1.f - fy) * ((1.f - fx) * a.z + fx * b.z) + fy * ((1.f - fx) * c.z + fx * d.z);
-  o.w = gw * ((float)y + 0.5f) / (float)H;
+  o.w = gw < 0.f ? (1.f - fy) * ((1.f - fx) * a.w + fx * b.w) + fy * ((1.f - fx) * c.w + fx * d.w)
+                 : gw * ((float)y + 0.5f) / (float)H;
   out[p] = o;
 }
 
@@ -99,7 +105,27 @@ __global__ __launch_bounds__(256) void k_pack_exemplar(const uint8_t* __restrict
   if (p - (int64_t)y * W == 0) srow[y] = img[p].w;
 }
 
+// cnt[0] += the number of values of x [n] that are not finite
+__global__ __launch_bounds__(256) void k_count_nonfinite(const float* __restrict__ x, int64_t n, int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool bad = i < n && !isfinite(x[i]);
+  const uint64_t m = __ballot(bad);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(cnt, (int)__popcll(m));
+}
+
 static unsigned blocks_for(int64_t n, int per) { return (unsigned)ceil_div(n, per); }
+
+int64_t count_nonfinite(Ctx* c, const float* x, int64_t n) {
+  if (n == 0) return 0;
+  int* d = c->buf<int>("nonfinite_count", 1);
+  launch_zero_i32(c, d, 1);
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, x, n, d);
+  check_launch("k_count_nonfinite");
+  int h = 0;
+  PTS_HIP(hipMemcpyAsync(&h, d, 4, hipMemcpyDeviceToHost, c->stream));
+  PTS_HIP(hipStreamSynchronize(c->stream));
+  return h;
+}
 
 void launch_pack_exemplar(Ctx* c, const uint8_t* u8, int H, int W, const float* img, uint32_t* pk, float* srow) {
   ProfScope ps(c, "pack_exemplar");

@@ -16,6 +16,7 @@
 #include <climits>
 
 #include "kernels_bf16.hpp"
+#include "device_util.hpp"
 
 namespace pts {
 
@@ -416,7 +417,10 @@ __device__ __forceinline__ bool better_id(float d, int id, float bd, int bid) {
   return d < bd || (d == bd && id < bid);
 }
 
-template <int DP>
+// TOPK: each pair keeps its 8 best (distance, leaf position) instead of the
+// single best id, written sorted to top_d / top_i [pair][8] (with the
+// optional offset added, as the ranking uses it).
+template <int DP, bool TOPK>
 __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__ Qp, const float* __restrict__ Zp,
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ leaf_off,
@@ -425,7 +429,8 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
                                                        const int2* __restrict__ tiles,
                                                        const int32_t* __restrict__ ntiles, int P,
                                                        const float* __restrict__ zres,
-                                                       int32_t* __restrict__ nn, float* __restrict__ best_d2) {
+                                                       int32_t* __restrict__ nn, float* __restrict__ best_d2,
+                                                       float* __restrict__ top_d, int32_t* __restrict__ top_i) {
   // member rows stream through two LDS buffers: chunk c + 1 is stored while
   // chunk c is scanned, and chunk c + 2 is loaded into registers meanwhile
   constexpr int NF4 = LS_M * (DP / 4);          // float4 per chunk
@@ -459,6 +464,8 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
   }
   float bd = FLT_MAX;
   int bi = INT_MAX;
+  Top8Lex top;
+  if constexpr (TOPK) top.init();
   const int m0 = leaf_off[l], m1 = leaf_off[l + 1];
   const int nchunks = (m1 - m0 + LS_M - 1) / LS_M;
   // chunk loads carry no condition (rows past the leaf re-read its last row
@@ -517,13 +524,43 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
         acc = fmaf(t3, t3, acc);
       }
       acc += Zr[b][r];
-      const int id = Zid[b][r];
-      if (better_id(acc, id, bd, bi)) {
-        bd = acc;
-        bi = id;
+      if constexpr (TOPK) {
+        const int mp = m0 + c * LS_M + r;  // the member's leaf position
+        if (lex_lt(acc, mp, top.d[7], top.i[7])) top.insert(acc, mp);
+      } else {
+        const int id = Zid[b][r];
+        if (better_id(acc, id, bd, bi)) {
+          bd = acc;
+          bi = id;
+        }
       }
     }
     lds_barrier();
+  }
+  if constexpr (TOPK) {
+    // the 4 waves' lists through LDS
+    __shared__ float ld[4 * 8 * LS_Q];
+    __shared__ int li[4 * 8 * LS_Q];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      ld[(wave * 8 + t) * LS_Q + lane] = top.d[t];
+      li[(wave * 8 + t) * LS_Q + lane] = top.i[t];
+    }
+    __syncthreads();
+    if (wave == 0 && active) {
+      for (int w = 1; w < 4; ++w)
+        for (int t = 0; t < 8; ++t) {
+          const float v = ld[(w * 8 + t) * LS_Q + lane];
+          const int i = li[(w * 8 + t) * LS_Q + lane];
+          if (lex_lt(v, i, top.d[7], top.i[7])) top.insert(v, i);
+        }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        top_d[(int64_t)pair * 8 + t] = top.d[t];
+        top_i[(int64_t)pair * 8 + t] = top.i[t];
+      }
+    }
+    return;
   }
   rd[wave][lane] = bd;
   ri[wave][lane] = bi;
@@ -541,11 +578,18 @@ __global__ __launch_bounds__(256) void k_leaf_scan_f32(const float* __restrict__
 
 void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
                           const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, const float* zres,
-                          int32_t* nn, float* best_d2) {
+                          int32_t* nn, float* best_d2, float* top_d, int32_t* top_i) {
   ProfScope ps(c, "leaf_scan_f32");
   if (max_tiles == 0) return;
-  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_leaf_scan_f32<DPC>, dim3(max_tiles), dim3(256), 0, c->stream, Qp, Zp, perm,
-                                       leaf_off, b.off, b.order, b.tiles, b.ntiles, P, zres, nn, best_d2));
+  if (top_d) {
+    PTS_DP_SWITCH(dp, hipLaunchKernelGGL((k_leaf_scan_f32<DPC, true>), dim3(max_tiles), dim3(256), 0, c->stream, Qp,
+                                         Zp, perm, leaf_off, b.off, b.order, b.tiles, b.ntiles, P, zres, nn, best_d2,
+                                         top_d, top_i));
+  } else {
+    PTS_DP_SWITCH(dp, hipLaunchKernelGGL((k_leaf_scan_f32<DPC, false>), dim3(max_tiles), dim3(256), 0, c->stream, Qp,
+                                         Zp, perm, leaf_off, b.off, b.order, b.tiles, b.ntiles, P, zres, nn, best_d2,
+                                         nullptr, nullptr));
+  }
   check_launch("k_leaf_scan_f32");
 }
 

@@ -10,6 +10,8 @@ namespace pts {
 void launch_rgbs_from_u8(Ctx* c, const uint8_t* u8, int H, int W, float gw, float* out);
 // the 8-bit form of an exemplar (see Ctx::ex_pk): u8 [H][W][3], img its RGBS floats
 void launch_pack_exemplar(Ctx* c, const uint8_t* u8, int H, int W, const float* img, uint32_t* pk, float* srow);
+// number of non-finite values in x [n] (synchronous)
+int64_t count_nonfinite(Ctx* c, const float* x, int64_t n);
 void launch_fill_guidance(Ctx* c, float* x, int H, int W, float gw);
 void launch_blur_decimate(Ctx* c, const float* in, int H, int W, float gw, float* out);
 void launch_upsample2(Ctx* c, const float* in, int H, int W, float gw, float* out);
@@ -83,12 +85,14 @@ void launch_descend_low_margin(Ctx* c, const float* Qp, int64_t nq, int dp, cons
                                const float* cent, const int32_t* first_child, const int32_t* n_children,
                                const int32_t* leaf_of_node, int n_nodes, int32_t* list, int32_t* n, int32_t* leaf);
 void launch_bucket(Ctx* c, const int32_t* leaf, int64_t n, int n_leaves, int chunk, BucketBufs b);
-// order[] holds pair indices (query * P + slot); results per pair.  The
+// order[] holds pair indices (query * P + slot); results per pair: the best
+// id and distance (nn, best_d2), or with top_d non-null the 8 best
+// (distance, leaf position) sorted into top_d / top_i [pair][8].  The
 // bucketing for it must use chunks of leaf_scan_f32_chunk(dp) pairs.
 int leaf_scan_f32_chunk(int dp);
 void launch_leaf_scan_f32(Ctx* c, const float* Qp, int dp, const float* Zp, const int32_t* perm,
                           const int32_t* leaf_off, const BucketBufs& b, int max_tiles, int P, const float* zres,
-                          int32_t* nn, float* best_d2);
+                          int32_t* nn, float* best_d2, float* top_d = nullptr, int32_t* top_i = nullptr);
 void launch_learned_pairs(Ctx* c, const int32_t* prop, const float* margin, const int32_t* dleaf, int64_t nq, int P,
                           float thr, int n_leaves, int32_t* pair_leaf, int32_t* fallbacks);
 void launch_merge_pairs_f32(Ctx* c, const int32_t* pair_leaf, const int32_t* pair_id, const float* pair_d, int64_t nq,

@@ -50,6 +50,8 @@ int leaf_scan_bf16_chunk();
 // leaf.  Collect (over the pairs bucketed from pair_leaf2): the rows within
 // tau, hc slots per pair and half (0..16); queries with more rows go to a
 // per-query pass.  n_overflow: device int32, the number of such queries.
+// sum of the leaf sizes over the pairs with pair_leaf >= 0 (synchronous)
+int64_t count_scan_rows(Ctx* c, const int32_t* pair_leaf, int64_t n, const int32_t* leaf_off);
 void launch_leaf_scan_bf16_bound(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
                                  int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles,
                                  const int32_t* pair_leaf, int32_t* pair_leaf2);

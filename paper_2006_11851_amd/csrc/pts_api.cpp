@@ -106,6 +106,8 @@ int pts_set_exemplar(pts_ctx* c, const float* rgbs, int Hz, int Wz) {
   return guard(c, [&] {
     PTS_REQUIRE(rgbs && Hz >= 2 && Wz >= 2, PTS_ERR_ARG, "set_exemplar: bad image");
     PTS_REQUIRE((int64_t)Hz * Wz <= ((int64_t)1 << 26), PTS_ERR_UNSUPPORTED, "exemplar larger than 2^26 pixels");
+    PTS_REQUIRE(count_nonfinite(c, rgbs, (int64_t)Hz * Wz * 4) == 0, PTS_ERR_ARG,
+                "set_exemplar: the image holds non-finite values");
     float* dst = static_cast<float*>(c->ex.ensure(c, (size_t)Hz * Wz * 16));
     PTS_HIP(hipMemcpyAsync(dst, rgbs, (size_t)Hz * Wz * 16, hipMemcpyDeviceToDevice, c->stream));
     c->Hz = Hz;
@@ -121,6 +123,7 @@ int pts_set_exemplar_u8(pts_ctx* c, const uint8_t* rgb_host, int Hz, int Wz, flo
   CTX_REQUIRED(c);
   return guard(c, [&] {
     PTS_REQUIRE(rgb_host && Hz >= 2 && Wz >= 2, PTS_ERR_ARG, "set_exemplar_u8: bad image");
+    PTS_REQUIRE(std::isfinite(gw), PTS_ERR_ARG, "set_exemplar_u8: guidance weight must be finite");
     PTS_REQUIRE((int64_t)Hz * Wz <= ((int64_t)1 << 26), PTS_ERR_UNSUPPORTED, "exemplar larger than 2^26 pixels");
     uint8_t* tmp = c->buf<uint8_t>("u8_upload", (size_t)Hz * Wz * 3);
     PTS_HIP(hipMemcpyAsync(tmp, rgb_host, (size_t)Hz * Wz * 3, hipMemcpyHostToDevice, c->stream));
@@ -195,11 +198,17 @@ int pts_estep(pts_ctx* c, const float* x, int H, int W, const pts_estep_params* 
   CTX_REQUIRED(c);
   return guard(c, [&] {
     PTS_REQUIRE(p && x && nn && dist, PTS_ERR_ARG, "estep: null argument");
+    if (st) {  // the statistics call waits anyway: the image is checked too
+      PTS_REQUIRE(H > 0 && W > 0, PTS_ERR_ARG, "estep: bad image size");
+      PTS_REQUIRE(count_nonfinite(c, x, (int64_t)H * W * 4) == 0, PTS_ERR_ARG, "estep: the image holds non-finite values");
+    }
     EstepStats s = run_estep(c, x, H, W, *p, nn, dist, st != nullptr);
     if (st) {
       st->nq = s.nq;
       st->fallbacks = s.fallbacks;
       st->scan_overflows = s.scan_overflows;
+      st->scan_rows = s.scan_rows;
+      st->collect_rows = s.collect_rows;
       st->ms = s.ms;
     }
   });
@@ -322,6 +331,9 @@ int pts_solve(pts_ctx* c, const pts_solve_params* p, const float* x0, int H0, in
   CTX_REQUIRED(c);
   return guard(c, [&] {
     PTS_REQUIRE(p && x0 && x, PTS_ERR_ARG, "solve: null argument");
+    PTS_REQUIRE(H0 > 0 && W0 > 0, PTS_ERR_ARG, "solve: bad image size");
+    PTS_REQUIRE(count_nonfinite(c, x0, (int64_t)H0 * W0 * 4) == 0, PTS_ERR_ARG,
+                "solve: the initial output holds non-finite values");
     run_solve(c, *p, x0, H0, W0, x, H, W, tr);
   });
 }

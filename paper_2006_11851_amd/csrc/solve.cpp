@@ -20,12 +20,14 @@ const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int*
     c->pyr_h.assign(levels, 0);
     c->pyr_w.assign(levels, 0);
     for (int l = 0; l < levels; ++l) c->pyr_img.emplace_back(new DevMem());
-    // finest = the exemplar itself (guidance rewritten with this weight)
+    // finest = the exemplar itself, its guidance rewritten with this weight
+    // (gw < 0: its own guidance channel kept, and blurred for the coarser levels)
     const int L = levels - 1;
     c->pyr_h[L] = c->Hz;
     c->pyr_w[L] = c->Wz;
     float* fin = static_cast<float*>(c->pyr_img[L]->ensure(c, (size_t)c->Hz * c->Wz * 16));
     PTS_HIP(hipMemcpyAsync(fin, c->ex.ptr, (size_t)c->Hz * c->Wz * 16, hipMemcpyDeviceToDevice, c->stream));
+    if (gw >= 0.f) launch_fill_guidance(c, fin, c->Hz, c->Wz, gw);
     for (int l = L - 1; l >= 0; --l) {
       c->pyr_h[l] = c->pyr_h[l + 1] / 2;
       c->pyr_w[l] = c->pyr_w[l + 1] / 2;

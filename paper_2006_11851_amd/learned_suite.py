@@ -2,15 +2,15 @@
 
 For each exemplar (the 256^2 -> 512^2 workload's finest level: 8 x 8
 windows on the stride-2 grid, PCA 64, 32-way k-means tree of depth 2 =
-1024 leaves): build the index, label every query of two plain search/blend
-iterations with the leaf of its exhaustive full-dimension match (about
-130 000 pairs per exemplar, ~2M over 16 exemplars), train the leaf-proposal
-MLP on them, then run ten learned search/blend iterations from another
-initial output and measure, at every iterate, the energy gap to
-exhaustive search on the same image (G_t = E(x; nn_method) / E(x; nn_exact)
-- 1): the learned form with an FP32 scan of the proposed leaves in PCA
-space, the same with BF16 scans and an FP32 full-dimension re-rank of 8
-candidates, and the plain tree.  Each exemplar's network proposes the leaves
+1024 leaves): build the index, label sampled queries of two plain
+search/blend iterations and of six other initial outputs with the leaf of
+their exhaustive full-dimension match (131 072 pairs per exemplar, ~2.1M
+over 16 exemplars), train the leaf-proposal MLP on them, then run ten
+learned search/blend iterations from another initial output and measure,
+at every iterate, the energy gap to exhaustive search on the same image
+(G_t = E(x; nn_method) / E(x; nn_exact) - 1): the learned form with an
+exact FP32 scan of the proposed leaves (top-8 in PCA space, re-ranked in
+full dimension), the same with BF16 scans, and the plain tree.  Each exemplar's network proposes the leaves
 of that exemplar's tree.  Only C-ABI calls are sequenced here.
 """
 from __future__ import annotations
@@ -22,27 +22,28 @@ import numpy as np
 from . import synth, training
 
 
-def run_exemplar(ctx, wl, seed: int, iters: int = 10, train_iters: int = 2, epochs: float = 8.0,
-                 mode: str = "learned", margin: float = 0.2, log=None):
+def run_exemplar(ctx, wl, seed: int, iters: int = 10, train_iters: int = 2, extra_inits: int = 6,
+                 per_source: int = 16384, epochs: float = 16.0, mode: str = "learned", margin: float = 0.2,
+                 n_proposals: int = 4, residual: int = 0, log=None):
     w, s = wl.w[-1], wl.stride[-1]
     H = wl.out_size
     ex = wl.exemplar(seed)
     ctx.set_exemplar_u8(ex, 0.5)
     info = ctx.build_index(w, wl.pca_dims, wl.branching, wl.depth, seed=0, make_bf16=True)
-    init, _ = synth.row_matched_init(seed, ex, H, H, w)
-    x0 = ctx.rgbs_from_u8(init, 0.5)
     t0 = time.time()
-    q, lab = training.collect_pairs(ctx, x0, w, s, train_iters)
+    q, lab = training.collect_training_pairs(ctx, ex, H, H, w, s, seed, solve_iters=train_iters,
+                                             extra_inits=extra_inits, per_source=per_source, seed=seed)
     ctx.mlp_init(info.d, 256, info.n_leaves, seed=seed)
     losses = training.train(ctx, q, lab, epochs=epochs, batch=4096, lr=2e-3, log_every=25)
-    prop, _ = ctx.mlp_propose(q, 4)
+    prop, _ = ctx.mlp_propose(q, n_proposals)
     recall = float((prop == lab[:, None]).any(dim=1).float().mean())
     train_s = time.time() - t0
     # evaluation from another initial output
     init2, _ = synth.row_matched_init(seed + 1000, ex, H, H, w)
     res = {}
-    forms = (("learned", dict(mode=mode, margin=margin, n_proposals=4)),
-             ("learned_bf16", dict(mode="learned_bf16", margin=margin, n_proposals=4, rerank_full=1)),
+    forms = (("learned", dict(mode=mode, margin=margin, n_proposals=n_proposals, rerank_full=1)),
+             ("learned_bf16", dict(mode="learned_bf16", margin=margin, n_proposals=n_proposals, rerank_full=1,
+                                   residual=residual)),
              ("tree", dict(mode="tree")))
     for name, kw in forms:
         x = ctx.rgbs_from_u8(init2, 0.5)

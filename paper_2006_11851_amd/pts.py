@@ -45,8 +45,53 @@ class PtsError(RuntimeError):
         self.code = code
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
 class pts_alloc(C.Structure):
-    _fields_ = [("alloc", C.c_void_p), ("release", C.c_void_p), ("user", C.c_void_p)]
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Serves the library's device memory (exemplar copy, pyramid, index,
+    MLP, scratch) from PyTorch's caching allocator on the context's stream.
+    ``budget`` (bytes, optional) makes it refuse requests that would exceed
+    it, as a full device would: the library then returns PTS_ERR_OOM."""
+
+    def __init__(self, device: int = 0, budget: int | None = None):
+        self.device = device
+        self.budget = budget
+        self.in_use = 0
+        self.sizes = {}
+        self.refused = 0
+        self._alloc = ALLOC_FN(self._on_alloc)
+        self._release = RELEASE_FN(self._on_release)
+
+    def _on_alloc(self, user, nbytes, stream):
+        import torch
+
+        if self.budget is not None and self.in_use + nbytes > self.budget:
+            self.refused += 1
+            return None
+        try:
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or None)
+        except RuntimeError:
+            self.refused += 1
+            return None
+        self.sizes[ptr] = int(nbytes)
+        self.in_use += int(nbytes)
+        return ptr
+
+    def _on_release(self, user, ptr, nbytes, stream):
+        import torch
+
+        if ptr:
+            self.in_use -= self.sizes.pop(ptr, 0)
+            torch.cuda.caching_allocator_delete(ptr)
+
+    def struct(self):
+        return pts_alloc(self._alloc, self._release, None)
 
 
 class pts_index_params(C.Structure):
@@ -112,7 +157,8 @@ class pts_estep_params(C.Structure):
 
 
 class pts_estep_stats(C.Structure):
-    _fields_ = [("nq", C.c_int64), ("fallbacks", C.c_int64), ("scan_overflows", C.c_int64), ("ms", C.c_double)]
+    _fields_ = [("nq", C.c_int64), ("fallbacks", C.c_int64), ("scan_overflows", C.c_int64),
+                ("scan_rows", C.c_int64), ("collect_rows", C.c_int64), ("ms", C.c_double)]
 
 
 class pts_mstep_params(C.Structure):
@@ -283,14 +329,19 @@ def eig_sym_top(Cm: np.ndarray, d: int, nthreads: int = 0):
 class Context:
     """One libpts context on a torch device, ordered on the current stream."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, allocator: "TorchAllocator | None" = None):
+        """allocator: None = the library's own (hipMalloc); a TorchAllocator
+        serves the library's memory from PyTorch's caching allocator."""
         import torch
 
         self.torch = torch
         self.device = torch.device("cuda", device)
         self._h = C.c_void_p()
+        self.allocator = allocator  # kept alive as long as the context
         stream = torch.cuda.current_stream(self.device).cuda_stream
-        _check(lib().pts_create(C.byref(self._h), device, C.c_void_p(stream), None), None)
+        self._alloc_struct = allocator.struct() if allocator is not None else None
+        _check(lib().pts_create(C.byref(self._h), device, C.c_void_p(stream),
+                                C.byref(self._alloc_struct) if self._alloc_struct is not None else None), None)
         self.index_info = None
 
     # -- plumbing

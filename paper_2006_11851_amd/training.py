@@ -10,6 +10,8 @@ from __future__ import annotations
 
 import torch
 
+from . import synth
+
 
 def collect_pairs(ctx, x0, w: int, stride: int, iters: int, mode: str = "tree"):
     """Run `iters` search/blend iterations from x0 (not modified); return
@@ -49,4 +51,23 @@ def collect_pairs_sampled(ctx, x0, w: int, stride: int, iters: int, per_iter: in
         ls.append(ctx.leaf_of(nn_exact))
         nn, dist = ctx.estep(x, w, stride, mode=mode)
         ctx.mstep(nn, dist, x, w, stride)
+    return torch.cat(qs).contiguous(), torch.cat(ls).contiguous()
+
+
+def collect_training_pairs(ctx, ex_u8, H: int, W: int, w: int, stride: int, init_seed: int, solve_iters: int = 2,
+                           extra_inits: int = 6, per_source: int = 16384, seed: int = 0, guidance: float = 0.5):
+    """The training recipe: pairs from `solve_iters` iterations of a plain
+    solve started from the initial output of `init_seed`, plus the initial
+    outputs of `extra_inits` other seeds (init_seed + 2000 + k), a seeded
+    sample of `per_source` queries from each.  The extra initial outputs
+    matter: a solve's first iterations move its queries away from those of a
+    freshly initialised output, which the network must also serve."""
+    src, _ = synth.row_matched_init(init_seed, ex_u8, H, W, w)
+    q, lab = collect_pairs_sampled(ctx, ctx.rgbs_from_u8(src, guidance), w, stride, solve_iters, per_source, seed=seed)
+    qs, ls = [q], [lab]
+    for k in range(extra_inits):
+        ik, _ = synth.row_matched_init(init_seed + 2000 + k, ex_u8, H, W, w)
+        a, b = collect_pairs_sampled(ctx, ctx.rgbs_from_u8(ik, guidance), w, stride, 1, per_source, seed=seed + 1 + k)
+        qs.append(a)
+        ls.append(b)
     return torch.cat(qs).contiguous(), torch.cat(ls).contiguous()

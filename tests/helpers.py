@@ -67,14 +67,16 @@ def scanned_members(t, leaves) -> np.ndarray:
     return np.unique(np.concatenate([t.leaf_members(int(l)) for l in leaves]))
 
 
-def topk_rerank_validity(Qp, Zp, t, lists, got, k=8, offset=None, Q_full=None, Zm=None, mu=None):
+def topk_rerank_validity(Qp, Zp, t, lists, got, k=8, offset=None, Q_full=None, Zm=None, mu=None, bf16=True):
     """Per query: is ``got`` a valid outcome of the exact BF16 top-k over the
     members of the leaves in ``lists[i]`` (with t None: lists[i] holds the
     exemplar ids themselves) followed by the FP32 re-rank (full
     dimension when Q_full/Zm are given, else PCA space with the offset)?
     The scores are the oracle's exact values; two scores closer than the
     bound of their FP32 evaluation (or 1e-4 of the k-th) may be ordered
-    either way (oracle.parity.topk_rerank_valid).  Returns a bool array."""
+    either way (oracle.parity.topk_rerank_valid).  bf16=False: the scores are
+    the unrounded PCA-space distances the FP32 scan ranks by (evaluated in
+    the direct form, whose FP32 error is relative).  Returns a bool array."""
     from oracle import bf16 as obf16
     from oracle import parity
 
@@ -83,10 +85,16 @@ def topk_rerank_validity(Qp, Zp, t, lists, got, k=8, offset=None, Q_full=None, Z
     for i, ls in enumerate(lists):
         m = scanned_members(t, ls) if t is not None else np.unique(np.asarray(ls, dtype=np.int64))
         off = None if offset is None else offset[m]
-        sc = obf16.scan_scores(Qp[i], Zp[m], off)
-        sk = np.sort(sc)[min(k, sc.size) - 1]
-        tol = max(1e-4 * abs(sk), obf16.fp32_score_tolerance(
-            Qp[i], Zp[m], d, off, None if (offset is None or Zm is None) else Zm[m], mu))
+        if bf16:
+            sc = obf16.scan_scores(Qp[i], Zp[m], off)
+            sk = np.sort(sc)[min(k, sc.size) - 1]
+            tol = max(1e-4 * abs(sk), obf16.fp32_score_tolerance(
+                Qp[i], Zp[m], d, off, None if (offset is None or Zm is None) else Zm[m], mu))
+        else:
+            df = Zp[m] - Qp[i][None, :]
+            sc = np.einsum("ij,ij->i", df, df) + (0.0 if off is None else off)
+            sk = np.sort(sc)[min(k, sc.size) - 1]
+            tol = max(1e-4, 2 * (d + 4) * 2.0 ** -24) * abs(sk)
         if Q_full is not None:
             diff = Zm[m] - Q_full[i][None, :]
         else:

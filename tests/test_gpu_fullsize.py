@@ -98,3 +98,27 @@ def test_headline_learned_bf16_sampled(headline):
     assert 0.05 <= fb <= 0.5, fb
     dg = parity.sqdist_rows(S["Q"], S["Zm"], got)
     assert np.allclose(_np(dist)[sample], np.sqrt(dg), rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("o", [0, 1])
+def test_headline_mstep_both_patch_origins(headline, o):
+    """The blend over the whole 2048^2 output at w = 8, s = 2 (16 covering
+    windows per patch at o = 0, 9 wholly containing ones at o = 1),
+    teacher-forced with the GPU's tree matches, against the oracle's."""
+    from oracle import irls, mstep
+    from paper_2006_11851_amd import synth
+
+    S = headline
+    ctx, w, s = S["ctx"], S["w"], S["s"]
+    x = S["x"].clone()
+    nn, dist = ctx.estep(x, w, s, mode="tree")
+    wl = synth.workload("ex1024_out2048")
+    ex = wl.exemplar()
+    init, _ = synth.row_matched_init(wl.init_seed, ex, wl.out_size, wl.out_size, w)
+    X = vectors.rgbs(init, 0.5)
+    Z = vectors.rgbs(ex, 0.5)
+    Xo, _ = mstep.mstep(X, Z, _np(nn).astype(np.int64), irls.weights(_np(dist).astype(np.float64)), w, s, o)
+    ctx.mstep(nn, dist, x, w, s, 0.8, 1e-3, o)
+    err = np.abs(_np(x) - Xo).max()
+    print(f"headline mstep o={o}: max pixel difference {err:.2e}", flush=True)
+    assert err <= 1e-3, err

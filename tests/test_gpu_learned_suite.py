@@ -1,9 +1,9 @@
 """The learned-proposal form over seeded exemplars (the 256^2 -> 512^2
-workload's finest level): trained on pairs the plain method generates, its
-energy gap to exhaustive search stays below the plain tree's; with BF16
-scans and the full-dimension re-rank it is within 1.5 % at the initial
-output and within 1 % from the third iteration on; two of the sixteen
-exemplars."""
+workload's finest level): trained on pairs the plain method generates, both
+learned forms (exact FP32 scan of the proposed leaves, BF16 scans; each
+with the exact top-8 re-ranked in full dimension) stay within 1 % of
+exhaustive search at every one of ten iterates from a held-out initial
+output, and below the plain tree's gap; two of the sixteen exemplars."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -16,7 +16,8 @@ def test_learned_suite_two_exemplars(gpu_ctx):
     rows = learned_suite.run(gpu_ctx, [100, 101], log=lambda m: print(m, flush=True))
     for r in rows:
         assert r["pairs"] >= 120000
-        assert r["learned"]["max_gap"] < r["tree"]["max_gap"]
-        assert r["learned_bf16"]["max_gap"] < r["tree"]["max_gap"]
-        G = r["learned_bf16"]["gaps"]
-        assert G[0] <= 0.015 and max(G[2:]) <= 0.01, G
+        for form in ("learned", "learned_bf16"):
+            G = r[form]["gaps"]
+            print(form, ["%.4f" % g for g in G], flush=True)
+            assert max(G) <= 0.01, (form, G)
+            assert r[form]["max_gap"] < r["tree"]["max_gap"]

@@ -181,6 +181,14 @@ def test_learned_search_teacher_forced(learned_c1, mode):
     assert st.fallbacks == sum(1 for i in range(L.shape[0]) if not (M[i] >= 0.2))
     if mode == "learned":
         nn_o, _ = tree.search_leaves(Qp, Zp, t, lists)
+        # the exact FP32 top-8 over the scanned members, re-ranked in full dimension
+        from oracle import vectors
+
+        nn_r, _ = ctx.estep(x, 8, 4, mode=mode, rerank_full=1)
+        Q, Zm = helpers.query_and_exemplar(vectors.rgbs(S["init"]), vectors.rgbs(S["ex"]), 8, 4)
+        valid = helpers.topk_rerank_validity(Qp, Zp, t, lists, _np(nn_r), 8, Q_full=Q, Zm=Zm, bf16=False)
+        print(f"learned + full-D re-rank: valid outcomes {valid.mean():.4f}", flush=True)
+        assert valid.mean() >= 0.999, valid.mean()
     else:
         # the exact BF16 top-8 over the scanned members, re-ranked in FP32 PCA space
         valid = helpers.topk_rerank_validity(Qp, Zp, t, lists, _np(nn), 8)

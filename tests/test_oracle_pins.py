@@ -566,6 +566,27 @@ def test_scan_rerank_invariant():
     assert inside >= 140
 
 
+def test_search_leaves_topk_over_every_leaf_is_exhaustive_topk():
+    # the FP32 learned form's candidates over every leaf are the exhaustive
+    # top-k in PCA space (with and without the offset), and the first of them
+    # is the leaf search's winner
+    r = np.random.default_rng(26)
+    Zp = r.normal(size=(500, 6))
+    Qp = Zp[r.integers(0, 500, 30)] + 0.05 * r.normal(size=(30, 6))
+    t = tree.build(Zp, 4, 2, seed=0)
+    every = [list(range(t.n_leaves))] * 30
+    off = r.uniform(0, 0.3, 500)
+    for o in (None, off):
+        ids, d2 = tree.search_leaves_topk(Qp, Zp, t, every, 8, offset=o)
+        ids_e, d2_e = exact.topk(Qp, Zp, 8, offset=o)
+        assert np.array_equal(np.stack(ids), ids_e)
+        assert np.allclose(np.stack(d2), d2_e, rtol=1e-12, atol=1e-12)
+    leaves, _ = tree.descend(t, Qp)
+    ids1, _ = tree.search_leaves_topk(Qp, Zp, t, leaves, 8)
+    nn1, _ = tree.search_leaves(Qp, Zp, t, leaves)
+    assert np.array_equal(np.array([a[0] for a in ids1]), nn1)
+
+
 def test_topk_rerank_validity_rule():
     ids = np.arange(20)
     score = np.arange(20, dtype=np.float64)  # well separated
