@@ -527,18 +527,19 @@ __device__ __forceinline__ void hit_flush(HitLane& L, const int2* lbuf, int hc) 
 }
 
 // rows of a tile (accumulator acc, first row tpos) at or below the query's
-// bound, tested in pairs (values r and r + 8: rows i and i + 16)
-__device__ __forceinline__ void collect_rows(const floatx16& acc, HitLane& L, int2* lbuf, int hc, int tpos,
-                                             int row_end) {
+// bound, tested four values at a time (rows i, i + 8, i + 16, i + 24 of the
+// lane's half) so that a tile takes 4 tests.  Rows past the leaf score
+// FLT_MAX and the bound's score is held below FLT_MAX, so they never pass.
+__device__ __forceinline__ void collect_rows(const floatx16& acc, HitLane& L, int2* lbuf, int hc, int tpos) {
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    if (__builtin_fminf(acc[c], acc[c + 8]) <= L.tv) {
+  for (int c = 0; c < 4; ++c) {
+    const float m = __builtin_fminf(__builtin_fminf(acc[c], acc[c + 4]), __builtin_fminf(acc[c + 8], acc[c + 12]));
+    if (m <= L.tv) {
 #pragma unroll
-      for (int r = c; r < 16; r += 8) {
+      for (int r = c; r < 16; r += 4) {
         const float v = acc[r];
         const int pos = tpos + 8 * (r >> 2) + (r & 3);
-        if (v <= L.tv && pos < row_end && (v < L.tv || pos <= L.tp))
-          hit_push(L, lbuf, hc, make_int2(__float_as_int(v), pos));
+        if (v <= L.tv && (v < L.tv || pos <= L.tp)) hit_push(L, lbuf, hc, make_int2(__float_as_int(v), pos));
       }
     }
   }
@@ -574,8 +575,8 @@ __device__ __forceinline__ void stage_collect(const BruteSmem<KS>& S, int buf, c
       cinit[4 * g + 3] = z4.w;
     }
     if (t > 0) {
-      collect_rows(accp[0], L0, lbuf, hc, pos0 + (t - 1) * 32 + hofs, row_end);
-      collect_rows(accp[1], L1, lbuf, hc, pos0 + (t - 1) * 32 + hofs, row_end);
+      collect_rows(accp[0], L0, lbuf, hc, pos0 + (t - 1) * 32 + hofs);
+      collect_rows(accp[1], L1, lbuf, hc, pos0 + (t - 1) * 32 + hofs);
     }
     floatx16 accn[2] = {cinit, cinit};
 #pragma unroll
@@ -586,8 +587,8 @@ __device__ __forceinline__ void stage_collect(const BruteSmem<KS>& S, int buf, c
     accp[0] = accn[0];
     accp[1] = accn[1];
   }
-  collect_rows(accp[0], L0, lbuf, hc, pos0 + (BB_STAGE / 32 - 1) * 32 + hofs, row_end);
-  collect_rows(accp[1], L1, lbuf, hc, pos0 + (BB_STAGE / 32 - 1) * 32 + hofs, row_end);
+  collect_rows(accp[0], L0, lbuf, hc, pos0 + (BB_STAGE / 32 - 1) * 32 + hofs);
+  collect_rows(accp[1], L1, lbuf, hc, pos0 + (BB_STAGE / 32 - 1) * 32 + hofs);
 }
 
 // One tile = (leaf, LS_QPB pairs of the bucketed order); rows = the leaf's
@@ -645,7 +646,10 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       L.lds = (tid * 2 + qt) * HB_STAGE;
       if (pr[qt] >= 0) {
         const uint64_t k = o.tau_q[qid[qt]];
-        L.tv = key_score(k);
+        // a bound of FLT_MAX (fewer than 8 rows in all of the query's
+        // leaves: every row qualifies) is held just below it, so that the
+        // padding rows, which score FLT_MAX, never qualify
+        L.tv = fminf(key_score(k), 0x1.fffffcp127f);
         L.tp = key_pos(k);
         L.dst = o.hits + ((int64_t)pr[qt] * 2 + h) * o.hs;
       } else {  // nothing is ever collected for a lane without a pair
