@@ -223,6 +223,11 @@ typedef struct pts_mstep_params {
   float delta;      /* distance floor for W = max(d, delta)^(r-2), 1e-3 */
   int patch_offset; /* 0: patches at even origins (exact IRLS minimiser);
                        1: odd origins (9 windows wholly contain a patch at w=8, s=2) */
+  int hist_bins;    /* 0: weights of Eq. 7; 2..256: histogram-weighted (Section 3, Eq. 9):
+                       W_q / (1 + sum_j max[0, H_x,j(b) - H_z,j(b)]) over the R, G, B
+                       histograms (fractions, hist_bins equal bins over [0, 1]) of the
+                       output as given and of the exemplar, b the bin of the centre pixel
+                       of matched exemplar window nn[q] (exact binning for powers of two) */
 } pts_mstep_params;
 
 /* With W_q = max(dist[q], delta)^(r-2) (Eq. 7), set for every pixel p of
@@ -234,6 +239,18 @@ typedef struct pts_mstep_params {
  * the E-step read.  No atomics: each patch is written by one thread. */
 int pts_mstep(pts_ctx* ctx, const int32_t* nn, const float* dist, float* x_rgbs, int H, int W,
               const pts_mstep_params* p);
+
+/* The blend weights the M-step uses (Eq. 7; with hist_bins, Eq. 9 for the
+ * output x_rgbs [H][W][4] as given): weights float32 [nq], device. */
+int pts_irls_weights(pts_ctx* ctx, const int32_t* nn, const float* dist, const float* x_rgbs, int H, int W,
+                     const pts_mstep_params* p, float* weights);
+
+/* Final histogram match (Section 4, step 4): each of R, G, B of x_rgbs
+ * [H][W][4] takes the context exemplar's distribution rank for rank - the
+ * pixels sorted by value (ties in pixel order), the i-th smallest of n takes
+ * the exemplar's sorted value of rank floor((i + 1/2) n_z / n).  Guidance
+ * untouched; in place. */
+int pts_histogram_match(pts_ctx* ctx, float* x_rgbs, int H, int W);
 
 /* Energy (Eqs. 4-5): E = sum_q rho(dist[q]) with rho(d) = d^r for
  * d >= delta and (1 - r/2) delta^r + (r/2) delta^(r-2) d^2 below (the
@@ -277,6 +294,8 @@ typedef struct pts_solve_params {
   int reuse_finest_index;         /* 1: use the context's current index (and MLP) at the finest
                                      level; that index must have been built from an exemplar
                                      whose guidance channel is the one the solve uses there */
+  int hist_bins;                  /* every blend histogram-weighted (Eq. 9) with this many bins; 0: off */
+  int final_hist_match;           /* 1: the result's histograms matched to the exemplar's at the end */
 } pts_solve_params;
 
 typedef struct pts_solve_trace {

@@ -8,7 +8,8 @@
 // so no two threads write the same pixel and no atomics are needed.
 //
 // The distance is floored at delta before the power (the weight is undefined
-// at zero distance), and the energy uses the matching smooth penalty
+// at zero distance); wscale (optional) multiplies each window's weight (the
+// histogram factor of Eq. 9).  The energy uses the matching smooth penalty
 //   rho(d) = d^r (d >= delta),  (1 - r/2) delta^r + (r/2) delta^(r-2) d^2 (d < delta).
 #include "kernels.hpp"
 #include "device_util.hpp"
@@ -24,7 +25,8 @@ __global__ __launch_bounds__(256) void k_mstep_patch2x2(const int32_t* __restric
                                                         const float* __restrict__ dist, float4* __restrict__ x,
                                                         int H, int W, int w, int s, const float4* __restrict__ ex,
                                                         const uint32_t* __restrict__ pk, int Hz, int Wz, float r,
-                                                        float delta, int o, int npx, int npy) {
+                                                        float delta, int o, int npx, int npy,
+                                                        const float* __restrict__ wscale) {
   const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= (int64_t)npx * npy) return;
   const int a = (int)(t % npx);
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(256) void k_mstep_patch2x2(const int32_t* __restric
       const int64_t q = (int64_t)i * cols + u / s;
       const int e = nn[q];
       if (e < 0 || e >= N) continue;
-      const float Wq = powf(fmaxf(dist[q], delta), r - 2.0f);
+      const float Wq = powf(fmaxf(dist[q], delta), r - 2.0f) * (wscale ? wscale[q] : 1.0f);
       const int ey = e / nu, exx = e - ey * nu;
       wsum += Wq;
 #pragma unroll
@@ -113,7 +115,8 @@ __global__ __launch_bounds__(256) void k_mstep_patch2x2(const int32_t* __restric
 }
 
 void launch_mstep(Ctx* c, const int32_t* nn, const float* dist, float* x, int H, int W, int w, int s,
-                  const float* ex, const uint32_t* ex_pk, int Hz, int Wz, float r, float delta, int o) {
+                  const float* ex, const uint32_t* ex_pk, int Hz, int Wz, float r, float delta, int o,
+                  const float* wscale) {
   ProfScope ps(c, "mstep_patch2x2");
   PTS_REQUIRE(o == 0 || o == 1, PTS_ERR_ARG, "patch_offset must be 0 or 1");
   const int npx = W / 2;
@@ -123,10 +126,10 @@ void launch_mstep(Ctx* c, const int32_t* nn, const float* dist, float* x, int H,
   const dim3 grid((unsigned)ceil_div(n, 256));
   if (ex_pk)
     hipLaunchKernelGGL(k_mstep_patch2x2<true>, grid, dim3(256), 0, c->stream, nn, dist, reinterpret_cast<float4*>(x),
-                       H, W, w, s, reinterpret_cast<const float4*>(ex), ex_pk, Hz, Wz, r, delta, o, npx, npy);
+                       H, W, w, s, reinterpret_cast<const float4*>(ex), ex_pk, Hz, Wz, r, delta, o, npx, npy, wscale);
   else
     hipLaunchKernelGGL(k_mstep_patch2x2<false>, grid, dim3(256), 0, c->stream, nn, dist, reinterpret_cast<float4*>(x),
-                       H, W, w, s, reinterpret_cast<const float4*>(ex), ex_pk, Hz, Wz, r, delta, o, npx, npy);
+                       H, W, w, s, reinterpret_cast<const float4*>(ex), ex_pk, Hz, Wz, r, delta, o, npx, npy, wscale);
   check_launch("k_mstep_patch2x2");
 }
 

@@ -35,10 +35,23 @@ void launch_exact_subset(Ctx* c, const float* x, int H, int W, int w, int s, con
 void launch_count_diff(Ctx* c, const int32_t* a, const int32_t* b, int64_t n, int32_t* count);
 void launch_zero_i32(Ctx* c, int32_t* p, int64_t n);
 
+// ---- histogram matching (k_hist.hip)
+// counts [3][bins] of the R, G, B channels of img [n][4] (2 <= bins <= 256)
+void launch_channel_hist(Ctx* c, const float* img, int64_t n, int bins, unsigned* counts);
+// Eq. 9 factors 1 / (1 + excess) of the matched windows nn [nq] for output x
+// and exemplar ex: both histograms and the factors (context scratch)
+const float* hist_weight_factors(Ctx* c, const int32_t* nn, int64_t nq, const float* x, int H, int W,
+                                 const float* ex, int Hz, int Wz, int w, int bins);
+// W = max(dist, delta)^(r-2) [* factor]
+void launch_irls_weights(Ctx* c, const float* dist, const float* factor, int64_t nq, float r, float delta, float* W);
+// the final match: x's R, G, B take the exemplar's distribution rank for rank
+void histogram_match(Ctx* c, float* x, int H, int W, const float* ex, int Hz, int Wz);
+
 // ---- blend and energy (k_mstep.hip)
 // ex_pk (optional): the exemplar's 8-bit form (Ctx::ex_pk), read instead of ex's RGB
 void launch_mstep(Ctx* c, const int32_t* nn, const float* dist, float* x, int H, int W, int w, int s,
-                  const float* ex, const uint32_t* ex_pk, int Hz, int Wz, float r, float delta, int o);
+                  const float* ex, const uint32_t* ex_pk, int Hz, int Wz, float r, float delta, int o,
+                  const float* wscale = nullptr);
 void launch_energy(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2);
 
 // ---- index (k_index.hip)

@@ -270,9 +270,43 @@ int pts_mstep(pts_ctx* c, const int32_t* nn, const float* dist, float* x, int H,
     validate_grid(H, W, p->w, p->stride);
     PTS_REQUIRE(p->w <= c->Hz && p->w <= c->Wz, PTS_ERR_ARG, "mstep: window larger than exemplar");
     PTS_REQUIRE(p->r > 0.f && p->r <= 2.f && p->delta > 0.f, PTS_ERR_ARG, "mstep: need 0 < r <= 2, delta > 0");
+    PTS_REQUIRE(p->hist_bins == 0 || (p->hist_bins >= 2 && p->hist_bins <= 256), PTS_ERR_ARG,
+                "mstep: hist_bins must be 0 or 2..256");
+    const float* factor =
+        p->hist_bins ? hist_weight_factors(c, nn, Grid{H, W, p->w, p->stride}.nq(), x, H, W, c->ex.as<float>(), c->Hz,
+                                           c->Wz, p->w, p->hist_bins)
+                     : nullptr;
     launch_mstep(c, nn, dist, x, H, W, p->w, p->stride, c->ex.as<float>(),
                  c->ex_packed ? c->ex_pk.as<uint32_t>() : nullptr, c->Hz, c->Wz, p->r, p->delta,
-                 p->patch_offset);
+                 p->patch_offset, factor);
+  });
+}
+
+int pts_irls_weights(pts_ctx* c, const int32_t* nn, const float* dist, const float* x, int H, int W,
+                     const pts_mstep_params* p, float* weights) {
+  CTX_REQUIRED(c);
+  return guard(c, [&] {
+    PTS_REQUIRE(p && nn && dist && x && weights, PTS_ERR_ARG, "irls_weights: null argument");
+    PTS_REQUIRE(c->Hz > 0, PTS_ERR_STATE, "irls_weights: no exemplar");
+    validate_grid(H, W, p->w, p->stride);
+    PTS_REQUIRE(p->w <= c->Hz && p->w <= c->Wz, PTS_ERR_ARG, "irls_weights: window larger than exemplar");
+    PTS_REQUIRE(p->r > 0.f && p->r <= 2.f && p->delta > 0.f, PTS_ERR_ARG, "irls_weights: need 0 < r <= 2, delta > 0");
+    PTS_REQUIRE(p->hist_bins == 0 || (p->hist_bins >= 2 && p->hist_bins <= 256), PTS_ERR_ARG,
+                "irls_weights: hist_bins must be 0 or 2..256");
+    const int64_t nq = Grid{H, W, p->w, p->stride}.nq();
+    const float* factor =
+        p->hist_bins ? hist_weight_factors(c, nn, nq, x, H, W, c->ex.as<float>(), c->Hz, c->Wz, p->w, p->hist_bins)
+                     : nullptr;
+    launch_irls_weights(c, dist, factor, nq, p->r, p->delta, weights);
+  });
+}
+
+int pts_histogram_match(pts_ctx* c, float* x, int H, int W) {
+  CTX_REQUIRED(c);
+  return guard(c, [&] {
+    PTS_REQUIRE(x && H > 0 && W > 0, PTS_ERR_ARG, "histogram_match: bad image");
+    PTS_REQUIRE(c->Hz > 0, PTS_ERR_STATE, "histogram_match: no exemplar");
+    histogram_match(c, x, H, W, c->ex.as<float>(), c->Hz, c->Wz);
   });
 }
 

@@ -49,6 +49,8 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
   PTS_REQUIRE(p.levels >= 1 && p.levels <= 8 && p.level, PTS_ERR_ARG, "solve: levels must be 1..8");
   const int L = p.levels;
   PTS_REQUIRE(H == (H0 << (L - 1)) && W == (W0 << (L - 1)), PTS_ERR_ARG, "solve: H, W must be H0, W0 << (levels-1)");
+  PTS_REQUIRE(p.hist_bins == 0 || (p.hist_bins >= 2 && p.hist_bins <= 256), PTS_ERR_ARG,
+              "solve: hist_bins must be 0 or 2..256");
   for (int l = 0; l < L; ++l) {
     const pts_level_params& lp = p.level[l];
     validate_grid(H0 << l, W0 << l, lp.w, lp.stride);
@@ -112,7 +114,10 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
       launch_energy(c, dist, nq, p.r, p.delta, eo);
       launch_zero_i32(c, dcount, 1);
       if (t > 0) launch_count_diff(c, nn_cur, nn_prev, nq, dcount);
-      launch_mstep(c, nn_cur, dist, cur, h, w, lp.w, lp.stride, zimg, nullptr, hz, wz, p.r, p.delta, p.patch_offset);
+      const float* factor =
+          p.hist_bins ? hist_weight_factors(c, nn_cur, nq, cur, h, w, zimg, hz, wz, lp.w, p.hist_bins) : nullptr;
+      launch_mstep(c, nn_cur, dist, cur, h, w, lp.w, lp.stride, zimg, nullptr, hz, wz, p.r, p.delta, p.patch_offset,
+                   factor);
       if (tr) {
         float eh[2];
         int32_t ch = 0;
@@ -140,6 +145,8 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
     }
   }
   PTS_HIP(hipMemcpyAsync(x, cur, (size_t)H * W * 16, hipMemcpyDeviceToDevice, c->stream));
+  // Section 4, step 4: the result's histograms matched to the exemplar's
+  if (p.final_hist_match) histogram_match(c, x, H, W, c->ex.as<float>(), c->Hz, c->Wz);
   PTS_HIP(hipStreamSynchronize(c->stream));
 }
 

@@ -168,6 +168,7 @@ class pts_mstep_params(C.Structure):
         ("r", C.c_float),
         ("delta", C.c_float),
         ("patch_offset", C.c_int),
+        ("hist_bins", C.c_int),
     ]
 
 
@@ -200,6 +201,8 @@ class pts_solve_params(C.Structure):
         ("seed", C.c_uint64),
         ("kmeans_max_iter", C.c_int),
         ("reuse_finest_index", C.c_int),
+        ("hist_bins", C.c_int),
+        ("final_hist_match", C.c_int),
     ]
 
 
@@ -257,6 +260,8 @@ SIGNATURES = {
     "pts_leaf_of": (_I, [_P, _P, _I64, _P]),
     "pts_descend": (_I, [_P, _P, _I64, _P]),
     "pts_mstep": (_I, [_P, _P, _P, _P, _I, _I, C.POINTER(pts_mstep_params)]),
+    "pts_irls_weights": (_I, [_P, _P, _P, _P, _I, _I, C.POINTER(pts_mstep_params), _P]),
+    "pts_histogram_match": (_I, [_P, _P, _I, _I]),
     "pts_energy": (_I, [_P, _P, _I64, _F, _F, C.POINTER(_D), C.POINTER(_D)]),
     "pts_energy_device": (_I, [_P, _P, _I64, _F, _F, _P]),
     "pts_solve": (_I, [_P, C.POINTER(pts_solve_params), _P, _I, _I, _P, _I, _I, C.POINTER(pts_solve_trace)]),
@@ -518,9 +523,19 @@ class Context:
         self._ok(lib().pts_descend(self._h, _ptr(qproj), qproj.shape[0], _ptr(out)))
         return out
 
-    def mstep(self, nn, dist, x, w, stride, r=0.8, delta=1e-3, patch_offset=0):
-        p = pts_mstep_params(w, stride, r, delta, patch_offset)
+    def mstep(self, nn, dist, x, w, stride, r=0.8, delta=1e-3, patch_offset=0, hist_bins=0):
+        p = pts_mstep_params(w, stride, r, delta, patch_offset, hist_bins)
         self._ok(lib().pts_mstep(self._h, _ptr(nn), _ptr(dist), _ptr(x), x.shape[0], x.shape[1], C.byref(p)))
+
+    def irls_weights(self, nn, dist, x, w, stride, r=0.8, delta=1e-3, hist_bins=0):
+        p = pts_mstep_params(w, stride, r, delta, 0, hist_bins)
+        out = self._f32(nn.numel())
+        self._ok(lib().pts_irls_weights(self._h, _ptr(nn), _ptr(dist), _ptr(x), x.shape[0], x.shape[1], C.byref(p),
+                                        _ptr(out)))
+        return out
+
+    def histogram_match(self, x):
+        self._ok(lib().pts_histogram_match(self._h, _ptr(x), x.shape[0], x.shape[1]))
 
     def energy(self, dist, r=0.8, delta=1e-3):
         E = C.c_double()
@@ -550,7 +565,7 @@ class Context:
 
     def solve(self, x0, levels, mode="tree", coarse_mode="tree", topk=8, rerank_full=0, n_proposals=4,
               margin=0.2, residual=0, r=0.8, delta=1e-3, patch_offset=0, guidance_weight=0.5, seed=0,
-              kmeans_max_iter=50, reuse_finest_index=False, trace=True):
+              kmeans_max_iter=50, reuse_finest_index=False, trace=True, hist_bins=0, final_hist_match=False):
         """levels: list of dicts with w, stride, iters, pca_dims, branching, depth (coarse to fine)."""
         L = len(levels)
         lv = (pts_level_params * L)(*[
@@ -559,7 +574,7 @@ class Context:
         p = pts_solve_params(L, lv, MODES[mode] if isinstance(mode, str) else mode,
                              MODES[coarse_mode] if isinstance(coarse_mode, str) else coarse_mode, topk, rerank_full,
                              n_proposals, margin, int(residual), r, delta, patch_offset, guidance_weight, seed,
-                             kmeans_max_iter, int(reuse_finest_index))
+                             kmeans_max_iter, int(reuse_finest_index), int(hist_bins), int(final_hist_match))
         H0, W0 = x0.shape[:2]
         H, W = H0 << (L - 1), W0 << (L - 1)
         out = self._f32((H, W, 4))

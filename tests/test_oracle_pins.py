@@ -7,7 +7,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import bf16, exact, irls, mlp, mstep, parity, pca, solve, tree, vectors
+from oracle import bf16, exact, histogram, irls, mlp, mstep, parity, pca, solve, tree, vectors
 from paper_2006_11851_amd import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -628,3 +628,79 @@ def test_fp32_score_tolerance_covers_float32_evaluation():
             acc = (acc + np.float32(-2.0) * qb[k].astype(np.float32) * Zb[:, k].astype(np.float32)).astype(np.float32)
         tol = bf16.fp32_score_tolerance(q, Zp, 64)
         assert np.abs(acc.astype(np.float64) - exact_s).max() <= tol / 2
+
+
+# ---------------------------------------------------------------- histograms (Eq. 9, Section 4 step 4)
+
+def test_histogram_weights_unchanged_when_histograms_agree():
+    r = np.random.default_rng(30)
+    Z = r.uniform(0, 1, size=(20, 24, 4))
+    nn = r.integers(0, (20 - 4 + 1) * (24 - 4 + 1), 50)
+    W = r.uniform(0.5, 3.0, 50)
+    # the output is the exemplar itself (a permutation of it has the same histograms too)
+    X = Z[:, ::-1].copy()
+    assert np.allclose(histogram.weights(W, X, Z, nn, 4, 16), W, rtol=0, atol=0)
+
+
+def test_histogram_weights_hand_computed():
+    # 2 bins per channel.  Output R values 0.1, 0.2, 0.3, 0.9: fractions (0.75, 0.25);
+    # exemplar R values 0.1, 0.6, 0.7, 0.8: (0.25, 0.75).  G and B sit in bin 1 on
+    # both sides.  A window whose colour has R in bin 0 carries the excess
+    # 0.75 - 0.25 = 0.5 (weight / 1.5); R in bin 1: no excess (weight kept).
+    X = np.zeros((2, 2, 4))
+    X[..., 0] = [[0.1, 0.2], [0.3, 0.9]]
+    X[..., 1:3] = 0.7
+    Z = np.zeros((2, 2, 4))
+    Z[..., 0] = [[0.1, 0.6], [0.7, 0.8]]
+    Z[..., 1:3] = 0.9
+    Hx, Hz = histogram.channel_histograms(X, 2), histogram.channel_histograms(Z, 2)
+    assert np.allclose(Hx[0], [0.75, 0.25]) and np.allclose(Hz[0], [0.25, 0.75])
+    exc = histogram.excess(np.array([[0.1, 0.7, 0.7], [0.6, 0.7, 0.7], [0.49, 0.51, 0.99]]), Hx, Hz, 2)
+    assert np.allclose(exc, [0.5, 0.0, 0.5])
+    # through the window colours: w = 2 windows of a 3x3 exemplar, centre = pixel (1, 1) of the window
+    Z3 = np.zeros((3, 3, 4))
+    Z3[..., 0] = [[0.9, 0.9, 0.9], [0.9, 0.1, 0.9], [0.9, 0.9, 0.6]]
+    Z3[..., 1:3] = 0.9
+    cols = histogram.window_colours(Z3, np.array([0, 1]), 2)  # windows with corners (0,0) and (1,0)
+    assert np.allclose(cols[:, 0], [0.1, 0.9])
+    Hz3 = histogram.channel_histograms(Z3, 2)
+    X3 = np.zeros((3, 3, 4))
+    X3[..., 0] = 0.1  # every output pixel in R bin 0
+    X3[..., 1:3] = 0.9
+    W = histogram.weights(np.array([2.0, 2.0]), X3, Z3, np.array([0, 1]), 2, 2)
+    # R bin 0: output fraction 1, exemplar 1/9 -> excess 8/9; bin 1: no excess
+    assert np.allclose(W, [2.0 / (1 + 8.0 / 9.0), 2.0])
+
+
+def test_histogram_match_maps_a_ramp_onto_the_exemplar_distribution():
+    r = np.random.default_rng(31)
+    Z = r.uniform(0, 1, size=(16, 16, 4))
+    X = np.zeros((16, 16, 4))
+    ramp = np.linspace(0, 1, 256).reshape(16, 16)
+    for j in range(3):
+        X[..., j] = ramp
+    X[..., 3] = 0.25
+    Y = histogram.match(X, Z)
+    for j in range(3):
+        # same number of pixels: the ramp's i-th value takes the exemplar's i-th smallest
+        assert np.array_equal(Y[..., j].reshape(-1), np.sort(Z[..., j].reshape(-1)))
+    assert np.array_equal(Y[..., 3], X[..., 3])
+    # a larger output: every value comes from the exemplar, order kept, quantiles matched
+    Xb = r.uniform(0, 1, size=(32, 32, 4))
+    Yb = histogram.match(Xb, Z)
+    for j in range(3):
+        assert np.isin(Yb[..., j], Z[..., j]).all()
+        o = np.argsort(Xb[..., j].reshape(-1), kind="stable")
+        assert np.all(np.diff(Yb[..., j].reshape(-1)[o]) >= 0)
+        assert np.allclose(np.sort(Yb[..., j].reshape(-1))[::4], np.sort(Z[..., j].reshape(-1)))
+    # idempotent
+    assert np.array_equal(histogram.match(Yb, Z), Yb)
+
+
+def test_histogram_match_ties_follow_pixel_order():
+    Z = np.zeros((1, 4, 4))
+    Z[0, :, 0] = [0.4, 0.1, 0.3, 0.2]
+    X = np.zeros((1, 4, 4))
+    X[0, :, 0] = [0.5, 0.5, 0.0, 0.5]  # three equal values
+    Y = histogram.match(X, Z)
+    assert list(Y[0, :, 0]) == [0.2, 0.3, 0.1, 0.4]
