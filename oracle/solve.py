@@ -19,7 +19,11 @@ Readings where the paper is silent:
   R, G, B; the guidance channel is recomputed for each level's size;
 * upsampling: bilinear on R, G, B at coarse position
   ((x + 0.5) / 2 - 0.5, (y + 0.5) / 2 - 0.5), wrapping in x and clamping in
-  y; the guidance channel is recomputed at the finer size.
+  y; the guidance channel is recomputed at the finer size;
+* with a perspective scale map (slant, tilt; Methodology 1) in place of the
+  row guidance, each exemplar level's guidance is the normalised map of its
+  own size and each output level's the resample of its exemplar level's
+  map (Section 4, steps 1-2).
 """
 from __future__ import annotations
 
@@ -27,7 +31,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import exact, irls, mstep as mstep_mod, pca as pca_mod, tree as tree_mod
+from . import exact, irls, mstep as mstep_mod, pca as pca_mod, scale as scale_mod, tree as tree_mod
 from .vectors import exemplar_matrix, query_matrix, rgbs
 
 _BLUR = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0
@@ -46,13 +50,20 @@ def blur_decimate(rgb: np.ndarray) -> np.ndarray:
     return t[0::2, 0::2]
 
 
-def exemplar_pyramid(Z: np.ndarray, levels: int, weight: float = 0.5):
+def _level_guidance(h: int, w: int, weight: float, scale):
+    if scale is None:
+        return guidance(h, w, weight)
+    return scale_mod.guidance(scale[0], scale[1], h, w, weight)
+
+
+def exemplar_pyramid(Z: np.ndarray, levels: int, weight: float = 0.5, scale=None):
     """Coarse-to-fine list of RGBS exemplars; the last is Z itself.  A
     negative weight keeps Z's own guidance channel (a scale map) and blurs
-    it like the colours; otherwise each level's guidance is recomputed."""
+    it like the colours; otherwise each level's guidance is recomputed (the
+    row guidance, or with scale = (slant, tilt) the level's scale map)."""
     out = [np.array(Z, dtype=np.float64)]
     if weight >= 0:
-        out[0][..., 3] = guidance(Z.shape[0], Z.shape[1], weight)
+        out[0][..., 3] = _level_guidance(Z.shape[0], Z.shape[1], weight, scale)
     for _ in range(levels - 1):
         if weight < 0:
             out.insert(0, blur_decimate(out[0]))
@@ -60,12 +71,14 @@ def exemplar_pyramid(Z: np.ndarray, levels: int, weight: float = 0.5):
         rgb = blur_decimate(out[0][..., :3])
         img = np.empty(rgb.shape[:2] + (4,))
         img[..., :3] = rgb
-        img[..., 3] = guidance(rgb.shape[0], rgb.shape[1], weight)
+        img[..., 3] = _level_guidance(rgb.shape[0], rgb.shape[1], weight, scale)
         out.insert(0, img)
     return out
 
 
-def upsample2(X: np.ndarray, weight: float = 0.5) -> np.ndarray:
+def upsample2(X: np.ndarray, weight: float = 0.5, scale=None, ref=None) -> np.ndarray:
+    """2x bilinear upsampling; with scale = (slant, tilt) the new guidance is
+    the map of an exemplar of size ref = (h, w) resampled to the new size."""
     Hc, Wc = X.shape[:2]
     H, W = 2 * Hc, 2 * Wc
     yc = (np.arange(H) + 0.5) / 2.0 - 0.5
@@ -82,7 +95,10 @@ def upsample2(X: np.ndarray, weight: float = 0.5) -> np.ndarray:
     out = np.empty((H, W, 4))
     out[..., : ch.shape[2]] = (1 - fy) * top + fy * bot
     if weight >= 0:
-        out[..., 3] = guidance(H, W, weight)
+        if scale is None:
+            out[..., 3] = guidance(H, W, weight)
+        else:
+            out[..., 3] = scale_mod.output_guidance(scale[0], scale[1], ref[0], ref[1], H, W, weight)
     return out
 
 
@@ -163,10 +179,11 @@ def iterate(X, Z, w, s, T, mode="exact", index=None, r=irls.R_DEFAULT, delta=irl
 
 
 def multiscale(Z_fine, X0, ws, ss, Ts, mode="exact", pca_dims=0, branching=4, depth=0, seed=0,
-               r=irls.R_DEFAULT, delta=irls.DELTA_DEFAULT, patch_offset=0, weight=0.5):
-    """Coarse-to-fine solve; X0 is the RGBS initial output at the coarsest level."""
+               r=irls.R_DEFAULT, delta=irls.DELTA_DEFAULT, patch_offset=0, weight=0.5, scale=None):
+    """Coarse-to-fine solve; X0 is the RGBS initial output at the coarsest
+    level; scale = (slant, tilt) selects the scale-map guidance."""
     L = len(ws)
-    pyr = exemplar_pyramid(Z_fine, L, weight)
+    pyr = exemplar_pyramid(Z_fine, L, weight, scale)
     X = np.array(X0, dtype=np.float64, copy=True)
     trace = Trace()
     for l in range(L):
@@ -175,7 +192,7 @@ def multiscale(Z_fine, X0, ws, ss, Ts, mode="exact", pca_dims=0, branching=4, de
             idx = build_index(pyr[l], ws[l], pca_dims, branching, depth if mode == "tree" else 0, seed)
         X = iterate(X, pyr[l], ws[l], ss[l], Ts[l], mode, idx, r, delta, patch_offset, trace, l)
         if l + 1 < L:
-            X = upsample2(X, weight)
+            X = upsample2(X, weight, scale, pyr[l + 1].shape[:2])
     return X, trace
 
 
