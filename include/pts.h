@@ -101,6 +101,39 @@ int pts_fill_guidance(pts_ctx* ctx, float* x_rgbs, int H, int W, float guidance_
  * S as in pts_fill_guidance). */
 int pts_rgbs_from_u8(pts_ctx* ctx, const uint8_t* rgb_host, int H, int W, float guidance_weight, float* x_rgbs);
 
+/* ---- perspective scale map (Methodology 1, Eqs. 1-3; Section 4 steps 1-3) */
+
+/* Fill the guidance channel of a device image x_rgbs [H][W][4] with the
+ * scale map of a locally planar texture seen under slant `slant` and tilt
+ * `tilt` (radians; slant in [0, pi/2), tilt in [0, pi/2]), computed for an
+ * image of ref_h x ref_w pixels (>= 3 each) with its origin at the
+ * bottom-left corner (Eqs. 1-3, the leading term of Eq. 3 read as S_max),
+ * then resampled bilinearly to H x W (pixel centres aligned, edge
+ * coordinates clamped).  The channel holds weight * (S - S_min) / S_D, the
+ * map normalised to [0, 1] (zero when slant = 0 makes it flat).  ref = (H,
+ * W) gives an image its own map (an exemplar), ref = the exemplar's size
+ * the output's map (step 2).  R, G, B are untouched.  Out-of-range angles or
+ * sizes: PTS_ERR_ARG, nothing written. */
+int pts_scale_guidance(pts_ctx* ctx, float* x_rgbs, int H, int W, int ref_h, int ref_w, double slant, double tilt,
+                       float weight);
+/* Section 4 step 3, the scale-matched initial output: every tile x tile
+ * block of x_rgbs [H][W][4] (row-major tiles, ragged last row and column
+ * taking the window's top-left part) copies R, G, B of the exemplar window
+ * (corner (u, v), tile x tile pixels) of ex_rgbs [Hz][Wz][4] (device, the
+ * exemplar at the output's scale, e.g. the coarsest pyramid level) whose
+ * centre (u + tile/2, v + tile/2) has the scale of the block's centre
+ * pixel: equal scale is equal projected coordinate p(Y), a line through
+ * the exemplar point the block's centre samples.  rnd (device uint32
+ * [tiles][2]) holds the caller's uniform draws: the column rnd[k][0] mod
+ * (Wz - tile + 1) when cos(tilt) >= sin(tilt), else the row rnd[k][1] mod
+ * (Hz - tile + 1), the other coordinate being the nearest to the line
+ * (rounded half up, clamped into the exemplar); with slant = 0 (a flat map)
+ * both are drawn.  The guidance channel is that of pts_scale_guidance with
+ * ref = (Hz, Wz).  tile in 1..min(Hz, Wz); the exemplar's own guidance is
+ * not read. */
+int pts_scale_init(pts_ctx* ctx, const float* ex_rgbs, int Hz, int Wz, float* x_rgbs, int H, int W, int tile,
+                   const uint32_t* rnd, double slant, double tilt, float weight);
+
 /* ---- index: PCA basis + k-means tree (Methodology 2.2) ----------------- */
 
 typedef struct pts_index_params {
@@ -296,6 +329,11 @@ typedef struct pts_solve_params {
                                      whose guidance channel is the one the solve uses there */
   int hist_bins;                  /* every blend histogram-weighted (Eq. 9) with this many bins; 0: off */
   int final_hist_match;           /* 1: the result's histograms matched to the exemplar's at the end */
+  int scale_map;                  /* 1: the guidance of every level is the perspective scale map
+                                     (pts_scale_guidance) of slant and tilt instead of the row
+                                     guidance: each exemplar level its own, each upsampled output
+                                     the resample of its exemplar level's; guidance_weight >= 0 */
+  double slant, tilt;             /* radians, used when scale_map = 1 */
 } pts_solve_params;
 
 typedef struct pts_solve_trace {

@@ -55,7 +55,8 @@ void descend_unpadded(Ctx* c, const float* qproj, int64_t n, int32_t* leaf);
 BucketBufs bucket_buffers(Ctx* c, int64_t n, int n_leaves, int chunk, int* max_tiles, const char* tag = "bk");
 
 // solve.cpp
-const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int* w);
+const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int* w,
+                           const ScaleSpec& scale = ScaleSpec());
 void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W0, float* x, int H, int W,
                pts_solve_trace* tr);
 

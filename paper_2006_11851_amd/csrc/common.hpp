@@ -113,6 +113,15 @@ struct ProfEntry {
   int64_t launches = 0;
 };
 
+// the guidance a solve writes at every level: the row guidance, or (on) the
+// perspective scale map of a slant and a tilt (radians)
+struct ScaleSpec {
+  bool on = false;
+  double slant = 0.0, tilt = 0.0;
+  bool operator==(const ScaleSpec& o) const { return on == o.on && slant == o.slant && tilt == o.tilt; }
+  bool operator!=(const ScaleSpec& o) const { return !(*this == o); }
+};
+
 struct Ctx {
   int device = 0;
   int n_cu = 256;  // compute units of the device
@@ -143,6 +152,7 @@ struct Ctx {
   uint64_t pyr_version = ~0ull;
   int pyr_levels = 0;
   float pyr_gw = -1.f;
+  ScaleSpec pyr_scale;
   std::vector<std::unique_ptr<DevMem>> pyr_img;
   std::vector<int> pyr_h, pyr_w;
 

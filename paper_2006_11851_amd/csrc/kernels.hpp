@@ -16,6 +16,21 @@ void launch_fill_guidance(Ctx* c, float* x, int H, int W, float gw);
 void launch_blur_decimate(Ctx* c, const float* in, int H, int W, float gw, float* out);
 void launch_upsample2(Ctx* c, const float* in, int H, int W, float gw, float* out);
 
+// ---- perspective scale map (k_scale.hip)
+// Eqs. 1-2 of an exemplar of ref_h x ref_w pixels under a slant and a tilt
+// (radians), evaluated on the host; scale_geom validates the ranges.
+struct ScaleGeom {
+  double smax, smin, sd, ymax, sin_t, cos_t;
+  int ref_h, ref_w;
+};
+ScaleGeom scale_geom(double slant, double tilt, int ref_h, int ref_w);
+// channel 3 of x [H][W][4] = gw * the normalised map resampled to H x W
+void launch_scale_guidance(Ctx* c, float* x, int H, int W, const ScaleGeom& g, float gw);
+// x [H][W][4]: t x t tiles copied from the scale-matched windows of ex
+// [Hz][Wz][4] (the map's size), rnd [tiles][2] uniform uint32 draws
+void launch_scale_init(Ctx* c, const float* ex, int Hz, int Wz, float* x, int H, int W, int t, const uint32_t* rnd,
+                       const ScaleGeom& g, float gw);
+
 // ---- windows and exhaustive search (k_search.hip)
 // Materialise windows as rows of float32 [n][D]: output grid (stride s, x
 // wrap) when wrap, else the exemplar grid (all corners at stride s).

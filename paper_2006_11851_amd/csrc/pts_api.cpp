@@ -150,6 +150,26 @@ int pts_fill_guidance(pts_ctx* c, float* x, int H, int W, float gw) {
   });
 }
 
+int pts_scale_guidance(pts_ctx* c, float* x, int H, int W, int ref_h, int ref_w, double slant, double tilt,
+                       float weight) {
+  CTX_REQUIRED(c);
+  return guard(c, [&] {
+    PTS_REQUIRE(x && H > 0 && W > 0, PTS_ERR_ARG, "scale_guidance: bad image");
+    PTS_REQUIRE(std::isfinite(weight), PTS_ERR_ARG, "scale_guidance: weight must be finite");
+    launch_scale_guidance(c, x, H, W, scale_geom(slant, tilt, ref_h, ref_w), weight);
+  });
+}
+
+int pts_scale_init(pts_ctx* c, const float* ex, int Hz, int Wz, float* x, int H, int W, int tile,
+                   const uint32_t* rnd, double slant, double tilt, float weight) {
+  CTX_REQUIRED(c);
+  return guard(c, [&] {
+    PTS_REQUIRE(ex && x && rnd && H > 0 && W > 0, PTS_ERR_ARG, "scale_init: bad image");
+    PTS_REQUIRE(std::isfinite(weight), PTS_ERR_ARG, "scale_init: weight must be finite");
+    launch_scale_init(c, ex, Hz, Wz, x, H, W, tile, rnd, scale_geom(slant, tilt, Hz, Wz), weight);
+  });
+}
+
 int pts_rgbs_from_u8(pts_ctx* c, const uint8_t* rgb_host, int H, int W, float gw, float* x) {
   CTX_REQUIRED(c);
   return guard(c, [&] {

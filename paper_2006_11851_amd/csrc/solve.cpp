@@ -10,8 +10,17 @@
 
 namespace pts {
 
-const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int* w) {
-  if (c->pyr_version != c->ex_version || c->pyr_levels != levels || c->pyr_gw != gw) {
+// writes level l's guidance (gw >= 0): the row guidance, or the scale map
+static void level_guidance(Ctx* c, float* img, int h, int w, float gw, const ScaleSpec& sc) {
+  if (sc.on)
+    launch_scale_guidance(c, img, h, w, scale_geom(sc.slant, sc.tilt, h, w), gw);
+  else
+    launch_fill_guidance(c, img, h, w, gw);
+}
+
+const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int* w, const ScaleSpec& scale) {
+  if (c->pyr_version != c->ex_version || c->pyr_levels != levels || c->pyr_gw != gw || c->pyr_scale != scale) {
+    c->pyr_version = ~0ull;  // invalid until complete
     PTS_REQUIRE((c->Hz >> (levels - 1)) >= 4 && (c->Wz >> (levels - 1)) >= 4, PTS_ERR_ARG,
                 "pyramid: exemplar too small for that many levels");
     PTS_REQUIRE(levels == 1 || ((c->Hz % (1 << (levels - 1))) == 0 && (c->Wz % (1 << (levels - 1))) == 0),
@@ -27,16 +36,18 @@ const float* pyramid_level(Ctx* c, int levels, int level, float gw, int* h, int*
     c->pyr_w[L] = c->Wz;
     float* fin = static_cast<float*>(c->pyr_img[L]->ensure(c, (size_t)c->Hz * c->Wz * 16));
     PTS_HIP(hipMemcpyAsync(fin, c->ex.ptr, (size_t)c->Hz * c->Wz * 16, hipMemcpyDeviceToDevice, c->stream));
-    if (gw >= 0.f) launch_fill_guidance(c, fin, c->Hz, c->Wz, gw);
+    if (gw >= 0.f) level_guidance(c, fin, c->Hz, c->Wz, gw, scale);
     for (int l = L - 1; l >= 0; --l) {
       c->pyr_h[l] = c->pyr_h[l + 1] / 2;
       c->pyr_w[l] = c->pyr_w[l + 1] / 2;
       float* dst = static_cast<float*>(c->pyr_img[l]->ensure(c, (size_t)c->pyr_h[l] * c->pyr_w[l] * 16));
       launch_blur_decimate(c, c->pyr_img[l + 1]->as<float>(), c->pyr_h[l + 1], c->pyr_w[l + 1], gw, dst);
+      if (gw >= 0.f && scale.on) level_guidance(c, dst, c->pyr_h[l], c->pyr_w[l], gw, scale);
     }
     c->pyr_version = c->ex_version;
     c->pyr_levels = levels;
     c->pyr_gw = gw;
+    c->pyr_scale = scale;
   }
   *h = c->pyr_h[level];
   *w = c->pyr_w[level];
@@ -58,6 +69,15 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
   }
   if (tr) tr->count = 0;
   const float gw = p.guidance_weight;
+  ScaleSpec scale;
+  if (p.scale_map) {
+    PTS_REQUIRE(gw >= 0.f, PTS_ERR_ARG, "solve: the scale map needs guidance_weight >= 0");
+    scale.on = true;
+    scale.slant = p.slant;
+    scale.tilt = p.tilt;
+    // checks the angles and every level's size before any work
+    for (int l = 0; l < L; ++l) scale_geom(scale.slant, scale.tilt, c->Hz >> (L - 1 - l), c->Wz >> (L - 1 - l));
+  }
   // working image of the current level (two buffers for the upsampling)
   DevMem buf_a, buf_b;
   float* cur = static_cast<float*>(buf_a.ensure(c, (size_t)H0 * W0 * 16));
@@ -68,7 +88,7 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
     const pts_level_params& lp = p.level[l];
     const int h = H0 << l, w = W0 << l;
     int hz = 0, wz = 0;
-    const float* zimg = pyramid_level(c, L, l, gw, &hz, &wz);
+    const float* zimg = pyramid_level(c, L, l, gw, &hz, &wz, scale);
     ExView ex{zimg, hz, wz};
     const bool finest = (l == L - 1);
     const int mode = finest ? p.mode : p.coarse_mode;
@@ -141,6 +161,9 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
     if (!finest) {
       float* nxt = static_cast<float*>((l % 2 == 0 ? buf_b : buf_a).ensure(c, (size_t)(2 * h) * (2 * w) * 16));
       launch_upsample2(c, cur, h, w, gw, nxt);
+      if (scale.on)  // the next exemplar level's map resampled to the output
+        launch_scale_guidance(c, nxt, 2 * h, 2 * w,
+                              scale_geom(scale.slant, scale.tilt, c->Hz >> (L - 2 - l), c->Wz >> (L - 2 - l)), gw);
       cur = nxt;
     }
   }

@@ -203,6 +203,9 @@ class pts_solve_params(C.Structure):
         ("reuse_finest_index", C.c_int),
         ("hist_bins", C.c_int),
         ("final_hist_match", C.c_int),
+        ("scale_map", C.c_int),
+        ("slant", C.c_double),
+        ("tilt", C.c_double),
     ]
 
 
@@ -262,6 +265,8 @@ SIGNATURES = {
     "pts_mstep": (_I, [_P, _P, _P, _P, _I, _I, C.POINTER(pts_mstep_params)]),
     "pts_irls_weights": (_I, [_P, _P, _P, _P, _I, _I, C.POINTER(pts_mstep_params), _P]),
     "pts_histogram_match": (_I, [_P, _P, _I, _I]),
+    "pts_scale_guidance": (_I, [_P, _P, _I, _I, _I, _I, _D, _D, _F]),
+    "pts_scale_init": (_I, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _D, _D, _F]),
     "pts_energy": (_I, [_P, _P, _I64, _F, _F, C.POINTER(_D), C.POINTER(_D)]),
     "pts_energy_device": (_I, [_P, _P, _I64, _F, _F, _P]),
     "pts_solve": (_I, [_P, C.POINTER(pts_solve_params), _P, _I, _I, _P, _I, _I, C.POINTER(pts_solve_trace)]),
@@ -537,6 +542,28 @@ class Context:
     def histogram_match(self, x):
         self._ok(lib().pts_histogram_match(self._h, _ptr(x), x.shape[0], x.shape[1]))
 
+    # -- perspective scale map
+    def scale_guidance(self, x, slant, tilt, weight=0.5, ref=None):
+        """x's guidance channel = weight * the normalised scale map of an
+        image of size ref (default: x's own) resampled to x's size."""
+        H, W = x.shape[:2]
+        rh, rw = (H, W) if ref is None else ref
+        self._ok(lib().pts_scale_guidance(self._h, _ptr(x), H, W, rh, rw, float(slant), float(tilt), weight))
+        return x
+
+    def scale_init(self, ex_rgbs, H, W, tile, rnd, slant, tilt, weight=0.5):
+        """Scale-matched initial output [H][W][4] from the device exemplar
+        ex_rgbs; rnd: device uint32 draws [tiles][2] (int32 storage)."""
+        torch = self.torch
+        Hz, Wz = ex_rgbs.shape[:2]
+        nt = (-(-H // tile)) * (-(-W // tile))
+        if rnd.numel() != 2 * nt or rnd.dtype not in (torch.int32, torch.uint32) or not rnd.is_contiguous():
+            raise ValueError(f"rnd must hold {nt} x 2 contiguous 32-bit integers")
+        out = self._f32((H, W, 4))
+        self._ok(lib().pts_scale_init(self._h, _ptr(ex_rgbs), Hz, Wz, _ptr(out), H, W, tile, _ptr(rnd),
+                                      float(slant), float(tilt), weight))
+        return out
+
     def energy(self, dist, r=0.8, delta=1e-3):
         E = C.c_double()
         E2 = C.c_double()
@@ -565,8 +592,10 @@ class Context:
 
     def solve(self, x0, levels, mode="tree", coarse_mode="tree", topk=8, rerank_full=0, n_proposals=4,
               margin=0.2, residual=0, r=0.8, delta=1e-3, patch_offset=0, guidance_weight=0.5, seed=0,
-              kmeans_max_iter=50, reuse_finest_index=False, trace=True, hist_bins=0, final_hist_match=False):
-        """levels: list of dicts with w, stride, iters, pca_dims, branching, depth (coarse to fine)."""
+              kmeans_max_iter=50, reuse_finest_index=False, trace=True, hist_bins=0, final_hist_match=False,
+              scale=None):
+        """levels: list of dicts with w, stride, iters, pca_dims, branching, depth (coarse to fine);
+        scale = (slant, tilt) in radians selects the scale-map guidance."""
         L = len(levels)
         lv = (pts_level_params * L)(*[
             pts_level_params(l["w"], l["stride"], l["iters"], l.get("pca_dims", 0), l.get("branching", 4),
@@ -574,7 +603,8 @@ class Context:
         p = pts_solve_params(L, lv, MODES[mode] if isinstance(mode, str) else mode,
                              MODES[coarse_mode] if isinstance(coarse_mode, str) else coarse_mode, topk, rerank_full,
                              n_proposals, margin, int(residual), r, delta, patch_offset, guidance_weight, seed,
-                             kmeans_max_iter, int(reuse_finest_index), int(hist_bins), int(final_hist_match))
+                             kmeans_max_iter, int(reuse_finest_index), int(hist_bins), int(final_hist_match),
+                             int(scale is not None), *(map(float, scale) if scale is not None else (0.0, 0.0)))
         H0, W0 = x0.shape[:2]
         H, W = H0 << (L - 1), W0 << (L - 1)
         out = self._f32((H, W, 4))

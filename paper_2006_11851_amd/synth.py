@@ -35,6 +35,7 @@ import numpy as np
 __all__ = [
     "perspective_exemplar",
     "row_matched_init",
+    "tile_draws",
     "Workload",
     "WORKLOADS",
     "workload",
@@ -123,6 +124,14 @@ def row_matched_init(seed: int, ex: np.ndarray, H: int, W: int, w: int):
             ww = min(w, W - tj * w)
             out[ti * w : ti * w + h, tj * w : tj * w + ww] = ex[v : v + h, u : u + ww]
     return out, corners
+
+
+def tile_draws(seed: int, H: int, W: int, t: int) -> np.ndarray:
+    """Uniform 32-bit integers [tiles][2] for the t x t tiles of an H x W
+    output (row-major tiles): the draws a scale-matched initialisation
+    consumes, one pair per tile."""
+    n = (-(-H // t)) * (-(-W // t))
+    return np.random.default_rng(seed).integers(0, 2**32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
 
 
 @dataclass(frozen=True)

@@ -166,9 +166,8 @@ def test_flat_map_draws_both_coordinates_and_init_copies_windows():
 
 def test_solve_with_the_scale_map_wires_each_level():
     """Every exemplar level carries its own size's map; every upsampled
-    output the resample of the next exemplar level's map; at tau = 0 the
-    solve's matches equal those of the row guidance scaled to the same
-    slope (both channels are affine images of each other)."""
+    output the resample of the next exemplar level's map; the colours are
+    upsampled as without it."""
     s, t = math.radians(30), math.radians(18)
     rng = np.random.default_rng(1)
     Z = rng.random((32, 32, 4))
