@@ -299,6 +299,20 @@ int pts_energy(pts_ctx* ctx, const float* dist, int64_t nq, float r, float delta
  * returns without waiting, so iterations that only record their energy
  * need no host round trip.  nq == 0 writes zeros. */
 int pts_energy_device(pts_ctx* ctx, const float* dist, int64_t nq, float r, float delta, float* out_device);
+/* pts_energy_device for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or other allocating routine.
+ * Same kernels, launch shape and results (bitwise) as pts_energy_device.
+ * Its per-block partial sums live in a fixed library array of 2 x 1024
+ * floats (8 KiB) per device, located when the first context is created on
+ * that device and held until the process ends; every nq >= 0 fits (at most
+ * 1024 blocks, each striding over the distances), so no size is refused.
+ * Every call on a device shares that array and the next call overwrites it:
+ * calls that overlap on one device (other streams, other contexts, other
+ * threads) race and must be ordered by the caller.  The library's own
+ * profiler does not record this call.  Errors as pts_energy_device. */
+int pts_energy_device_noalloc(pts_ctx* ctx, const float* dist, int64_t nq, float r, float delta,
+                              float* out_device);
 
 /* ---- multiscale solve (Methodology 2.1: coarse-to-fine) ---------------- */
 

@@ -125,6 +125,7 @@ struct ScaleSpec {
 struct Ctx {
   int device = 0;
   int n_cu = 256;  // compute units of the device
+  float* energy_scratch = nullptr;  // the device's fixed energy scratch (set at creation)
   hipStream_t stream = nullptr;
   pts_alloc alloc{};
   bool has_alloc = false;

@@ -11,6 +11,9 @@
 // at zero distance); wscale (optional) multiplies each window's weight (the
 // histogram factor of Eq. 9).  The energy uses the matching smooth penalty
 //   rho(d) = d^r (d >= delta),  (1 - r/2) delta^r + (r/2) delta^(r-2) d^2 (d < delta).
+#include <map>
+#include <mutex>
+
 #include "kernels.hpp"
 #include "device_util.hpp"
 
@@ -192,10 +195,33 @@ __global__ __launch_bounds__(256) void k_energy_final(const float* __restrict__ 
   }
 }
 
-void launch_energy(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2) {
-  ProfScope ps(c, "energy");
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(n, 256)));
-  float* part = c->buf<float>("energy_part", 2 * (size_t)nb);
+// The energy entry point that allocates nothing keeps its per-block
+// partial sums (E, E2) in this array: one copy per device, at its own
+// address, held until the process ends.  In host code the name is a
+// host-side stand-in, never the device address: kernels get the pointer
+// that energy_scratch_init returned for the device.
+constexpr int ENERGY_MAX_BLOCKS = 1024;
+static __device__ __align__(256) float scratch[2 * ENERGY_MAX_BLOCKS];
+
+float* energy_scratch_init(int device) {
+  static std::mutex mu;
+  static std::map<int, float*> ptrs;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = ptrs.find(device);
+  if (it != ptrs.end()) return it->second;
+  int cur = -1;
+  PTS_HIP(hipGetDevice(&cur));
+  PTS_REQUIRE(cur == device, PTS_ERR_STATE, "energy scratch: the device must be current");
+  void* p = nullptr;
+  PTS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  PTS_REQUIRE(p != nullptr, PTS_ERR_HIP, "energy scratch: no device address");
+  ptrs[device] = static_cast<float*>(p);
+  return static_cast<float*>(p);
+}
+
+// part: 2 x (at most ENERGY_MAX_BLOCKS) floats, each written before it is read
+static void energy_into(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2, float* part,
+                        int nb) {
   const double dr = r, dd = delta;
   const float c0 = (float)((1.0 - dr / 2.0) * std::pow(dd, dr));
   const float c1 = (float)((dr / 2.0) * std::pow(dd, dr - 2.0));
@@ -203,6 +229,23 @@ void launch_energy(Ctx* c, const float* dist, int64_t n, float r, float delta, f
   check_launch("k_energy_partial");
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, c->stream, part, nb, out2);
   check_launch("k_energy_final");
+}
+
+static int energy_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ENERGY_MAX_BLOCKS, ceil_div(n, 256)));
+}
+
+void launch_energy(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2) {
+  ProfScope ps(c, "energy");
+  const int nb = energy_blocks(n);
+  energy_into(c, dist, n, r, delta, out2, c->buf<float>("energy_part", 2 * (size_t)nb), nb);
+}
+
+void launch_energy_scratch(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2,
+                           float* scratch_ptr) {
+  // no profiling scope: its events would be created here
+  PTS_REQUIRE(scratch_ptr != nullptr, PTS_ERR_STATE, "energy scratch: not set up on this device");
+  energy_into(c, dist, n, r, delta, out2, scratch_ptr, energy_blocks(n));
 }
 
 }  // namespace pts

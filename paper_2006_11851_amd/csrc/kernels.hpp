@@ -68,6 +68,12 @@ void launch_mstep(Ctx* c, const int32_t* nn, const float* dist, float* x, int H,
                   const float* ex, const uint32_t* ex_pk, int Hz, int Wz, float r, float delta, int o,
                   const float* wscale = nullptr);
 void launch_energy(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2);
+// The same energy with its partial sums in the library's fixed per-device
+// array (no allocation); energy_scratch_init returns that array's device
+// address for `device`, which must be current at the first call.
+float* energy_scratch_init(int device);
+void launch_energy_scratch(Ctx* c, const float* dist, int64_t n, float r, float delta, float* out2,
+                           float* scratch_ptr);
 
 // ---- index (k_index.hip)
 void launch_mean_cov_image(Ctx* c, const float* img, int H, int W, int w, double* mean, double* cov);

@@ -66,8 +66,21 @@ int pts_create(pts_ctx** out, int device, void* hip_stream, const pts_alloc* all
       g_create_error = "allocator needs both alloc and release";
       return PTS_ERR_ARG;
     }
+    // the fixed scratch of the allocation-free entry points, once per device
+    float* escratch = nullptr;
+    try {
+      if (hipSetDevice(device) != hipSuccess) {
+        g_create_error = "hipSetDevice failed";
+        return PTS_ERR_HIP;
+      }
+      escratch = pts::energy_scratch_init(device);
+    } catch (const pts::Error& e) {
+      g_create_error = e.msg;
+      return e.code;
+    }
     pts_ctx* c = new pts_ctx();
     c->device = device;
+    c->energy_scratch = escratch;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (alloc_or_null) {
@@ -354,6 +367,17 @@ int pts_energy_device(pts_ctx* c, const float* dist, int64_t nq, float r, float 
     PTS_REQUIRE(r > 0.f && r <= 2.f && delta > 0.f, PTS_ERR_ARG, "energy_device: need 0 < r <= 2, delta > 0");
     // a fill kernel, not a memset node, so that a caller may capture the call
     if (nq > 0) launch_energy(c, dist, nq, r, delta, out);
+    else launch_zero_i32(c, reinterpret_cast<int32_t*>(out), 2);
+  });
+}
+
+int pts_energy_device_noalloc(pts_ctx* c, const float* dist, int64_t nq, float r, float delta, float* out) {
+  CTX_REQUIRED(c);
+  return guard(c, [&] {
+    PTS_REQUIRE(nq >= 0 && (nq == 0 || dist) && out, PTS_ERR_ARG, "energy_device_noalloc: bad arguments");
+    PTS_REQUIRE(r > 0.f && r <= 2.f && delta > 0.f, PTS_ERR_ARG,
+                "energy_device_noalloc: need 0 < r <= 2, delta > 0");
+    if (nq > 0) launch_energy_scratch(c, dist, nq, r, delta, out, c->energy_scratch);
     else launch_zero_i32(c, reinterpret_cast<int32_t*>(out), 2);
   });
 }

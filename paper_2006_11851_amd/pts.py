@@ -65,12 +65,14 @@ class TorchAllocator:
         self.in_use = 0
         self.sizes = {}
         self.refused = 0
+        self.calls = 0  # allocation requests received
         self._alloc = ALLOC_FN(self._on_alloc)
         self._release = RELEASE_FN(self._on_release)
 
     def _on_alloc(self, user, nbytes, stream):
         import torch
 
+        self.calls += 1
         if self.budget is not None and self.in_use + nbytes > self.budget:
             self.refused += 1
             return None
@@ -269,6 +271,7 @@ SIGNATURES = {
     "pts_scale_init": (_I, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _D, _D, _F]),
     "pts_energy": (_I, [_P, _P, _I64, _F, _F, C.POINTER(_D), C.POINTER(_D)]),
     "pts_energy_device": (_I, [_P, _P, _I64, _F, _F, _P]),
+    "pts_energy_device_noalloc": (_I, [_P, _P, _I64, _F, _F, _P]),
     "pts_solve": (_I, [_P, C.POINTER(pts_solve_params), _P, _I, _I, _P, _I, _I, C.POINTER(pts_solve_trace)]),
     "pts_exemplar_pyramid_level": (_I, [_P, _I, _I, _F, _P]),
     "pts_upsample2": (_I, [_P, _P, _I, _I, _F, _P]),
@@ -575,6 +578,13 @@ class Context:
         if out is None:
             out = self._f32((2,))
         self._ok(lib().pts_energy_device(self._h, _ptr(dist), dist.numel(), r, delta, _ptr(out)))
+        return out
+
+    def energy_device_noalloc(self, dist, out, r=0.8, delta=1e-3):
+        """energy_device without any device allocation: out is the caller's
+        float32 device tensor [2]; the partial sums use the library's fixed
+        per-device array, so overlapping calls on one device race."""
+        self._ok(lib().pts_energy_device_noalloc(self._h, _ptr(dist), dist.numel(), r, delta, _ptr(out)))
         return out
 
     # -- multiscale
