@@ -138,10 +138,14 @@ int pts_scale_init(pts_ctx* ctx, const float* ex_rgbs, int Hz, int Wz, float* x_
 
 typedef struct pts_index_params {
   int w;                  /* neighbourhood width (even, 2..32) */
-  int pca_dims;           /* d (1..128); 0 = smallest d reaching variance_target */
+  int pca_dims;           /* d (1..128); 0 = smallest d reaching variance_target, at
+                             most 128 (the widest search kernels): where 128 dimensions
+                             retain less, d = 128 and retained_variance reports it */
   double variance_target; /* used when pca_dims == 0 (the paper keeps 95 %) */
   int branching;          /* k of the k-means splits (paper: 4), 2..64 */
-  int depth;              /* maximum tree depth; 0 = a single leaf */
+  int depth;              /* maximum tree depth, 0..8 (0 = a single leaf); -1 = no cap,
+                             the paper's rule alone: split until every leaf holds
+                             fewer than `branching` members */
   int kmeans_max_iter;    /* Lloyd iterations per split (default 50) */
   uint64_t seed;          /* seeds the k-means++ initial centres */
   int make_bf16;          /* also keep a bf16 copy of the projected exemplar */
@@ -161,8 +165,10 @@ typedef struct pts_index_info {
  * exemplar windows (FP64 accumulation on the GPU), host FP64 symmetric
  * eigensolve, basis B = the d leading eigenvectors (largest-|entry| made
  * positive), projection z' = B^T (z - mu), and the k-means tree over z'
- * (nodes split while depth < `depth` and the node holds >= branching
- * members - the paper's stop rule for small clusters).  Synchronous. */
+ * (nodes split while depth < `depth`, any depth with depth = -1, and the
+ * node holds >= branching members - the paper's stop rule for small
+ * clusters; a node whose k-means leaves one cluster, i.e. whose points are
+ * identical, stays a leaf).  Synchronous. */
 int pts_build_index(pts_ctx* ctx, const pts_index_params* p, pts_index_info* info_host);
 
 /* Host form of an index, for export/import (parity tests share a basis and

@@ -4,16 +4,19 @@ Methodology 2.2: starting at the root, k-means with k = 4 splits the
 neighbourhoods held by a node into k children, and each child is split again
 recursively; the paper stops when a node holds fewer than k neighbourhoods
 (replacing the 1 % rule of the method it builds on).  The search runs in the
-PCA-reduced space.  Here k is the ``branching`` argument and the recursion
-also stops at ``depth`` levels, so that a node is a leaf at depth ``depth``
-or when it holds fewer than ``branching`` members.
+PCA-reduced space.  Here k is the ``branching`` argument; the recursion may
+also stop at ``depth`` levels (``depth=None``: no cap, the paper's rule
+alone), so that a node is a leaf at depth ``depth`` or when it holds fewer
+than ``branching`` members.
 
 Readings where the paper is silent:
 * k-means++ seeding from one seeded PCG64 stream, drawn in breadth-first
   node order; Lloyd iterations until the assignment no longer changes or 50
   iterations; a cluster that becomes empty is dropped; the final centroids
   are the means of the final assignment; children are ordered by cluster
-  index; assignment ties go to the lowest cluster index;
+  index; assignment ties go to the lowest cluster index; a node whose
+  k-means keeps a single cluster (its points are identical, so no split
+  separates them) stays a leaf, which the uncapped recursion needs to end;
 * search = greedy descent (nearest child centroid at every level, ties to the
   lowest child), then exhaustive search of that one leaf, ties to the lowest
   exemplar id.
@@ -103,8 +106,9 @@ def lloyd(P: np.ndarray, C: np.ndarray, max_iter: int = 50):
     return C, a
 
 
-def build(Zp: np.ndarray, branching: int, depth: int, seed: int = 0, max_iter: int = 50) -> Tree:
-    """Build the tree over PCA-projected exemplar vectors Zp [N][d]."""
+def build(Zp: np.ndarray, branching: int, depth, seed: int = 0, max_iter: int = 50) -> Tree:
+    """Build the tree over PCA-projected exemplar vectors Zp [N][d]
+    (depth None or negative: no depth cap)."""
     Zp = np.asarray(Zp, dtype=np.float64)
     N, d = Zp.shape
     rng = np.random.default_rng(seed)
@@ -117,9 +121,12 @@ def build(Zp: np.ndarray, branching: int, depth: int, seed: int = 0, max_iter: i
     while head < len(members):
         mem = members[head]
         dep = ndepth[head]
-        if dep < depth and mem.size >= branching:
+        if (depth is None or depth < 0 or dep < depth) and mem.size >= branching:
             P = Zp[mem]
             C, a = lloyd(P, kmeanspp(P, branching, rng), max_iter)
+            if C.shape[0] < 2:  # one cluster: the points cannot be separated
+                head += 1
+                continue
             first[head] = len(members)
             nch[head] = C.shape[0]
             for j in range(C.shape[0]):

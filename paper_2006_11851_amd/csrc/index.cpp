@@ -7,8 +7,11 @@
 // made on the host from the GPU's running minimum distances), then Lloyd
 // iterations whose assignment and centroid sums run on the GPU, until no
 // assignment changes or the iteration limit is reached.  A node becomes a
-// leaf at the depth limit or when it holds fewer members than the branching
-// factor (the paper stops below k members).  Empty clusters are dropped.
+// leaf at the depth limit (none with depth -1: the paper's own rule) or when
+// it holds fewer members than the branching factor (the paper stops below k
+// members).  Empty clusters are dropped; a node whose split leaves a single
+// cluster (its points cannot be told apart) stays a leaf, so that the
+// uncapped growth ends.
 // Children are kept in cluster order and a node's members in ascending id.
 #include <algorithm>
 #include <chrono>
@@ -94,7 +97,7 @@ void grow_tree(Ctx* c, const float* P, int64_t N, int d, int dp, int branching, 
 
   DevMem d_members, d_seg_of, d_cent_off, d_k, d_cents, d_assign, d_mind, d_ids, d_cand, d_sums, d_counts, d_changed;
 
-  for (int level = 0; level < depth; ++level) {
+  for (int level = 0; depth < 0 || level < depth; ++level) {
     std::vector<int> segs;
     for (int i = 0; i < (int)nodes.size(); ++i)
       if (nodes[i].depth == level && nodes[i].n_children == 0 && nodes[i].count >= branching) segs.push_back(i);
@@ -176,7 +179,9 @@ void grow_tree(Ctx* c, const float* P, int64_t N, int d, int dp, int branching, 
     int32_t* changed = static_cast<int32_t*>(d_changed.ensure(c, 4));
     std::vector<unsigned long long> sums_h;
     std::vector<int32_t> counts_h;
-    for (int it = 0; it < max_iter + branching; ++it) {
+    // Runs until an iteration drops no cluster (every drop removes a centroid,
+    // so this ends): the final assignment must use the final numbering.
+    for (int it = 0;; ++it) {
       upload(c, d_cent_off, cent_off);
       upload(c, d_k, kk);
       launch_zero_i32(c, changed, 1);
@@ -230,6 +235,7 @@ void grow_tree(Ctx* c, const float* P, int64_t N, int d, int dp, int branching, 
     for (int s = 0; s < ns; ++s) {
       Node& nd = nodes[segs[s]];
       const int k = kk[s];
+      if (k < 2) continue;  // k-means left one cluster (identical points): the node stays a leaf
       nd.first_child = (int)nodes.size();
       nd.n_children = k;
       std::vector<std::vector<int32_t>> parts(k);
@@ -349,7 +355,7 @@ void build_index_on(Ctx* c, ExView ex, const pts_index_params& p, Index& ix, pts
   PTS_REQUIRE(p.pca_dims > 0 || (p.variance_target > 0.0 && p.variance_target <= 1.0), PTS_ERR_ARG,
               "index: variance_target must be in (0, 1]");
   PTS_REQUIRE(p.branching >= 2 && p.branching <= 64, PTS_ERR_UNSUPPORTED, "index: branching must be 2..64");
-  PTS_REQUIRE(p.depth >= 0 && p.depth <= 8, PTS_ERR_UNSUPPORTED, "index: depth must be 0..8");
+  PTS_REQUIRE(p.depth >= -1 && p.depth <= 8, PTS_ERR_UNSUPPORTED, "index: depth must be -1 (no cap) or 0..8");
   const int w = p.w, D = 4 * w * w;
   const int64_t N = (int64_t)(ex.Hz - w + 1) * (ex.Wz - w + 1);
   PTS_REQUIRE(N < ((int64_t)1 << 31) - 1, PTS_ERR_UNSUPPORTED, "index: too many exemplar windows");

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_descend_tiles(const float* __restrict__
                                                        const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ order,
                                                        const int2* __restrict__ tiles,
-                                                       const int32_t* __restrict__ ntiles,
+                                                       const int32_t* __restrict__ ntiles, int n_nodes,
                                                        int32_t* __restrict__ leaf) {
   const int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
   if (t >= *ntiles) return;  // uniform per wave
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_descend_tiles(const float* __restrict__
     qv[k + 3] = v.w;
   }
   int nd = nearest_child<DP>(qv, first_child[node], n_children[node], cent);
-  for (int depth = 2; depth < 64; ++depth) {  // bounded: a valid tree ends at a leaf long before
+  for (int step = 0; step < n_nodes; ++step) {  // bounded: no path is longer than the node count
     const int nc = n_children[nd];
     if (nc == 0) break;
     nd = nearest_child<DP>(qv, first_child[nd], nc, cent);
@@ -178,7 +178,7 @@ static void descend_entries(Ctx* c, const float* Qp, const int32_t* list, const 
   bucket_core(c, node1, n, n_nodes, DS_CHUNK, b);
   PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_descend_tiles<DPC>, dim3((unsigned)ceil_div(max_tiles, 4)), dim3(256), 0,
                                        c->stream, Qp, list, cent, first_child, n_children, leaf_of_node, b.off,
-                                       b.order, b.tiles, b.ntiles, leaf));
+                                       b.order, b.tiles, b.ntiles, n_nodes, leaf));
   check_launch("k_descend_tiles");
 }
 

@@ -50,6 +50,51 @@ def dict_to_oracle_tree(a: dict) -> otree.Tree:
     )
 
 
+def node_members(t: otree.Tree) -> list:
+    """Exemplar ids under every node (children before parents are not
+    assumed: nodes are visited from the last, which is breadth-first safe)."""
+    mem = [None] * t.n_nodes
+    for i in range(t.n_nodes - 1, -1, -1):
+        if t.n_children[i] == 0:
+            l = t.leaf_of_node[i]
+            mem[i] = np.asarray(t.perm[t.leaf_off[l]:t.leaf_off[l + 1]], np.int64)
+        else:
+            f = t.first_child[i]
+            mem[i] = np.concatenate([mem[f + j] for j in range(t.n_children[i])])
+    return mem
+
+
+def check_tree_rules(t: otree.Tree, Zp: np.ndarray, branching: int, depth=None, atol: float = 0.0):
+    """The tree's structural rules (Methodology 2.2's stop rule): the leaves
+    partition the N ids; a node is split only if it holds >= branching
+    members and has >= 2 children (up to the depth cap, if any); a leaf with
+    >= branching members is allowed only at the cap or when its points are
+    identical (within atol, per coordinate); every child's centroid is the
+    mean of its members.  Returns (depth reached, leaf sizes)."""
+    N = Zp.shape[0]
+    assert np.array_equal(np.sort(np.asarray(t.perm, np.int64)), np.arange(N))
+    assert t.leaf_off[0] == 0 and t.leaf_off[-1] == N and np.all(np.diff(t.leaf_off) >= 0)
+    mem = node_members(t)
+    dep = np.zeros(t.n_nodes, np.int64)
+    for i in range(t.n_nodes):
+        nc = t.n_children[i]
+        if nc > 0:
+            assert nc >= 2 and mem[i].size >= branching, (i, nc, mem[i].size)
+            assert depth is None or dep[i] < depth
+            for j in range(nc):
+                c = t.first_child[i] + j
+                assert c > i
+                dep[c] = dep[i] + 1
+                assert mem[c].size > 0
+                cen = Zp[mem[c]].mean(axis=0)
+                assert np.abs(t.centroids[c] - cen).max() <= 1e-6 + 1e-5 * np.abs(cen).max(), (c,)
+        elif mem[i].size >= branching and not (depth is not None and dep[i] == depth):
+            P = Zp[mem[i]]
+            assert np.abs(P - P[0]).max() <= atol, (i, mem[i].size)
+    sizes = np.diff(t.leaf_off)
+    return int(dep.max()), sizes
+
+
 def projector_gap(B1, B2) -> float:
     return float(np.abs(B1 @ B1.T - B2 @ B2.T).max())
 
