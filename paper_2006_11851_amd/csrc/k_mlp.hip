@@ -592,10 +592,12 @@ __device__ __forceinline__ floatx16 tile_mfma_epi(const uint4* frag, const float
 // tile t + 1, barrier - is one straight block.  The first tile's products
 // and the last tile's epilogue are peeled.  Past the end the loads re-read
 // the last tile and the store writes it into the buffer no one reads again.
-template <int KS, int VPS, class Slot>
+// first(acc) sees the first tile's accumulator before any slot update.
+template <int KS, int VPS, class Slot, class First>
 __device__ __forceinline__ void stream_tiles_slots(uint4 (*frag)[KS * WF_KK], float (*bs)[32],
                                                    const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
-                                                   int ntiles, const bf16x8 (&B)[KS], int tid, int lane, Slot&& slot) {
+                                                   int ntiles, const bf16x8 (&B)[KS], int tid, int lane, Slot&& slot,
+                                                   First&& first) {
   const int last = ntiles - 1;
   TileRegs T0 = wt_load<KS>(Wb, bias, 0, tid);
   TileRegs T1 = wt_load<KS>(Wb, bias, min(1, last) * 32, tid);
@@ -605,6 +607,7 @@ __device__ __forceinline__ void stream_tiles_slots(uint4 (*frag)[KS * WF_KK], fl
   floatx16 acc[2];
   T0 = wt_load<KS>(Wb, bias, min(2, last) * 32, tid);
   acc[0] = tile_mfma<KS>(frag[0], bs[0], B, lane);
+  first(acc[0]);
   wt_store<KS>(T1, frag[1], bs[1], tid);
   lds_barrier();
   auto step = [&](auto U, int tt) {
@@ -632,6 +635,12 @@ __device__ __forceinline__ void stream_tiles_slots(uint4 (*frag)[KS * WF_KK], fl
 #pragma unroll
     for (int r = 0; r < 16; ++r) slot(acc[0], last, r);
   }
+}
+template <int KS, int VPS, class Slot>
+__device__ __forceinline__ void stream_tiles_slots(uint4 (*frag)[KS * WF_KK], float (*bs)[32],
+                                                   const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
+                                                   int ntiles, const bf16x8 (&B)[KS], int tid, int lane, Slot&& slot) {
+  stream_tiles_slots<KS, VPS>(frag, bs, Wb, bias, ntiles, B, tid, lane, slot, [](const floatx16&) {});
 }
 
 __device__ __forceinline__ bf16x8 gelu_bf16x8(const floatx16& acc, int c) {
@@ -997,16 +1006,20 @@ __device__ __forceinline__ void topp_finish(const TopP<PP>& top, float s, int la
 }
 
 // Output layer in one pass over the weight tiles.  Per value slot (lane,
-// register) the three largest logits m1 >= m2 >= m3, the tiles of the first
-// two, and sum_j exp(l_j - m1) over the slot (rescaled whenever m1 grows),
-// about 12 operations and one exponential per logit.  Then tau = the P-th
-// largest of the query's 64 values m1, m2 (as in the two-pass form, a lower
-// bound of the P-th largest logit); a slot whose m3 is below tau holds no
-// logit >= tau beyond m1 and m2, whose leaves are known, so the top-P is
-// exact unless some slot has m3 >= tau (three or more top logits in one
-// slot, or ties).  Returns that case - the caller hands the query to the
+// register) the three largest logit keys - the logit with its low tb
+// mantissa bits replaced by (2^tb - 1 - t), t the tile, so that a key names
+// its leaf and, among equal logits, the lower tile ranks first - kept by
+// medians (k1 >= k2 >= k3), and sum_j exp(l_j - R) over the slot, R the
+// query's largest logit of the first tile: one fused multiply-add, one
+// exponential, one add and four key operations per logit.  Then tau = the
+// P-th largest of the query's 64 values k1, k2 (a lower bound of the P-th
+// largest key, as in the two-pass form); a slot whose k3 is below tau holds
+// no key >= tau beyond k1 and k2, so the top-P is exact unless some slot has
+// k3 >= tau (three or more top logits in one slot, or ties), a hit list is
+// full, or some logit exceeds R by so much that the sum may have lost
+// precision.  Returns that case - the caller hands the query to the
 // two-pass form - and writes nothing for it; otherwise writes the top-P and
-// the margin.
+// the margin (from keys: logits to 2^(tb - 23) relative).
 template <int KS, int PP>
 __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q, int64_t nq,
                                                const uint16_t* __restrict__ Wb, const float* __restrict__ bias,
@@ -1016,46 +1029,56 @@ __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q,
   constexpr int HC = 8;  // hit-list capacity per lane
   const int h = lane >> 5;
   const int ntiles = (N + 31) / 32;
-  float m1[16], m2[16], m3[16], sm[16];
-  uint32_t i12[16];  // tile of m1 in the low half, of m2 in the high half
+  int tb = 1;
+  while ((1 << tb) < ntiles) ++tb;
+  const uint32_t lmask = (1u << tb) - 1u, kmask = ~lmask;
+  float k1[16], k2[16], k3[16], sm[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    m1[r] = -FLT_MAX;
-    m2[r] = -FLT_MAX;
-    m3[r] = -FLT_MAX;
+    k1[r] = -INFINITY;
+    k2[r] = -INFINITY;
+    k3[r] = -INFINITY;
     sm[r] = 0.f;
-    i12[r] = 0;
   }
-  stream_tiles_slots<KS, 14>(frag, bs, Wb, bias, ntiles, B, tid, lane, [&](const floatx16& acc, int t, int r) {
-    const float x = acc[r];
-    const bool g1 = x > m1[r], g2 = x > m2[r];
-    // exp(-|x - m1|): the new term, or the factor rescaling the old sum
-    const float e = __builtin_amdgcn_exp2f(-fabsf(x - m1[r]) * ML_LOG2E);
-    sm[r] = g1 ? fmaf(sm[r], e, 1.0f) : sm[r] + e;
-    m3[r] = __builtin_amdgcn_fmed3f(x, m2[r], m3[r]);  // m3 <= m2: max(m3, min(m2, x))
-    m2[r] = __builtin_amdgcn_fmed3f(x, m1[r], m2[r]);
-    const uint32_t shift1 = (i12[r] << 16) | (uint32_t)t;               // m1 -> m2, x -> m1
-    const uint32_t new2 = (i12[r] & 0xffffu) | ((uint32_t)t << 16);      // x -> m2
-    i12[r] = g1 ? shift1 : (g2 ? new2 : i12[r]);
-    m1[r] = g1 ? x : m1[r];
-  });
-  // the largest logit M and s = sum_j exp(l_j - M) over both halves
-  float mx = m1[0];
+  float rl2 = 0.f;  // R log2(e)
+  stream_tiles_slots<KS, 7>(
+      frag, bs, Wb, bias, ntiles, B, tid, lane,
+      [&](const floatx16& acc, int t, int r) {
+        const float x = acc[r];
+        sm[r] += __builtin_amdgcn_exp2f(fmaf(x, ML_LOG2E, -rl2));
+        const float k = __uint_as_float((__float_as_uint(x) & kmask) | (lmask - (uint32_t)t));
+        // with k3 <= k2 <= k1: the three largest of (k1, k2, k3, k)
+        k3[r] = __builtin_amdgcn_fmed3f(k, k2[r], k3[r]);
+        k2[r] = __builtin_amdgcn_fmed3f(k, k1[r], k2[r]);
+        k1[r] = __builtin_amdgcn_fmed3f(k1[r], k, INFINITY);
+      },
+      [&](const floatx16& acc0) {
+        float m = acc0[0];
 #pragma unroll
-  for (int r = 1; r < 16; ++r) mx = fmaxf(mx, m1[r]);
-  mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+        for (int r = 1; r < 16; ++r) m = __builtin_amdgcn_fmed3f(m, acc0[r], INFINITY);
+        m = __builtin_amdgcn_fmed3f(m, __shfl_xor(m, 32, 64), INFINITY);
+        rl2 = m * ML_LOG2E;
+      });
+  // the largest key M (the largest logit) and s = sum_j exp(l_j - M) over both halves
+  float mx = k1[0];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) mx = __builtin_amdgcn_fmed3f(mx, k1[r], INFINITY);
+  mx = __builtin_amdgcn_fmed3f(mx, __shfl_xor(mx, 32, 64), INFINITY);
   float ssum = 0.f;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) ssum = fmaf(sm[r], __builtin_amdgcn_exp2f((m1[r] - mx) * ML_LOG2E), ssum);
+  for (int r = 0; r < 16; ++r) ssum += sm[r];
   ssum += __shfl_xor(ssum, 32, 64);
-  // tau: the P-th largest of the query's 64 slot values m1, m2
+  // beyond 2^64 the sum's terms relative to R have grown too far
+  bool fallback = !(mx * ML_LOG2E - rl2 <= 64.f);
+  ssum *= __builtin_amdgcn_exp2f(rl2 - mx * ML_LOG2E);
+  // tau: the P-th largest of the query's 64 slot values k1, k2
   float tau;
   {
     // (max / min as medians with an infinity: fmaxf / fminf would first
     // quieten their operands)
     float v[PP];
 #pragma unroll
-    for (int u = 0; u < PP; ++u) v[u] = -FLT_MAX;
+    for (int u = 0; u < PP; ++u) v[u] = -INFINITY;
     auto push = [&](float x) {
 #pragma unroll
       for (int u = 0; u < PP; ++u) {
@@ -1066,8 +1089,8 @@ __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q,
     };
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      push(m1[r]);
-      push(m2[r]);
+      push(k1[r]);
+      push(k2[r]);
     }
     float ov[PP];
 #pragma unroll
@@ -1080,30 +1103,24 @@ __device__ __forceinline__ bool out_topk_1pass(const bf16x8 (&B)[KS], int64_t q,
       if (u < kout) tk = v[u];
     tau = tk;
   }
-  // the hits m1, m2 >= tau with their leaves; a slot with m3 >= tau (or a
+  // the hits k1, k2 >= tau with their leaves; a slot with k3 >= tau (or a
   // full list) leaves the query to the two-pass form
   int cnt = 0;
-  bool fallback = false;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int off = 8 * (r >> 2) + 4 * h + (r & 3);
-    fallback = fallback || (m3[r] >= tau);
-    if (m1[r] >= tau) {
-      if (cnt < HC) {
-        hv[cnt][tid] = m1[r];
-        hid[cnt][tid] = (int)(i12[r] & 0xffffu) * 32 + off;
-        ++cnt;
-      } else {
-        fallback = true;
-      }
-    }
-    if (m2[r] >= tau) {
-      if (cnt < HC) {
-        hv[cnt][tid] = m2[r];
-        hid[cnt][tid] = (int)(i12[r] >> 16) * 32 + off;
-        ++cnt;
-      } else {
-        fallback = true;
+    fallback = fallback || (k3[r] >= tau);
+    const float kv[2] = {k1[r], k2[r]};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (kv[u] >= tau) {
+        if (cnt < HC) {
+          hv[cnt][tid] = kv[u];
+          hid[cnt][tid] = (int)(lmask - (__float_as_uint(kv[u]) & lmask)) * 32 + off;
+          ++cnt;
+        } else {
+          fallback = true;
+        }
       }
     }
   }
