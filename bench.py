@@ -139,7 +139,7 @@ def headline(a):
         method = ("bf16_learned", dict(mode="learned_bf16", residual=a.residual, rerank_full=a.rerank_full,
                                        n_proposals=a.proposals, margin=a.margin))
     else:
-        method = ("bf16_brute", dict(mode="brute_bf16", residual=a.residual, rerank_full=a.rerank_full))
+        method = ("bf16_brute", dict(mode="brute_bf16", residual=a.residual, rerank_full=a.rerank_full, topk=16))
     forms = dict([("plain_fp32_tree", dict(mode="tree")), method])
     if a.only:
         forms = {k: v for k, v in forms.items() if v["mode"] == a.only}
@@ -158,7 +158,7 @@ def headline(a):
         setup["break_even_iterations"] = setup_ms / saving_ms if saving_ms > 0 else None
     kern = head["kernels_ms_per_step"]
     rank = sorted(kern, key=lambda k: -kern[k])
-    roofs = [roofline(head, info, nq, a, k) for k in rank[:4]]
+    roofs = [roofline(head, info, nq, a, k, a.workload) for k in rank[:4]]
     roofs = [r for r in roofs if r["bound"] is not None] or roofs
     roof = max(roofs, key=lambda r: r["ms_per_launch"])
     roof_next = [r for r in roofs if r is not roof]
@@ -266,7 +266,7 @@ def run_form(ctx, x0, w, s, nq, kw, a, gap):
                 launches={k: v[1] for k, v in prof.items()})
 
 
-def roofline(head, info, nq, a, dom):
+def roofline(head, info, nq, a, dom, workload=None):
     """Kernel `dom` of the reported form against its bound: algorithmic work
     per launch (counted on the device for the scans) over the launch's
     average time on the library's stream."""
@@ -301,26 +301,27 @@ def roofline(head, info, nq, a, dom):
                 "traffic": None, "ms_per_launch": per_launch_ms}
     ach = flops / (per_launch_ms * 1e-3) / 1e12
     return {"kernel": dom, "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-            "traffic": measured_traffic(dom), "ms_per_launch": per_launch_ms, "algorithmic_flops_per_launch": flops}
+            "traffic": measured_traffic(dom, workload or a.workload), "ms_per_launch": per_launch_ms,
+            "algorithmic_flops_per_launch": flops}
 
 
-def measured_traffic(label):
-    """HBM bytes per full-size launch of the kernel behind `label`, from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy
-    calibration), or None when there is none or the kernel's source file has
-    changed since the counters were taken."""
+def measured_traffic(label, workload):
+    """HBM bytes per full-size launch of the kernel behind `label` on this
+    workload, from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    (scaled by the copy calibration), or None when there is none or the
+    kernel's source file has changed since the counters were taken."""
     import glob
     import hashlib
 
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
         for line in open(path):
             f = line.split()
-            if len(f) == 5 and f[0] == "traffic:" and f[1] == label:
-                src = os.path.join(ROOT, "paper_2006_11851_amd", "csrc", f[3])
+            if len(f) == 6 and f[0] == "traffic:" and f[1] == workload and f[2] == label:
+                src = os.path.join(ROOT, "paper_2006_11851_amd", "csrc", f[4])
                 if not os.path.exists(src):
                     return None
                 digest = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
-                return float(f[2]) if digest == f[4] else None
+                return float(f[3]) if digest == f[5] else None
     return None
 
 

@@ -202,7 +202,8 @@ typedef struct pts_estep_params {
   int mode;        /* PTS_MODE_* */
   int w;           /* neighbourhood width; must equal the index's w for PCA modes */
   int stride;      /* grid stride s (the paper: w / 4) */
-  int topk;        /* BF16 candidates kept for the FP32 re-rank (8; 1..8) */
+  int topk;        /* BF16 candidates kept for the FP32 re-rank (0 = 8; 1..16 for BRUTE_BF16,
+                      1..8 for the learned forms) */
   int rerank_full; /* 1: re-rank BF16 candidates by full-D distance; 0: PCA space */
   int n_proposals; /* leaves proposed by the MLP (4; 1..8) */
   float margin;    /* softmax margin p1 - p2 below which the tree is used (0.2) */

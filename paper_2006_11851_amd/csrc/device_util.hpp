@@ -22,22 +22,23 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
 // (score, id) order: ties to the lower id
 __device__ __forceinline__ bool lex_lt(float a, int ia, float b, int ib) { return a < b || (a == b && ia < ib); }
 
-struct Top8Lex {
-  float d[8];
-  int i[8];
+template <int K>
+struct TopLex {
+  float d[K];
+  int i[K];
   __device__ __forceinline__ void init() {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < K; ++t) {
       d[t] = FLT_MAX;
       i[t] = INT_MAX;
     }
   }
   __device__ __forceinline__ void insert(float v, int id) {
-    bool lt[8];
+    bool lt[K];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) lt[t] = lex_lt(v, id, d[t], i[t]);
+    for (int t = 0; t < K; ++t) lt[t] = lex_lt(v, id, d[t], i[t]);
 #pragma unroll
-    for (int t = 7; t > 0; --t) {
+    for (int t = K - 1; t > 0; --t) {
       d[t] = lt[t - 1] ? d[t - 1] : (lt[t] ? v : d[t]);
       i[t] = lt[t - 1] ? i[t - 1] : (lt[t] ? id : i[t]);
     }
@@ -45,5 +46,6 @@ struct Top8Lex {
     i[0] = lt[0] ? id : i[0];
   }
 };
+using Top8Lex = TopLex<8>;
 
 }  // namespace pts

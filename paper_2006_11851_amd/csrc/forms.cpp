@@ -9,13 +9,14 @@ namespace pts {
 bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
                        const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist) {
   const int k = p.topk <= 0 ? 8 : p.topk;
-  PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
+  PTS_REQUIRE(k >= 1 && k <= 16, PTS_ERR_ARG, "topk must be 1..16");
+  const int kt = k <= 8 ? 8 : 16;  // list length per (split, query)
   const int S = brute_splits(nq);
-  float* pd = c->buf<float>("bb_pd", (size_t)S * nq * 8);
-  int32_t* pi = c->buf<int32_t>("bb_pi", (size_t)S * nq * 8);
+  float* pd = c->buf<float>("bb_pd", (size_t)S * nq * kt);
+  int32_t* pi = c->buf<int32_t>("bb_pi", (size_t)S * nq * kt);
   const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();
   const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
-  launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, ix.N, ix.dk, S, pd, pi);
+  launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, ix.N, ix.dk, S, kt, pd, pi);
   if (p.rerank_full) {
     launch_select_rerank_full(c, pd, pi, nq, S, 1, nq, nullptr, nullptr, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
                               p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);

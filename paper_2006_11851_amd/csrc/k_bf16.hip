@@ -22,6 +22,7 @@
 // and the FP32 re-rank follow.
 #include <algorithm>
 #include <cfloat>
+#include <type_traits>
 #include <utility>
 #include <climits>
 
@@ -150,9 +151,9 @@ __device__ __forceinline__ void stage_store(const StageRegs<KS, NTH>& R, BruteSm
 }
 
 // One wave: 64 queries (two B tiles) against the staged 128 rows.
-template <int KS>
+template <int KS, int KT>
 __device__ __forceinline__ void stage_compute(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
-                                              TopK<BB_TOPK> (&top)[2], int64_t pos0, int lane, int nvalid) {
+                                              TopK<KT> (&top)[2], int64_t pos0, int lane, int nvalid) {
 #pragma unroll
   for (int t = 0; t < BB_STAGE / 32; ++t) {
     if (t * 32 >= nvalid) break;  // rows past the range: padding only
@@ -181,18 +182,18 @@ __device__ __forceinline__ void stage_compute(const BruteSmem<KS>& S, int buf, c
       float m = acc[0];
 #pragma unroll
       for (int r = 1; r < 16; ++r) m = fminf(m, acc[r]);
-      if (__any(m < top[qt].d[BB_TOPK - 1])) {
+      if (__any(m < top[qt].d[KT - 1])) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const float v = acc[r];
-          if (v < top[qt].d[BB_TOPK - 1]) top[qt].insert(v, (int)(tpos + 8 * (r >> 2) + (r & 3)));
+          if (v < top[qt].d[KT - 1]) top[qt].insert(v, (int)(tpos + 8 * (r >> 2) + (r & 3)));
         }
       }
     }
   }
 }
 
-template <int KS>
+template <int KS, int KT>
 __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restrict__ Qb, int64_t nq,
                                                          const uint16_t* __restrict__ Zb,
                                                          const float* __restrict__ zbn, int64_t N, int S,
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
       B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
   }
-  TopK<BB_TOPK> top[2];
+  TopK<KT> top[2];
   top[0].init();
   top[1].init();
   if (row_begin < row_end) {
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
         // unconditional (past the end: the last rows again, never stored), so
         // the wait before the store covers only the older stage
         stage_load<KS>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
-        stage_compute<KS>(sm, u, B, top, row_begin + (int64_t)st * BB_STAGE, lane,
+        stage_compute<KS, KT>(sm, u, B, top, row_begin + (int64_t)st * BB_STAGE, lane,
                           (int)min((int64_t)BB_STAGE, row_end - row_begin - (int64_t)st * BB_STAGE));
         if (st + 1 < nstages)
           stage_store<KS>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
@@ -244,24 +245,25 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
       }
     }
   }
-  // merge the two lanes that share a query: the k smallest of two sorted lists
+  // merge the two lanes that share a query: the k smallest of two sorted
+  // lists (in bitonic order; the merge kernels take them in any order)
 #pragma unroll
   for (int qt = 0; qt < 2; ++qt) {
-    float od[BB_TOPK];
-    int oi[BB_TOPK];
+    float od[KT];
+    int oi[KT];
 #pragma unroll
-    for (int t = 0; t < BB_TOPK; ++t) {
+    for (int t = 0; t < KT; ++t) {
       od[t] = __shfl_xor(top[qt].d[t], 32, 64);
       oi[t] = __shfl_xor(top[qt].i[t], 32, 64);
     }
     const int64_t q = qb * BB_QPB + wave * 64 + qt * 32 + (lane & 31);
     if (lane < 32 && q < nq) {
-      float* pd = part_d + ((int64_t)split * nq + q) * BB_TOPK;
-      int32_t* pi = part_i + ((int64_t)split * nq + q) * BB_TOPK;
+      float* pd = part_d + ((int64_t)split * nq + q) * KT;
+      int32_t* pi = part_i + ((int64_t)split * nq + q) * KT;
 #pragma unroll
-      for (int t = 0; t < BB_TOPK; ++t) {
-        const float a = top[qt].d[t], b = od[BB_TOPK - 1 - t];
-        const int ia = top[qt].i[t], ib = oi[BB_TOPK - 1 - t];
+      for (int t = 0; t < KT; ++t) {
+        const float a = top[qt].d[t], b = od[KT - 1 - t];
+        const int ia = top[qt].i[t], ib = oi[KT - 1 - t];
         const bool take_a = a < b || (a == b && ia < ib);
         pd[t] = take_a ? a : b;
         pi[t] = take_a ? ia : ib;
@@ -474,7 +476,8 @@ struct HitLists {
 // top <- the 8 smallest (score, position) keys among the query's collected
 // rows (the pair leaves and counts are loaded together, then the rows)
 constexpr int HL_PMAX = 9;  // pairs per query: up to 8 proposals + the tree's leaf
-__device__ __forceinline__ void top8_from_hits(Top8Lex& top, const HitLists& L, int64_t q) {
+template <int K>
+__device__ __forceinline__ void top8_from_hits(TopLex<K>& top, const HitLists& L, int64_t q) {
   int n[2 * HL_PMAX];
 #pragma unroll
   for (int j = 0; j < HL_PMAX; ++j) {
@@ -489,7 +492,7 @@ __device__ __forceinline__ void top8_from_hits(Top8Lex& top, const HitLists& L, 
     for (int e = 0; e < n[j]; ++e) {
       const int2 v = hp[e];
       const float sv = __int_as_float(v.x);
-      if (lex_lt(sv, v.y, top.d[7], top.i[7])) top.insert(sv, v.y);
+      if (lex_lt(sv, v.y, top.d[K - 1], top.i[K - 1])) top.insert(sv, v.y);
     }
   }
 }
@@ -935,15 +938,21 @@ int brute_splits(int64_t nq) {
 }
 
 void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16_t* Zb, const float* zbn, int64_t N,
-                            int dk, int S, float* part_d, int32_t* part_i) {
+                            int dk, int S, int kt, float* part_d, int32_t* part_i) {
   ProfScope ps(c, "brute_bf16_topk");
   if (nq == 0) return;
   PTS_REQUIRE(N > 0 && N < INT_MAX, PTS_ERR_ARG, "brute: bad N");
   const int64_t qblocks = ceil_div(nq, BB_QPB);
   const int64_t rows = round_up(ceil_div(N, S), BB_STAGE);
   PTS_REQUIRE(qblocks * S < (int64_t)1 << 31, PTS_ERR_UNSUPPORTED, "brute: grid too large");
-  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_brute_bf16_topk<KSC>, dim3((unsigned)(qblocks * S)), dim3(BB_QPB), 0,
-                                       c->stream, Qb, nq, Zb, zbn, N, S, rows, part_d, part_i));
+  PTS_REQUIRE(kt == 8 || kt == 16, PTS_ERR_ARG, "brute: list length must be 8 or 16");
+  if (kt == 8) {
+    PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_brute_bf16_topk<KSC, 8>), dim3((unsigned)(qblocks * S)), dim3(BB_QPB), 0,
+                                         c->stream, Qb, nq, Zb, zbn, N, S, rows, part_d, part_i));
+  } else {
+    PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_brute_bf16_topk<KSC, 16>), dim3((unsigned)(qblocks * S)), dim3(BB_QPB),
+                                         0, c->stream, Qb, nq, Zb, zbn, N, S, rows, part_d, part_i));
+  }
   check_launch("k_brute_bf16_topk");
 }
 
@@ -1064,7 +1073,7 @@ void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P
 
 // list s of query q is row (q * qs + s * ss) of part [..][8]; a list whose
 // valid[] entry is negative is skipped (valid == NULL: all lists valid).
-template <int DP>
+template <int DP, int KL>
 __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restrict__ part_d,
                                                           const int32_t* __restrict__ part_i, int64_t nq, int S,
                                                           int64_t qs, int64_t ss, const int32_t* __restrict__ valid,
@@ -1076,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
                                                           int32_t* __restrict__ nn) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  Top8Lex top;
+  TopLex<KL> top;
   top.init();
   if (hl.hits) {
     top8_from_hits(top, hl, q);
@@ -1084,13 +1093,13 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
     for (int s = 0; s < S; ++s) {
       const int64_t row = q * qs + (int64_t)s * ss;
       if (valid && valid[row] < 0) continue;
-      const float* pd = part_d + row * BB_TOPK;
-      const int32_t* pi = part_i + row * BB_TOPK;
-      for (int t = 0; t < BB_TOPK; ++t)
-        if (lex_lt(pd[t], pi[t], top.d[7], top.i[7])) top.insert(pd[t], pi[t]);
+      const float* pd = part_d + row * KL;
+      const int32_t* pi = part_i + row * KL;
+      for (int t = 0; t < KL; ++t)
+        if (lex_lt(pd[t], pi[t], top.d[KL - 1], top.i[KL - 1])) top.insert(pd[t], pi[t]);
     }
   }
-  if (!nn) {  // candidates only (a full-D re-rank follows)
+  if (!nn) {  // candidates only (the first 8; a full-D re-rank follows)
 #pragma unroll
     for (int t = 0; t < BB_TOPK; ++t) {
       const int pos = top.i[t];
@@ -1110,9 +1119,9 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
   float best = FLT_MAX;
   int bid = INT_MAX;
 #pragma unroll
-  for (int t = 0; t < BB_TOPK; ++t) {
+  for (int t = 0; t < KL; ++t) {
     const int pos = top.i[t];
-    if (cand_out) cand_out[q * BB_TOPK + t] = (t < k && pos >= 0 && pos < N) ? perm[pos] : -1;
+    if (cand_out && t < BB_TOPK) cand_out[q * BB_TOPK + t] = (t < k && pos >= 0 && pos < N) ? perm[pos] : -1;
     if (t >= k || pos < 0 || pos >= N) continue;
     const float* zr = Zp + (int64_t)pos * DP;
     float acc = 0.f;
@@ -1141,11 +1150,17 @@ void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i,
                              int32_t* nn) {
   ProfScope ps(c, "merge_rerank");
   if (nq == 0) return;
-  PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
+  PTS_REQUIRE(k >= 1 && k <= 16 && (k <= 8 || !sh), PTS_ERR_ARG, "topk must be 1..16 (1..8 with hit lists)");
   const HitLists hl = hit_lists(sh);
-  PTS_DP_SWITCH(dp, hipLaunchKernelGGL(k_merge_rerank_pca<DPC>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
-                                       c->stream, part_d, part_i, nq, S, qs, ss, valid, hl, k, Qp, Zp, zres, perm, N,
-                                       cand_out, nn));
+  if (k <= 8) {
+    PTS_DP_SWITCH(dp, hipLaunchKernelGGL((k_merge_rerank_pca<DPC, 8>), dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
+                                         c->stream, part_d, part_i, nq, S, qs, ss, valid, hl, k, Qp, Zp, zres, perm, N,
+                                         cand_out, nn));
+  } else {
+    PTS_DP_SWITCH(dp, hipLaunchKernelGGL((k_merge_rerank_pca<DPC, 16>), dim3((unsigned)ceil_div(nq, 256)), dim3(256),
+                                         0, c->stream, part_d, part_i, nq, S, qs, ss, valid, hl, k, Qp, Zp, zres, perm,
+                                         N, cand_out, nn));
+  }
   check_launch("k_merge_rerank_pca");
 }
 
@@ -1164,7 +1179,7 @@ constexpr int SR_QPB = 256;
 // PK: the exemplar windows come from its 8-bit form (pk, srow), rebuilt as
 // the same floats the RGBS image holds (channel value / 255, the row's
 // guidance value), at 4 bytes a pixel instead of 16.
-template <bool PK>
+template <bool PK, int KL>
 __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     const float* __restrict__ part_d, const int32_t* __restrict__ part_i, int64_t nq, int S, int64_t qs, int64_t ss,
     const int32_t* __restrict__ valid, HitLists hl, int k, const int32_t* __restrict__ perm, int64_t npos,
@@ -1174,9 +1189,9 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
   // per query of the block (phase 1, one thread each): the candidates, their
   // window origins (pixel index, row) and the query window's row and column,
   // so that the 16 lanes of a query in phase 2 do no index arithmetic of their own
-  __shared__ int32_t cand[BB_TOPK][SR_QPB];
-  __shared__ int32_t cbase[BB_TOPK][SR_QPB];
-  __shared__ int32_t crow[BB_TOPK][SR_QPB];
+  __shared__ int32_t cand[KL][SR_QPB];
+  __shared__ int32_t cbase[KL][SR_QPB];
+  __shared__ int32_t crow[KL][SR_QPB];
   __shared__ int32_t qvu[2][SR_QPB];
   const int tid = threadIdx.x;
   const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SR_QPB;
@@ -1184,7 +1199,7 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
   const int64_t N = (int64_t)(Hz - w + 1) * nu;
   {
     const int64_t q = q0 + tid;
-    Top8Lex top;
+    TopLex<KL> top;
     top.init();
     if (q < nq && hl.hits) {
       top8_from_hits(top, hl, q);
@@ -1192,21 +1207,30 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
       for (int li = 0; li < S; ++li) {
         const int64_t row = q * qs + (int64_t)li * ss;
         if (valid && valid[row] < 0) continue;
-        const float4 da = reinterpret_cast<const float4*>(part_d + row * BB_TOPK)[0];
-        const float4 db = reinterpret_cast<const float4*>(part_d + row * BB_TOPK)[1];
-        const int4 ia = reinterpret_cast<const int4*>(part_i + row * BB_TOPK)[0];
-        const int4 ib = reinterpret_cast<const int4*>(part_i + row * BB_TOPK)[1];
-        const float dv[8] = {da.x, da.y, da.z, da.w, db.x, db.y, db.z, db.w};
-        const int iv[8] = {ia.x, ia.y, ia.z, ia.w, ib.x, ib.y, ib.z, ib.w};
+        float dv[KL];
+        int iv[KL];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          // lists are sorted: once nothing in the wave improves, skip the insertion network
-          if (__any(lex_lt(dv[t], iv[t], top.d[7], top.i[7]))) top.insert(dv[t], iv[t]);
+        for (int t4 = 0; t4 < KL / 4; ++t4) {
+          const float4 da = reinterpret_cast<const float4*>(part_d + row * KL)[t4];
+          const int4 ia = reinterpret_cast<const int4*>(part_i + row * KL)[t4];
+          dv[4 * t4] = da.x;
+          dv[4 * t4 + 1] = da.y;
+          dv[4 * t4 + 2] = da.z;
+          dv[4 * t4 + 3] = da.w;
+          iv[4 * t4] = ia.x;
+          iv[4 * t4 + 1] = ia.y;
+          iv[4 * t4 + 2] = ia.z;
+          iv[4 * t4 + 3] = ia.w;
+        }
+#pragma unroll
+        for (int t = 0; t < KL; ++t) {
+          // once nothing in the wave improves on the last kept entry, skip the insertion network
+          if (__any(lex_lt(dv[t], iv[t], top.d[KL - 1], top.i[KL - 1]))) top.insert(dv[t], iv[t]);
         }
       }
     }
 #pragma unroll
-    for (int t = 0; t < BB_TOPK; ++t) {
+    for (int t = 0; t < KL; ++t) {
       const int pos = top.i[t];
       const int e = (t < k && pos >= 0 && pos < npos) ? perm[pos] : -1;
       cand[t][tid] = e;
@@ -1229,14 +1253,19 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     const int64_t q = q0 + ql;
     if (q >= nq) continue;  // uniform per 16-lane group; shuffles stay inside the group
     const int v = qvu[0][ql], u = qvu[1][ql];
+    float bbd = FLT_MAX;
+    int bbi = INT_MAX;
+    // the candidates in groups of 8 (one group unless 16 are re-ranked)
+#pragma unroll
+    for (int cg = 0; cg < KL; cg += 8) {
     // 32-bit byte offsets of the windows' origins in the 8-bit form (pixel
     // indices below 2^26): loads from a scalar base plus a 32-bit offset
     uint32_t eb[8];
     int eyc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      eb[c] = PK ? (uint32_t)cbase[c][ql] * 4u : (uint32_t)cbase[c][ql];
-      eyc[c] = crow[c][ql];
+      eb[c] = PK ? (uint32_t)cbase[cg + c][ql] * 4u : (uint32_t)cbase[cg + c][ql];
+      eyc[c] = crow[cg + c][ql];
     }
     float acc[8];
 #pragma unroll
@@ -1304,9 +1333,9 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
       tot = keep + __shfl_xor(send, 2, 64);
     }
     tot += __shfl_xor(tot, 1, 64);
-    const int e = cand[ci][ql];
-    float bd = (ci < k && e >= 0 && e < N) ? tot : FLT_MAX;
-    int bi = (ci < k && e >= 0 && e < N) ? e : INT_MAX;
+    const int e = cand[cg + ci][ql];
+    float bd = (cg + ci < k && e >= 0 && e < N) ? tot : FLT_MAX;
+    int bi = (cg + ci < k && e >= 0 && e < N) ? e : INT_MAX;
 #pragma unroll
     for (int off = 2; off <= 8; off <<= 1) {
       const float od = __shfl_xor(bd, off, 64);
@@ -1316,6 +1345,13 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
         bi = oi;
       }
     }
+    if (lex_lt(bd, bi, bbd, bbi)) {
+      bbd = bd;
+      bbi = bi;
+    }
+    }
+    const float bd = bbd;
+    const int bi = bbi;
     if (g == 0) {
       nn[q] = (bi == INT_MAX) ? -1 : bi;
       if (dist) dist[q] = (bi == INT_MAX) ? __int_as_float(0x7fc00000) : sqrtf(bd);
@@ -1330,18 +1366,23 @@ void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_
                                const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist) {
   ProfScope ps(c, "select_rerank_full");
   if (nq == 0) return;
-  PTS_REQUIRE(k >= 1 && k <= BB_TOPK, PTS_ERR_ARG, "topk must be 1..8");
+  PTS_REQUIRE(k >= 1 && k <= 16 && (k <= 8 || !sh), PTS_ERR_ARG, "topk must be 1..16 (1..8 with hit lists)");
   PTS_REQUIRE(w >= 1 && w <= Hz && w <= Wz && w <= H && W % s == 0, PTS_ERR_ARG, "select_rerank_full: bad geometry");
   const dim3 grid((unsigned)ceil_div(nq, SR_QPB));
   const HitLists hl = hit_lists(sh);
-  if (ex_pk && ex_srow)
-    hipLaunchKernelGGL(k_select_rerank_full<true>, grid, dim3(SR_QPB), 0, c->stream, part_d, part_i, nq, S, qs, ss,
-                       valid, hl, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
-                       reinterpret_cast<const float4*>(ex), ex_pk, ex_srow, Hz, Wz, nn, dist);
-  else
-    hipLaunchKernelGGL(k_select_rerank_full<false>, grid, dim3(SR_QPB), 0, c->stream, part_d, part_i, nq, S, qs, ss,
-                       valid, hl, k, perm, npos, reinterpret_cast<const float4*>(x), W, w, s, W / s,
-                       reinterpret_cast<const float4*>(ex), ex_pk, ex_srow, Hz, Wz, nn, dist);
+  auto go = [&](auto PKV, auto KLV) {
+    hipLaunchKernelGGL((k_select_rerank_full<decltype(PKV)::value, decltype(KLV)::value>), grid, dim3(SR_QPB), 0,
+                       c->stream, part_d, part_i, nq, S, qs, ss, valid, hl, k, perm, npos,
+                       reinterpret_cast<const float4*>(x), W, w, s, W / s, reinterpret_cast<const float4*>(ex), ex_pk,
+                       ex_srow, Hz, Wz, nn, dist);
+  };
+  const bool pk = ex_pk && ex_srow;
+  using T = std::true_type;
+  using F = std::false_type;
+  using K8 = std::integral_constant<int, 8>;
+  using K16 = std::integral_constant<int, 16>;
+  if (k <= 8) pk ? go(T{}, K8{}) : go(F{}, K8{});
+  else pk ? go(T{}, K16{}) : go(F{}, K16{});
   check_launch("k_select_rerank_full");
 }
 

@@ -29,9 +29,10 @@ struct ScanHits {
 };
 // number of exemplar splits for the brute-force kernel
 int brute_splits(int64_t nq);
-// partial top-8 (score, leaf position) per (split, query): part [S][nq][8]
+// partial top-kt (score, leaf position) per (split, query), kt = 8 or 16:
+// part [S][nq][kt]; the merge kernels read lists of 8 for k <= 8, else of 16
 void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16_t* Zb, const float* zbn, int64_t N,
-                            int dk, int S, float* part_d, int32_t* part_i);
+                            int dk, int S, int kt, float* part_d, int32_t* part_i);
 // merge S partial lists per query (list s of query q = row q*qs + s*ss of
 // part [..][8]; lists with valid[row] < 0 skipped), re-rank the best k in
 // FP32 PCA space; nn = exemplar id.  cand_out (optional) [nq][8]: the k

@@ -85,7 +85,7 @@ def test_brute_bf16_ragged_and_rerank_full(gpu_ctx):
     # fewer candidates: the winner must be the outcome of some top-k that FP32
     # evaluation of the scores can produce (scores within its error bound swap)
     allz = [np.arange(Zp.shape[0])] * Qp.shape[0]
-    for k in (1, 3):
+    for k in (1, 3, 12, 16):
         nnk, _ = gpu_ctx.estep(x, w, s, mode="brute_bf16", topk=k)
         valid = helpers.topk_rerank_validity(Qp, Zp, None, allz, _np(nnk), k)
         assert valid.mean() >= 0.999, (k, valid.mean())
@@ -114,19 +114,23 @@ def test_brute_bf16_energy_gap_ex512_w16(gpu_ctx):
     # output): the energy the method assigns to each iterate against the
     # energy exhaustive full-D search assigns to the same image
     maxg, G_all = {}, {}
-    for rf, res in ((0, 0), (1, 0), (1, 1)):
+    for rf, res, k in ((0, 0, 8), (1, 0, 8), (1, 1, 8), (1, 0, 16)):
         xt = x.clone()
         G = []
         for t in range(10):
-            nn_m, d_m = gpu_ctx.estep(xt, w, s, mode="brute_bf16", rerank_full=rf, residual=res)
+            nn_m, d_m = gpu_ctx.estep(xt, w, s, mode="brute_bf16", rerank_full=rf, residual=res, topk=k)
             _, d_x = gpu_ctx.estep(xt, w, s, mode="exact_full")
             G.append(gpu_ctx.energy(d_m)[0] / gpu_ctx.energy(d_x)[0] - 1.0)
             gpu_ctx.mstep(nn_m, d_m, xt, w, s)
-        G_all[(rf, res)] = G
-        print(f"rerank_full={rf} residual={res}: gated gaps {['%.5f' % g for g in G]}", flush=True)
-    G = G_all[(1, 0)]
-    # BF16 distances + FP32 full-D re-rank of the top-8 (the precision form)
-    assert max(G[1:]) <= 0.005, G
+        G_all[(rf, res, k)] = G
+        print(f"rerank_full={rf} residual={res} topk={k}: gated gaps {['%.5f' % g for g in G]}", flush=True)
+    # BF16 distances + FP32 full-D re-rank of the top-16: within 0.5 % at every
+    # iterate, the patch-copied initial output included (with 8 candidates
+    # the full-D match is ranked below the 8th by the 64 of 1024 PCA
+    # dimensions often enough to cost 0.52 % there)
+    G = G_all[(1, 0, 16)]
+    assert max(G) <= 0.005, G
+    assert max(G_all[(1, 0, 8)][1:]) <= 0.005
     # PCA-space reading: BF16 top-8 + FP32 PCA re-rank against exact FP32
     # search in the same PCA space (the cost of BF16 alone)
     assert gaps["brute_bf16"] <= gaps["exact_pca"] + 0.005 * (1 + gaps["exact_pca"])
@@ -137,9 +141,4 @@ def test_brute_bf16_energy_gap_ex512_w16(gpu_ctx):
     valid = helpers.topk_rerank_validity(Qp[sample], Zp, None, [np.arange(Zp.shape[0])] * sample.size,
                                          _np(nn_b)[sample], 8)
     assert valid.mean() >= 0.999, valid.mean()
-    # the 0.5 % gate at the initial output (patches copied from the exemplar):
-    # BF16 ranks exactly like FP32 in the same PCA space (checked above), so
-    # what the 8 candidates miss there is the full-dimension match that 64 of
-    # 1024 dimensions rank below its 8th: the measured gap is 0.52 %
-    if G[0] > 0.005:
-        pytest.xfail(f"precision form at the initial output: gap {G[0]:.5f} > 0.005 (PCA 64 of 1024 dimensions)")
+
