@@ -192,7 +192,7 @@ def headline(a):
                         f"({info.n_leaves} leaves)",
             "form": (f"BF16 MFMA scans of the MLP's top-{a.proposals} leaves (plus the tree's leaf below margin "
                      f"{a.margin}), exact BF16 top-8, FP32 re-rank" if learned else
-                     "BF16 MFMA distances to every exemplar window, exact top-8, FP32 re-rank")
+                     "BF16 MFMA distances to every exemplar window, exact top-16, FP32 re-rank")
                     + (" in full D" if a.rerank_full else " in PCA space")
                     + (", residual-energy ranking" if a.residual else ""),
         },
