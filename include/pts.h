@@ -213,7 +213,7 @@ typedef struct pts_estep_params {
                       PCA-space distance */
   int scan_slots;  /* LEARNED_BF16: rows the second scan pass may collect per (query, leaf)
                       pair and half-wave before the query is redone by its exact per-query
-                      pass (0 = 16; 0..16).  Results do not depend on it. */
+                      pass (0 = 14; 0..14).  Results do not depend on it. */
 } pts_estep_params;
 
 typedef struct pts_estep_stats {

@@ -84,7 +84,7 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
     const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();
     const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
-    const int hc = p.scan_slots <= 0 ? 16 : p.scan_slots;
+    const int hc = p.scan_slots <= 0 ? 14 : p.scan_slots;
     ScanHits sh;
     int32_t* novf = c->buf<int32_t>("ln_scan_overflow", 1);
     // bound pass over every pair, then the collect pass over the pairs that

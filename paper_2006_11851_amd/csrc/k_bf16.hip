@@ -100,6 +100,27 @@ __device__ __forceinline__ uint4 stage_frag(const BruteSmem<KS>& S, int buf, int
   return S.frag[buf][t * L::TS + kk * L::KKS + (lane >> 5) * L::HS + (lane & 31)];
 }
 
+// A tile's operands from a stage: the lane's row fragments and the row
+// norms that start its accumulator (rows 8 (r / 4) + 4 (lane / 32) + r % 4)
+template <int KS>
+__device__ __forceinline__ void tile_operands(const BruteSmem<KS>& S, int buf, int t, int lane, bf16x8 (&A)[KS],
+                                              floatx16& cz) {
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
+    A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+  }
+  const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
+    cz[4 * g + 0] = z4.x;
+    cz[4 * g + 1] = z4.y;
+    cz[4 * g + 2] = z4.z;
+    cz[4 * g + 3] = z4.w;
+  }
+}
+
 // Loads one stage (rows r0 .. r0+127 of [row_begin, row_end)) from global
 // into registers: each thread owns up to 2 chunks of 16 B plus zn entries.
 template <int KS, int NTH = BB_QPB>
@@ -325,7 +346,14 @@ __device__ __forceinline__ void stage_compute_cls(const BruteSmem<KS>& S, int bu
 // pairs per leaf-scan tile (one block of 8 waves, 64 pairs each; blocks of
 // 4 waves, two per CU, were slower)
 constexpr int LS_QPB = 512;
+constexpr int LS_HC_MAX = 14;  // collect slots per (pair, half-lane): all of them held in LDS
 int leaf_scan_bf16_chunk() { return LS_QPB; }
+// collect slots that fit in LDS beside the stage buffers (at most LS_HC_MAX)
+template <int KS>
+constexpr int ls_hc_cap() {
+  constexpr int avail = (160 * 1024 - (int)sizeof(BruteSmem<KS>) - 256) / (2 * LS_QPB * (int)sizeof(int2));
+  return avail < LS_HC_MAX ? avail : LS_HC_MAX;
+}
 
 // The full-stage form of stage_compute_cls, software pipelined: the products
 // of tile t (two independent chains, one per query tile) are woven with the
@@ -351,27 +379,25 @@ __device__ __forceinline__ void stage_compute_cls_full(const BruteSmem<KS>& S, i
     ct[qt][c] = (m3 < cm[qt][c]) ? tbase : ct[qt][c];
     cm[qt][c] = m3;
   };
+  constexpr int NT = BB_STAGE / 32;
   floatx16 accp[2];
+  // tile t + 1's operands are read from LDS while tile t's products run
+  // (up to 64 dimensions; wider rows have no registers to spare for it)
+  constexpr bool PF = KS <= 4;
+  bf16x8 A[KS];
+  floatx16 cz;
+  if constexpr (PF) tile_operands<KS>(S, buf, 0, lane, A, cz);
 #pragma unroll
-  for (int t = 0; t < BB_STAGE / 32; ++t) {
+  for (int t = 0; t < NT; ++t) {
     __builtin_amdgcn_sched_barrier(0);  // tile by tile
-    bf16x8 A[KS];
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
-      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+    bf16x8 An[KS];
+    floatx16 czn;
+    if constexpr (PF) {
+      if (t + 1 < NT) tile_operands<KS>(S, buf, t + 1, lane, An, czn);
+    } else {
+      tile_operands<KS>(S, buf, t, lane, A, cz);
     }
-    floatx16 cinit;
-    const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
-      cinit[4 * g + 0] = z4.x;
-      cinit[4 * g + 1] = z4.y;
-      cinit[4 * g + 2] = z4.z;
-      cinit[4 * g + 3] = z4.w;
-    }
-    floatx16 accn[2] = {cinit, cinit};
+    floatx16 accn[2] = {cz, cz};
     const int tprev = pos0 + (t - 1) * 32;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
@@ -386,14 +412,17 @@ __device__ __forceinline__ void stage_compute_cls_full(const BruteSmem<KS>& S, i
         }
       }
     }
-    if (t > 0) {
-      __builtin_amdgcn_sched_group_barrier(0x100, 2 * KS, 0);
-      cls_order<KS>(std::make_integer_sequence<int, KS>{});
-    }
+    if (PF ? t + 1 < NT : t > 0) __builtin_amdgcn_sched_group_barrier(0x100, 2 * KS, 0);
+    if (t > 0) cls_order<KS>(std::make_integer_sequence<int, KS>{});
     accp[0] = accn[0];
     accp[1] = accn[1];
+    if (PF && t + 1 < NT) {
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) A[kk] = An[kk];
+      cz = czn;
+    }
   }
-  const int tlast = pos0 + (BB_STAGE / 32 - 1) * 32;
+  const int tlast = pos0 + (NT - 1) * 32;
 #pragma unroll
   for (int qt = 0; qt < 2; ++qt)
 #pragma unroll
@@ -451,7 +480,6 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-constexpr int LS_HC_MAX = 16;  // collect slots per (pair, half-lane)
 
 struct LeafScanOut {
   // pass 1
@@ -498,35 +526,27 @@ __device__ __forceinline__ void top8_from_hits(TopLex<K>& top, const HitLists& L
 }
 
 // Collected rows of a lane for one query tile: slot cnt is the next free
-// one.  Rows found during a stage go to the lane's few LDS slots and are
-// written to their global slots after the stage's row loads have been
-// consumed (flush): a global store issued between a load and its use would
-// make that use wait for the store too (loads and stores share one
-// completion counter), undoing the two-stage prefetch.  Rows beyond the LDS
-// slots in one stage are written at once.
-constexpr int HB_STAGE = 4;  // LDS slots per lane and query tile
+// one.  The rows stay in LDS (slot k of lane-set j at k * 2 LS_QPB + j) until
+// the tile's stages are done, and only then go to their global slots: a
+// global store pending in the stage loop would make every wait for the row
+// loads a full drain (loads and stores share one completion counter and may
+// complete out of order), undoing the two-stage prefetch.
 struct HitLane {
   float tv;    // the query's bound: score
   int tp;      // and position
   int2* dst;   // the (pair, half) slots
-  int cnt, done;
-  int lds;     // first LDS slot of the lane
+  int cnt;
+  int lds;     // the lane-set's first LDS slot
 };
 
 __device__ __forceinline__ void hit_push(HitLane& L, int2* lbuf, int hc, int2 e) {
-  const int i = L.cnt;
-  if (i < hc) {
-    const int k = i - L.done;
-    if (k < HB_STAGE) lbuf[L.lds + k] = e;
-    else L.dst[i] = e;
-  }
-  L.cnt = i + 1;
+  if (L.cnt < hc) lbuf[L.lds + L.cnt * (2 * LS_QPB)] = e;
+  ++L.cnt;
 }
 
-__device__ __forceinline__ void hit_flush(HitLane& L, const int2* lbuf, int hc) {
-  const int e = min(L.cnt, hc), n = min(e - L.done, HB_STAGE);
-  for (int k = 0; k < n; ++k) L.dst[L.done + k] = lbuf[L.lds + k];
-  L.done = e;
+__device__ __forceinline__ void hit_write(const HitLane& L, const int2* lbuf, int hc) {
+  const int n = min(L.cnt, hc);
+  for (int k = 0; k < n; ++k) L.dst[k] = lbuf[L.lds + k * (2 * LS_QPB)];
 }
 
 // rows of a tile (accumulator acc, first row tpos) at or below the query's
@@ -548,50 +568,51 @@ __device__ __forceinline__ void collect_rows(const floatx16& acc, HitLane& L, in
   }
 }
 
-// Pass 2 over one stage, software pipelined: tile t's fragments are read,
-// tile t - 1's rows are collected while they arrive, then tile t's products
-// are issued (read only at step t + 1).  Every stage takes all 4 tiles: rows
-// past the leaf are zero rows with norm FLT_MAX in LDS, so they score
-// FLT_MAX and are never collected (one code path keeps the kernel small).
+// Pass 2 over one stage, software pipelined: tile t + 1's operands are read
+// from LDS (up to 64 dimensions) and tile t's products issued, then tile
+// t - 1's rows are collected while they run.  Every stage takes all 4 tiles: rows past the
+// leaf are zero rows with norm FLT_MAX in LDS, so they score FLT_MAX and are
+// never collected (one code path keeps the kernel small).
 template <int KS>
 __device__ __forceinline__ void stage_collect(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
                                               HitLane& L0, HitLane& L1, int2* lbuf, int hc, int pos0, int lane,
                                               int row_end) {
+  constexpr int NT = BB_STAGE / 32;
   floatx16 accp[2];
   const int hofs = 4 * (lane >> 5);
+  constexpr bool PF = KS <= 4;  // as in the bound pass
+  bf16x8 A[KS];
+  floatx16 cz;
+  if constexpr (PF) tile_operands<KS>(S, buf, 0, lane, A, cz);
 #pragma unroll
-  for (int t = 0; t < BB_STAGE / 32; ++t) {
-    bf16x8 A[KS];
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
-      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+  for (int t = 0; t < NT; ++t) {
+    bf16x8 An[KS];
+    floatx16 czn;
+    if constexpr (PF) {
+      if (t + 1 < NT) tile_operands<KS>(S, buf, t + 1, lane, An, czn);
+    } else {
+      tile_operands<KS>(S, buf, t, lane, A, cz);
     }
-    floatx16 cinit;
-    const float* zr = &S.zn[buf][t * 32 + hofs];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
-      cinit[4 * g + 0] = z4.x;
-      cinit[4 * g + 1] = z4.y;
-      cinit[4 * g + 2] = z4.z;
-      cinit[4 * g + 3] = z4.w;
-    }
-    if (t > 0) {
-      collect_rows(accp[0], L0, lbuf, hc, pos0 + (t - 1) * 32 + hofs);
-      collect_rows(accp[1], L1, lbuf, hc, pos0 + (t - 1) * 32 + hofs);
-    }
-    floatx16 accn[2] = {cinit, cinit};
+    floatx16 accn[2] = {cz, cz};
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
       for (int qt = 0; qt < 2; ++qt)
         accn[qt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], accn[qt], 0, 0, 0);
+    if (t > 0) {
+      collect_rows(accp[0], L0, lbuf, hc, pos0 + (t - 1) * 32 + hofs);
+      collect_rows(accp[1], L1, lbuf, hc, pos0 + (t - 1) * 32 + hofs);
+    }
     accp[0] = accn[0];
     accp[1] = accn[1];
+    if (PF && t + 1 < NT) {
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) A[kk] = An[kk];
+      cz = czn;
+    }
   }
-  collect_rows(accp[0], L0, lbuf, hc, pos0 + (BB_STAGE / 32 - 1) * 32 + hofs);
-  collect_rows(accp[1], L1, lbuf, hc, pos0 + (BB_STAGE / 32 - 1) * 32 + hofs);
+  collect_rows(accp[0], L0, lbuf, hc, pos0 + (NT - 1) * 32 + hofs);
+  collect_rows(accp[1], L1, lbuf, hc, pos0 + (NT - 1) * 32 + hofs);
 }
 
 // One tile = (leaf, LS_QPB pairs of the bucketed order); rows = the leaf's
@@ -645,8 +666,8 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       }
   } else {
     auto init_lane = [&](HitLane& L, int qt) {
-      L.cnt = L.done = 0;
-      L.lds = (tid * 2 + qt) * HB_STAGE;
+      L.cnt = 0;
+      L.lds = tid * 2 + qt;
       if (pr[qt] >= 0) {
         const uint64_t k = o.tau_q[qid[qt]];
         // a bound of FLT_MAX (fewer than 8 rows in all of the query's
@@ -668,9 +689,8 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
     // stages load two ahead, as in the brute-force kernel: step st loads
     // stage st + 2 into the registers it frees, computes on LDS buffer st % 2
     // and stores stage st + 1 (loaded two steps earlier) into the other
-    // buffer.  The two register sets are named, not indexed, and swapped
-    // after each step, so that they stay in registers and the step's code
-    // appears once.
+    // buffer.  The two register sets are named, not indexed, so that they
+    // stay in registers.
     auto step = [&](StageRegs<KS, LS_QPB>& Rcur, StageRegs<KS, LS_QPB>& Rnext, int st,
                     int buf) __attribute__((always_inline)) {
       // unconditional (past the end: the last rows again, never stored), so
@@ -688,19 +708,20 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       }
       if (st + 1 < nstages)
         stage_store<KS, LS_QPB>(Rnext, sm, buf ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
-      if constexpr (PASS == 2) {  // the loaded rows are in LDS now
-        hit_flush(L0, lbuf, o.hc);
-        hit_flush(L1, lbuf, o.hc);
-      }
       lds_barrier();
     };
+    // every load issued so far (the query operands, the first two stages) is
+    // complete before the loop: the wait tracking cannot follow the query
+    // operands around the loop and would otherwise wait for them in every
+    // stage, draining the row loads issued two stages ahead each time
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     stage_store<KS, LS_QPB>(R0, sm, 0, tid, row_begin, row_end);
     lds_barrier();
-    for (int st = 0; st < nstages; ++st) {
-      step(R0, R1, st, st & 1);
-      const StageRegs<KS, LS_QPB> tmp = R0;  // the set just loaded is stored next
-      R0 = R1;
-      R1 = tmp;
+    // two steps per trip, the register sets trading roles, so that no copy
+    // of a set (which would wait for its loads in flight) is needed
+    for (int st = 0; st < nstages; st += 2) {
+      step(R0, R1, st, 0);
+      if (st + 1 < nstages) step(R1, R0, st + 1, 1);
     }
   }
   if constexpr (PASS == 1) {
@@ -736,6 +757,8 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       }
     }
   } else {
+    hit_write(L0, lbuf, o.hc);
+    hit_write(L1, lbuf, o.hc);
     if (pr[0] >= 0) o.hit_cnt[(int64_t)pr[0] * 2 + h] = L0.cnt;
     if (pr[1] >= 0) o.hit_cnt[(int64_t)pr[1] * 2 + h] = L1.cnt;
   }
@@ -755,7 +778,7 @@ __global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __res
                                                         const int32_t* __restrict__ ntiles,
                                                         int32_t* __restrict__ next, LeafScanOut o) {
   __shared__ BruteSmem<KS> sm;
-  __shared__ int2 s_hits[PASS == 2 ? LS_QPB * 2 * HB_STAGE : 1];
+  __shared__ int2 s_hits[PASS == 2 ? LS_QPB * 2 * ls_hc_cap<KS>() : 1];
   __shared__ int s_t;
   const int nt = *ntiles;
   for (;;) {
@@ -814,7 +837,8 @@ __global__ __launch_bounds__(256) void k_hit_overflow(const int32_t* __restrict_
 // products as the tile kernels (the query in all 32 columns, so each half of
 // the wave holds the same 16 rows of a tile: identical scores, the products
 // seeing the same operands in the same order), keeps a sorted top-8 of
-// (score, position) per lane, merges its two halves and writes the 8 into
+// (score, position) per lane over the rows within the query's bound (only
+// those can be among its 8 smallest keys), merges its two halves and writes the 8 into
 // the query's own slots (chunk c at 8 c: the query owns P * 2 * hs >= 8 *
 // FB_CHUNKS slots).  Merge: one thread per query takes the 8 best of the
 // chunk lists and leaves them in the slots of its first collect pair (count
@@ -828,8 +852,9 @@ __global__ __launch_bounds__(256) void k_scan_top8_chunks(const uint16_t* __rest
                                                           const int32_t* __restrict__ leaf_off,
                                                           const int32_t* __restrict__ pair_leaf,
                                                           const int32_t* __restrict__ list,
-                                                          const int32_t* __restrict__ n, int2* __restrict__ hits,
-                                                          int hs) {
+                                                          const int32_t* __restrict__ n,
+                                                          const uint64_t* __restrict__ tau_q,
+                                                          int2* __restrict__ hits, int hs) {
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -838,6 +863,11 @@ __global__ __launch_bounds__(256) void k_scan_top8_chunks(const uint16_t* __rest
   for (int64_t it = gw; it < items; it += nw) {
     const int64_t q = list[it / FB_CHUNKS];
     const int c = (int)(it % FB_CHUNKS);
+    // the query's bound from the first pass: only rows at or below it can be
+    // among its 8 smallest keys, so the rest skip the insertion
+    const uint64_t tk = tau_q[q];
+    const float tv = key_score(tk);
+    const int tp = key_pos(tk);
     bf16x8 B[KS];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
@@ -869,7 +899,8 @@ __global__ __launch_bounds__(256) void k_scan_top8_chunks(const uint16_t* __rest
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int pr = t0 + 8 * (r >> 2) + 4 * h + (r & 3);
-          if (pr < re && lex_lt(acc[r], pr, top.d[7], top.i[7])) top.insert(acc[r], pr);
+          const float v = acc[r];
+          if (pr < re && (v < tv || (v == tv && pr <= tp)) && lex_lt(v, pr, top.d[7], top.i[7])) top.insert(v, pr);
         }
       }
       g0 += nt;
@@ -1025,7 +1056,10 @@ void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P
                                    const float* zbn, int dk, const int32_t* leaf_off, const BucketBufs& b,
                                    int max_tiles, const int32_t* pair_leaf2, int hc, ScanHits* sh,
                                    int32_t* n_overflow) {
-  PTS_REQUIRE(hc >= 0 && hc <= LS_HC_MAX, PTS_ERR_ARG, "collect slots must be 0..16");
+  PTS_REQUIRE(hc >= 0 && hc <= LS_HC_MAX, PTS_ERR_ARG, "collect slots must be 0..14");
+  int cap = 0;  // fewer fit beside the wider stage buffers of 96 and 128 dimensions
+  PTS_KS_SWITCH(dk, cap = ls_hc_cap<KSC>());
+  hc = std::min(hc, cap);
   PTS_REQUIRE(P >= 1 && P <= HL_PMAX, PTS_ERR_ARG, "at most 9 scanned leaves per query");
   // slot stride: hc, but room for the per-query pass's chunk lists too
   const int hs = std::max(hc, (int)ceil_div(8 * FB_CHUNKS, 2 * P));
@@ -1060,7 +1094,7 @@ void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P
   // waves and threads loop over the list (its length is only known on the device)
   PTS_REQUIRE((int64_t)P * 2 * hs >= 8 * FB_CHUNKS, PTS_ERR_ARG, "too few collect slots per query");
   PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_scan_top8_chunks<KSC>, dim3(4 * c->n_cu), dim3(256), 0, c->stream, Qb, P,
-                                       Zb, zbn, leaf_off, pair_leaf2, list, n_overflow, o.hits, hs));
+                                       Zb, zbn, leaf_off, pair_leaf2, list, n_overflow, o.tau_q, o.hits, hs));
   check_launch("k_scan_top8_chunks");
   hipLaunchKernelGGL(k_scan_top8_merge, dim3(64), dim3(256), 0, c->stream, P, pair_leaf2, list, n_overflow, o.hits,
                      o.hit_cnt, hs);

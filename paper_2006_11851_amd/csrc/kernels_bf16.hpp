@@ -49,7 +49,7 @@ int leaf_scan_bf16_chunk();
 // 8th key of each pair bounds the query's 8th key from above (tau); pairs
 // that cannot hold a row within tau get pair_leaf2 = -1, the others their
 // leaf.  Collect (over the pairs bucketed from pair_leaf2): the rows within
-// tau, hc slots per pair and half (0..16); queries with more rows go to a
+// tau, hc slots per pair and half (0..14); queries with more rows go to a
 // per-query pass.  n_overflow: device int32, the number of such queries.
 // sum of the leaf sizes over the pairs with pair_leaf >= 0 (synchronous)
 int64_t count_scan_rows(Ctx* c, const int32_t* pair_leaf, int64_t n, const int32_t* leaf_off);
@@ -60,21 +60,10 @@ void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P
                                    const float* zbn, int dk, const int32_t* leaf_off, const BucketBufs& b,
                                    int max_tiles, const int32_t* pair_leaf2, int hc, ScanHits* sh,
                                    int32_t* n_overflow);
-// merge S partial lists per query (list s of query q = row q*qs + s*ss of
-// part [..][8]; lists with valid[row] < 0 skipped), re-rank the best k in
-// FP32 PCA space; nn = exemplar id.  cand_out (optional) [nq][8]: the k
-// candidates as exemplar ids (-1 beyond k)
-// (sh non-null: the candidates are the 8 smallest keys of the collected rows instead)
-void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
-                             int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const float* Qp, int dp,
-                             const float* Zp, const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out,
-                             int32_t* nn);
-// pairs per tile of the leaf scan (the bucketing chunk)
-int leaf_scan_bf16_chunk();
 // Exact BF16 top-8 of every query over the members of its bucketed leaves
 // (pair_leaf [nq*P], negative = not scanned): pass 1 bounds the 8th key per
 // pair, pass 2 collects the rows within the query's bound (hc slots per
-// pair and half, 0..16), queries with more rows go to a per-query pass.
+// pair and half, 0..14), queries with more rows go to a per-query pass.
 // n_overflow: device int32, the number of such queries.
 void launch_leaf_scan_bf16_exact(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
                                  int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles,
