@@ -136,11 +136,15 @@ def headline(a):
         return ctx.energy(dist[sample.long()].contiguous())[0] / ctx.energy(d_ex)[0] - 1.0
 
     if learned:
-        method = ("bf16_learned", dict(mode="learned_bf16", residual=a.residual, rerank_full=a.rerank_full,
-                                       n_proposals=a.proposals, margin=a.margin))
+        # headline: one BF16 pass whose candidates are the query's 8 smallest
+        # class minima; beside it the exact BF16 top-8 form (two passes)
+        exact_kw = dict(mode="learned_bf16", residual=a.residual, rerank_full=a.rerank_full,
+                        n_proposals=a.proposals, margin=a.margin)
+        method = ("bf16_learned_class", dict(exact_kw, mode="learned_bf16_class"))
+        forms = dict([("plain_fp32_tree", dict(mode="tree")), ("bf16_learned_exact_top8", exact_kw), method])
     else:
         method = ("bf16_brute", dict(mode="brute_bf16", residual=a.residual, rerank_full=a.rerank_full, topk=16))
-    forms = dict([("plain_fp32_tree", dict(mode="tree")), method])
+        forms = dict([("plain_fp32_tree", dict(mode="tree")), method])
     if a.only:
         forms = {k: v for k, v in forms.items() if v["mode"] == a.only}
     res = {}
@@ -152,6 +156,17 @@ def headline(a):
 
     head = res.get(method[0]) or res["plain_fp32_tree"]
     tree = res.get("plain_fp32_tree")
+    if learned and method[0] in res and "bf16_learned_exact_top8" in res:
+        # the class-minimum candidates against the exact top-8 on the initial
+        # output: identical winners and the energy difference
+        nn_c, d_c = ctx.estep(x0, w, s, **method[1])
+        nn_e, d_e = ctx.estep(x0, w, s, **forms["bf16_learned_exact_top8"])
+        setup["class_vs_exact_top8"] = dict(
+            identical_winners=float((nn_c == nn_e).float().mean()),
+            energy_ratio=float(ctx.energy(d_c)[0] / ctx.energy(d_e)[0]))
+        log(f"class candidates vs exact top-8 at x0: identical winners "
+            f"{setup['class_vs_exact_top8']['identical_winners']:.4f}, energy ratio "
+            f"{setup['class_vs_exact_top8']['energy_ratio']:.6f}")
     if learned and tree and method[0] in res:
         saving_ms = tree["ms_per_step"] - head["ms_per_step"]
         setup_ms = 1000.0 * (setup["labels_s"] + setup["training_s"])
@@ -190,8 +205,9 @@ def headline(a):
             "workload": f"{a.workload} finest level: exemplar {wl.ex_size}^2, output {Hout}^2, w={w}, stride={s}, "
                         f"N={info.N}, nq={nq}, PCA {info.d}, k-means tree b{wl.branching} L{wl.depth} "
                         f"({info.n_leaves} leaves)",
-            "form": (f"BF16 MFMA scans of the MLP's top-{a.proposals} leaves (plus the tree's leaf below margin "
-                     f"{a.margin}), exact BF16 top-8, FP32 re-rank" if learned else
+            "form": (f"one BF16 MFMA scan of the MLP's top-{a.proposals} leaves (plus the tree's leaf below margin "
+                     f"{a.margin}), the 8 smallest class minima as candidates (16 classes per leaf: rows i and "
+                     f"i + 16 of each 32-row tile), FP32 re-rank" if learned else
                      "BF16 MFMA distances to every exemplar window, exact top-16, FP32 re-rank")
                     + (" in full D" if a.rerank_full else " in PCA space")
                     + (", residual-energy ranking" if a.residual else ""),
@@ -281,7 +297,7 @@ def roofline(head, info, nq, a, dom, workload=None):
         # redone over its list run it again)
         flops = 2.0 * (K1 * h + h * h + h * (-(-L // 32) * 32)) * nq
         bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
-    elif dom == "leaf_scan_bf16":
+    elif dom in ("leaf_scan_bf16", "leaf_scan_bf16_class"):
         flops = 2.0 * dk * head["scan_rows_per_step"]
         bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
     elif dom == "leaf_scan_bf16_collect":
@@ -354,7 +370,8 @@ def solve_rows(ctx, wl, ex, learned, a):
     levels = [dict(w=wl.w[l], stride=wl.stride[l], iters=wl.iters, pca_dims=wl.pca_dims, branching=wl.branching,
                    depth=wl.depth) for l in range(wl.levels)]
     out = {}
-    modes = [("plain_fp32_tree", "tree")] + ([("bf16_learned", "learned_bf16")] if learned else [])
+    modes = [("plain_fp32_tree", "tree")] + ([("bf16_learned_class", "learned_bf16_class"),
+                                              ("bf16_learned_exact_top8", "learned_bf16")] if learned else [])
     for name, mode in modes:
         torch.cuda.synchronize()
         t0 = time.time()

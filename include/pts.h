@@ -61,6 +61,14 @@ extern "C" {
 #define PTS_MODE_BRUTE_BF16 3   /* PCA, all exemplars, BF16 MFMA distances, top-k, FP32 re-rank */
 #define PTS_MODE_LEARNED 4      /* PCA, MLP proposes leaves, FP32 scan of the proposed leaves */
 #define PTS_MODE_LEARNED_BF16 5 /* as LEARNED, leaves scanned with BF16 MFMA + top-k + FP32 re-rank */
+/* As LEARNED_BF16 but in one BF16 pass whose candidates are not the exact
+ * top-8: the scanned rows of each (query, leaf) are split into 16 classes
+ * (rows i and i + 16 of every 32-row tile of the leaf), each class keeps
+ * its smallest score and the row holding it, and the query's 8 smallest
+ * class minima over its leaves (always including the BF16 minimum) go to
+ * the FP32 re-rank.  A departure from the top-8 definition, for speed: the
+ * second pass and the per-query pass are saved. */
+#define PTS_MODE_LEARNED_BF16_CLASS 6
 
 typedef struct pts_ctx pts_ctx;
 

@@ -15,9 +15,12 @@ bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H
 // the return value above; *scan_overflows (if non-null) receives the device
 // counter of queries the BF16 scan sent to its per-query pass (null if none ran);
 // work (if non-null): [0] = scores of the leaf scan (BF16: its bound pass),
-// [1] = scores of the BF16 collect pass (synchronises)
+// [1] = scores of the BF16 collect pass (synchronises).  class_candidates
+// (with bf16_scan): class-minimum candidates from one pass instead of the
+// exact BF16 top-8
 int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
                        const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist, bool* dist_done,
-                       bool bf16_scan, bool count_fallbacks, int32_t** scan_overflows, int64_t* work);
+                       bool bf16_scan, bool class_candidates, bool count_fallbacks, int32_t** scan_overflows,
+                       int64_t* work);
 
 }  // namespace pts

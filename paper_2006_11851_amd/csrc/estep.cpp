@@ -99,20 +99,22 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       break;
     }
     case PTS_MODE_LEARNED:
-    case PTS_MODE_LEARNED_BF16: {
+    case PTS_MODE_LEARNED_BF16:
+    case PTS_MODE_LEARNED_BF16_CLASS: {
       require_index(c, ix, w);
       PTS_REQUIRE(c->mlp.valid, PTS_ERR_STATE, "learned modes need an MLP (pts_mlp_init / set_weights)");
       PTS_REQUIRE(c->mlp.n_in == ix->d && c->mlp.n_out == ix->tree.n_leaves(), PTS_ERR_STATE,
                   "MLP shape does not match the index (n_in = d, n_out = leaves)");
       float* qp = c->buf<float>("qproj", (size_t)nq * ix->dp);
-      const bool bf = p.mode == PTS_MODE_LEARNED_BF16;
+      const bool bf = p.mode != PTS_MODE_LEARNED;
       PTS_REQUIRE(!bf || ix->has_bf16, PTS_ERR_STATE, "LEARNED_BF16 needs an index built with make_bf16");
       uint16_t* qb = bf ? c->buf<uint16_t>("qbf16", (size_t)nq * ix->dk) : nullptr;
       project_on(c, *ix, x, H, W, p.stride, qp, qb);
       int32_t* novf = nullptr;
       int64_t work[2] = {0, 0};
       st.fallbacks =
-          search_learned(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist, &dist_done, bf, timing, &novf,
+          search_learned(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist, &dist_done, bf,
+                         p.mode == PTS_MODE_LEARNED_BF16_CLASS, timing, &novf,
                          count_work ? work : nullptr);
       st.scan_rows = work[0];
       st.collect_rows = work[1];

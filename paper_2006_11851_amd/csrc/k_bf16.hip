@@ -304,7 +304,9 @@ __global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restr
 // i % 32 == b and b + 16): 8 candidates that always include the minimum.
 // FULL: all 128 rows of the stage are valid (no per-tile exit, so the whole
 // stage is one straight-line block the scheduler can interleave).
-template <int KS, bool FULL>
+// ROW: ct records the row of the minimum's first occurrence (its tile's
+// first row, plus 16 if it is the class's second row of that tile)
+template <int KS, bool FULL, bool ROW = false>
 __device__ __forceinline__ void stage_compute_cls(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
                                                   float (&cm)[2][8], int (&ct)[2][8], int pos0, int lane,
                                                   int nvalid) {
@@ -336,7 +338,8 @@ __device__ __forceinline__ void stage_compute_cls(const BruteSmem<KS>& S, int bu
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const float m3 = __builtin_fminf(cm[qt][c], __builtin_fminf(acc[c], acc[c + 8]));
-        ct[qt][c] = (m3 < cm[qt][c]) ? tbase : ct[qt][c];
+        const int tb = ROW ? (acc[c + 8] < acc[c] ? tbase + 16 : tbase) : tbase;
+        ct[qt][c] = (m3 < cm[qt][c]) ? tb : ct[qt][c];
         cm[qt][c] = m3;
       }
     }
@@ -371,12 +374,13 @@ __device__ __forceinline__ void cls_order(std::integer_sequence<int, KK...>) {
   (cls_order_step<KS, KK>(), ...);
 }
 
-template <int KS>
+template <int KS, bool ROW = false>
 __device__ __forceinline__ void stage_compute_cls_full(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
                                                        float (&cm)[2][8], int (&ct)[2][8], int pos0, int lane) {
   auto update = [&](const floatx16& acc, int qt, int c, int tbase) {
     const float m3 = __builtin_fminf(cm[qt][c], __builtin_fminf(acc[c], acc[c + 8]));
-    ct[qt][c] = (m3 < cm[qt][c]) ? tbase : ct[qt][c];
+    const int tb = ROW ? (acc[c + 8] < acc[c] ? tbase + 16 : tbase) : tbase;  // as in stage_compute_cls
+    ct[qt][c] = (m3 < cm[qt][c]) ? tb : ct[qt][c];
     cm[qt][c] = m3;
   };
   constexpr int NT = BB_STAGE / 32;
@@ -485,6 +489,9 @@ struct LeafScanOut {
   // pass 1
   uint64_t* pair_tau;  // [pairs] upper bound on the pair's 8th smallest key
   float* pair_vmin;    // [pairs] the pair's smallest score
+  // class-minimum candidates (pass 3): [pairs][8] (score, leaf position)
+  float* part_d;
+  int32_t* part_i;
   // pass 2
   const uint64_t* tau_q;  // [nq] smallest bound over the query's pairs
   int2* hits;             // [pairs][2][hs] (score bits, leaf position)
@@ -656,7 +663,7 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
   float cm[2][8];
   int ct[2][8];
   HitLane L0, L1;
-  if constexpr (PASS == 1) {
+  if constexpr (PASS != 2) {
 #pragma unroll
     for (int qt = 0; qt < 2; ++qt)
 #pragma unroll
@@ -699,9 +706,9 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       if (wave_active) {
         const int nvalid = min(BB_STAGE, row_end - row_begin - st * BB_STAGE);
         const int p0 = row_begin + st * BB_STAGE;
-        if constexpr (PASS == 1) {
-          if (nvalid == BB_STAGE) stage_compute_cls_full<KS>(sm, buf, B, cm, ct, p0, lane);
-          else stage_compute_cls<KS, false>(sm, buf, B, cm, ct, p0, lane, nvalid);
+        if constexpr (PASS != 2) {
+          if (nvalid == BB_STAGE) stage_compute_cls_full<KS, PASS == 3>(sm, buf, B, cm, ct, p0, lane);
+          else stage_compute_cls<KS, false, PASS == 3>(sm, buf, B, cm, ct, p0, lane, nvalid);
         } else {
           stage_collect<KS>(sm, buf, B, L0, L1, lbuf, o.hc, p0, lane, row_end);
         }
@@ -754,6 +761,38 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       if (h == 0 && pr[qt] >= 0) {
         o.pair_tau[pr[qt]] = best;
         o.pair_vmin[pr[qt]] = key_score(k[0] < ok[0] ? k[0] : ok[0]);
+      }
+    }
+  } else if constexpr (PASS == 3) {
+    // class-minimum candidates: the pair's 8 smallest class keys (of its 16:
+    // each class's minimum and the row of its first occurrence), sorted
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt) {
+      uint64_t k[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int ra = ct[qt][c] + 8 * (c >> 2) + 4 * h + (c & 3);
+        k[c] = ct[qt][c] < 0 ? score_key(FLT_MAX, INT_MAX) : score_key(cm[qt][c], ra);
+      }
+      sort8(k);
+      // the 8 smallest of two sorted lists: the smaller of k[i] and the
+      // other half's k[7 - i] (a bitonic sequence), sorted again
+      uint64_t m[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const uint64_t o2 = shfl_xor_u64(k[7 - c], 32);
+        m[c] = k[c] < o2 ? k[c] : o2;
+      }
+      sort8(m);
+      if (h == 0 && pr[qt] >= 0) {
+        float* dd = o.part_d + (int64_t)pr[qt] * 8;
+        int32_t* di = o.part_i + (int64_t)pr[qt] * 8;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const bool ok = key_pos(m[c]) != INT_MAX;
+          dd[c] = ok ? key_score(m[c]) : FLT_MAX;
+          di[c] = ok ? key_pos(m[c]) : INT_MAX;
+        }
       }
     }
   } else {
@@ -1050,6 +1089,22 @@ void launch_leaf_scan_bf16_bound(Ctx* c, const uint16_t* Qb, int64_t nq, int P, 
   hipLaunchKernelGGL(k_pair_tau_min, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf, o.pair_tau,
                      o.pair_vmin, nq, P, tau_q, pair_leaf2);
   check_launch("k_pair_tau_min");
+}
+
+void launch_leaf_scan_bf16_class(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
+                                 int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* part_d,
+                                 int32_t* part_i) {
+  LeafScanOut o{};
+  o.part_d = part_d;
+  o.part_i = part_i;
+  if (nq == 0 || max_tiles <= 0) return;
+  ProfScope ps(c, "leaf_scan_bf16_class");
+  int32_t* next = c->buf<int32_t>("ls_next_tile", 1);
+  launch_zero_i32(c, next, 1);
+  const int grid = std::min(max_tiles, c->n_cu);
+  PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_leaf_scan_bf16<KSC, 3>), dim3(grid), dim3(LS_QPB), 0, c->stream, Qb, P, Zb,
+                                       zbn, leaf_off, b.off, b.order, b.tiles, b.ntiles, next, o));
+  check_launch("k_leaf_scan_bf16 (class candidates)");
 }
 
 void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb,

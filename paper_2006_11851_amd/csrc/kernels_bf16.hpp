@@ -68,6 +68,14 @@ void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P
 void launch_leaf_scan_bf16_exact(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
                                  int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles,
                                  const int32_t* pair_leaf, int hc, ScanHits* sh, int32_t* n_overflow);
+// Class-minimum candidates of the learned form's BF16 scan in one pass:
+// per pair (the pair_leaf layout: P per query), its 8 smallest class
+// minima as (score, leaf position) in part_d / part_i [nq * P][8] (16
+// classes: rows i and i + 16 of every 32-row tile, i < 16; each keeps its
+// smallest score and the row of its first occurrence).
+void launch_leaf_scan_bf16_class(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
+                                 int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* part_d,
+                                 int32_t* part_i);
 // merge S partial lists per query as above and re-rank the best k by the
 // full-D FP32 distance gathered from the images x [H][W][4] and ex
 // [Hz][Wz][4] (read from its 8-bit form ex_pk / ex_srow when given: the same

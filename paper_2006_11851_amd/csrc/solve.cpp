@@ -107,7 +107,8 @@ void run_solve(Ctx* c, const pts_solve_params& p, const float* x0, int H0, int W
         ip.depth = lp.depth;
         ip.kmeans_max_iter = p.kmeans_max_iter;
         ip.seed = p.seed;
-        ip.make_bf16 = (mode == PTS_MODE_BRUTE_BF16 || mode == PTS_MODE_LEARNED_BF16) ? 1 : 0;
+        ip.make_bf16 = (mode == PTS_MODE_BRUTE_BF16 || mode == PTS_MODE_LEARNED_BF16 ||
+                        mode == PTS_MODE_LEARNED_BF16_CLASS) ? 1 : 0;
         build_index_on(c, ex, ip, level_index, nullptr);
         ix = &level_index;
       }

@@ -44,6 +44,8 @@ def run_exemplar(ctx, wl, seed: int, iters: int = 10, train_iters: int = 2, extr
     forms = (("learned", dict(mode=mode, margin=margin, n_proposals=n_proposals, rerank_full=1)),
              ("learned_bf16", dict(mode="learned_bf16", margin=margin, n_proposals=n_proposals, rerank_full=1,
                                    residual=residual)),
+             ("learned_bf16_class", dict(mode="learned_bf16_class", margin=margin, n_proposals=n_proposals,
+                                         rerank_full=1, residual=residual)),
              ("tree", dict(mode="tree")))
     for name, kw in forms:
         x = ctx.rgbs_from_u8(init2, 0.5)
@@ -61,7 +63,8 @@ def run_exemplar(ctx, wl, seed: int, iters: int = 10, train_iters: int = 2, extr
         log(f"seed {seed}: pairs {out['pairs']}, loss {losses[0]:.3f} -> {losses[-1]:.3f}, recall {recall:.3f}, "
             f"learned gap max {res['learned']['max_gap']:.4f} last {res['learned']['last_gap']:.4f} "
             f"(fallbacks {res['learned']['fallback_rate']:.3f}); learned BF16 + full-D re-rank gap max "
-            f"{res['learned_bf16']['max_gap']:.4f} last {res['learned_bf16']['last_gap']:.4f}; "
+            f"{res['learned_bf16']['max_gap']:.4f} last {res['learned_bf16']['last_gap']:.4f}; class candidates "
+            f"{res['learned_bf16_class']['max_gap']:.4f} last {res['learned_bf16_class']['last_gap']:.4f}; "
             f"tree gap max {res['tree']['max_gap']:.4f}")
     return out
 

@@ -29,6 +29,7 @@ MODE_TREE = 2
 MODE_BRUTE_BF16 = 3
 MODE_LEARNED = 4
 MODE_LEARNED_BF16 = 5
+MODE_LEARNED_BF16_CLASS = 6
 MODES = {
     "exact_full": MODE_EXACT_FULL,
     "exact_pca": MODE_EXACT_PCA,
@@ -36,6 +37,7 @@ MODES = {
     "brute_bf16": MODE_BRUTE_BF16,
     "learned": MODE_LEARNED,
     "learned_bf16": MODE_LEARNED_BF16,
+    "learned_bf16_class": MODE_LEARNED_BF16_CLASS,
 }
 
 
