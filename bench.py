@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--only", default="", help="run one form only (tree, learned_bf16 or brute_bf16)")
     ap.add_argument("--suite", default="", help="learned_c4: the learned form over the 16 seeded 256^2 exemplars")
     ap.add_argument("--suite-seeds", type=int, default=16)
+    ap.add_argument("--class-topk", type=int, default=12,
+                    help="class-minimum candidates re-ranked in full D by the reported learned form")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB tensor 3 times (the HBM-counter scale for rocprofv3 --pmc) and exit")
     return ap.parse_args()
@@ -140,7 +142,7 @@ def headline(a):
         # class minima; beside it the exact BF16 top-8 form (two passes)
         exact_kw = dict(mode="learned_bf16", residual=a.residual, rerank_full=a.rerank_full,
                         n_proposals=a.proposals, margin=a.margin)
-        method = ("bf16_learned_class", dict(exact_kw, mode="learned_bf16_class"))
+        method = ("bf16_learned_class", dict(exact_kw, mode="learned_bf16_class", topk=a.class_topk))
         forms = dict([("plain_fp32_tree", dict(mode="tree")), ("bf16_learned_exact_top8", exact_kw), method])
     else:
         method = ("bf16_brute", dict(mode="brute_bf16", residual=a.residual, rerank_full=a.rerank_full, topk=16))
@@ -206,8 +208,8 @@ def headline(a):
                         f"N={info.N}, nq={nq}, PCA {info.d}, k-means tree b{wl.branching} L{wl.depth} "
                         f"({info.n_leaves} leaves)",
             "form": (f"one BF16 MFMA scan of the MLP's top-{a.proposals} leaves (plus the tree's leaf below margin "
-                     f"{a.margin}), the 8 smallest class minima as candidates (16 classes per leaf: rows i and "
-                     f"i + 16 of each 32-row tile), FP32 re-rank" if learned else
+                     f"{a.margin}), the {a.class_topk} smallest class minima as candidates (16 classes per leaf: "
+                     f"rows i and i + 16 of each 32-row tile), FP32 re-rank" if learned else
                      "BF16 MFMA distances to every exemplar window, exact top-16, FP32 re-rank")
                     + (" in full D" if a.rerank_full else " in PCA space")
                     + (", residual-energy ranking" if a.residual else ""),
@@ -408,8 +410,9 @@ def learned_suite(a):
     print(json.dumps({
         "suite": "learned_c4", "exemplars": len(rows), "pairs_total": int(sum(r["pairs"] for r in rows)),
         "config": "exemplar 256^2, output 512^2 finest level, w=8, stride 2, PCA 64, tree b32 L2 (1024 leaves), "
-                  f"MLP 64-256-256-1024, top-{a.proposals} leaves, tree leaf added below margin 0.2, exact top-8 "
-                  "re-ranked in full D (FP32 scan: 'learned'; BF16 scans: 'learned_bf16')",
+                  f"MLP 64-256-256-1024, top-{a.proposals} leaves, tree leaf added below margin 0.2, re-ranked in "
+                  "full D: exact top-8 of an FP32 scan ('learned') and of BF16 scans ('learned_bf16'), the 12 "
+                  "smallest class minima of one BF16 pass ('learned_bf16_class')",
         **summary,
         "top_p_train_recall_mean": float(np.mean([r["top4_train_recall"] for r in rows])),
         "seconds": time.time() - t0, "per_exemplar": rows}))

@@ -64,7 +64,7 @@ extern "C" {
 /* As LEARNED_BF16 but in one BF16 pass whose candidates are not the exact
  * top-8: the scanned rows of each (query, leaf) are split into 16 classes
  * (rows i and i + 16 of every 32-row tile of the leaf), each class keeps
- * its smallest score and the row holding it, and the query's 8 smallest
+ * its smallest score and the row holding it, and the query's topk smallest
  * class minima over its leaves (always including the BF16 minimum) go to
  * the FP32 re-rank.  A departure from the top-8 definition, for speed: the
  * second pass and the per-query pass are saved. */
@@ -210,8 +210,8 @@ typedef struct pts_estep_params {
   int mode;        /* PTS_MODE_* */
   int w;           /* neighbourhood width; must equal the index's w for PCA modes */
   int stride;      /* grid stride s (the paper: w / 4) */
-  int topk;        /* BF16 candidates kept for the FP32 re-rank (0 = 8; 1..16 for BRUTE_BF16,
-                      1..8 for the learned forms) */
+  int topk;        /* BF16 candidates kept for the FP32 re-rank (0 = 8; 1..16 for BRUTE_BF16
+                      and LEARNED_BF16_CLASS, 1..8 for the other learned forms) */
   int rerank_full; /* 1: re-rank BF16 candidates by full-D distance; 0: PCA space */
   int n_proposals; /* leaves proposed by the MLP (4; 1..8) */
   float margin;    /* softmax margin p1 - p2 below which the tree is used (0.2) */

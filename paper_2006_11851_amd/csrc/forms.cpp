@@ -80,23 +80,23 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     launch_merge_pairs_f32(c, pair_leaf, pid, pdd, nq, P1, nn);
     if (work) work[0] = count_scan_rows(c, pair_leaf, nq * P1, ix.leaf_off.as<int32_t>());
   } else if (class_candidates) {
-    // one BF16 pass: the query's 8 smallest class minima over its pairs as
-    // candidates, re-ranked as below
+    // one BF16 pass: the query's k smallest class minima over its pairs (16
+    // per pair) as candidates, re-ranked as below
     PTS_REQUIRE(ix.has_bf16 && qb, PTS_ERR_STATE, "LEARNED_BF16_CLASS needs an index built with make_bf16");
     const int k = p.topk <= 0 ? 8 : p.topk;
-    PTS_REQUIRE(k >= 1 && k <= 8, PTS_ERR_ARG, "topk must be 1..8");
+    PTS_REQUIRE(k >= 1 && k <= 16, PTS_ERR_ARG, "topk must be 1..16");
     const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();
-    float* pdd = c->buf<float>("ln_pair_cd", (size_t)nq * P1 * 8);
-    int32_t* pii = c->buf<int32_t>("ln_pair_ci", (size_t)nq * P1 * 8);
+    float* pdd = c->buf<float>("ln_pair_cd16", (size_t)nq * P1 * 16);
+    int32_t* pii = c->buf<int32_t>("ln_pair_ci16", (size_t)nq * P1 * 16);
     launch_leaf_scan_bf16_class(c, qb, nq, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b,
                                 max_tiles, pdd, pii);
     if (p.rerank_full) {
       launch_select_rerank_full(c, pdd, pii, nq, P1, P1, 1, pair_leaf, nullptr, k, ix.perm.as<int32_t>(), ix.N, x, H,
-                                W, ix.w, p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);
+                                W, ix.w, p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist, 16);
       *dist_done = dist != nullptr;
     } else {
       launch_merge_rerank_pca(c, pdd, pii, nq, P1, P1, 1, pair_leaf, nullptr, k, qp, ix.dp, ix.zproj.as<float>(),
-                              p.residual ? ix.zres.as<float>() : nullptr, ix.perm.as<int32_t>(), ix.N, nullptr, nn);
+                              p.residual ? ix.zres.as<float>() : nullptr, ix.perm.as<int32_t>(), ix.N, nullptr, nn, 16);
     }
     if (work) work[0] = count_scan_rows(c, pair_leaf, nq * P1, ix.leaf_off.as<int32_t>());
   } else {

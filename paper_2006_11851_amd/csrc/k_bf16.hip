@@ -764,35 +764,18 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
       }
     }
   } else if constexpr (PASS == 3) {
-    // class-minimum candidates: the pair's 8 smallest class keys (of its 16:
-    // each class's minimum and the row of its first occurrence), sorted
+    // class-minimum candidates: the pair's 16 class minima (each with the row
+    // of its first occurrence), half h's 8 at entries 8 h .. 8 h + 7
 #pragma unroll
     for (int qt = 0; qt < 2; ++qt) {
-      uint64_t k[8];
+      if (pr[qt] < 0) continue;
+      float* dd = o.part_d + (int64_t)pr[qt] * 16 + 8 * h;
+      int32_t* di = o.part_i + (int64_t)pr[qt] * 16 + 8 * h;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const int ra = ct[qt][c] + 8 * (c >> 2) + 4 * h + (c & 3);
-        k[c] = ct[qt][c] < 0 ? score_key(FLT_MAX, INT_MAX) : score_key(cm[qt][c], ra);
-      }
-      sort8(k);
-      // the 8 smallest of two sorted lists: the smaller of k[i] and the
-      // other half's k[7 - i] (a bitonic sequence), sorted again
-      uint64_t m[8];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const uint64_t o2 = shfl_xor_u64(k[7 - c], 32);
-        m[c] = k[c] < o2 ? k[c] : o2;
-      }
-      sort8(m);
-      if (h == 0 && pr[qt] >= 0) {
-        float* dd = o.part_d + (int64_t)pr[qt] * 8;
-        int32_t* di = o.part_i + (int64_t)pr[qt] * 8;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const bool ok = key_pos(m[c]) != INT_MAX;
-          dd[c] = ok ? key_score(m[c]) : FLT_MAX;
-          di[c] = ok ? key_pos(m[c]) : INT_MAX;
-        }
+        const bool ok = ct[qt][c] >= 0;
+        dd[c] = ok ? cm[qt][c] : FLT_MAX;
+        di[c] = ok ? ct[qt][c] + 8 * (c >> 2) + 4 * h + (c & 3) : INT_MAX;
       }
     }
   } else {
@@ -1236,12 +1219,15 @@ __global__ __launch_bounds__(256) void k_merge_rerank_pca(const float* __restric
 void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
                              int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const float* Qp, int dp,
                              const float* Zp, const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out,
-                             int32_t* nn) {
+                             int32_t* nn, int list_len) {
   ProfScope ps(c, "merge_rerank");
   if (nq == 0) return;
   PTS_REQUIRE(k >= 1 && k <= 16 && (k <= 8 || !sh), PTS_ERR_ARG, "topk must be 1..16 (1..8 with hit lists)");
+  PTS_REQUIRE(list_len == 0 || list_len == 8 || list_len == 16, PTS_ERR_ARG, "candidate lists hold 8 or 16");
+  const int kl = list_len ? list_len : (k <= 8 ? 8 : 16);
+  PTS_REQUIRE(k <= kl, PTS_ERR_ARG, "more candidates asked for than the lists hold");
   const HitLists hl = hit_lists(sh);
-  if (k <= 8) {
+  if (kl == 8) {
     PTS_DP_SWITCH(dp, hipLaunchKernelGGL((k_merge_rerank_pca<DPC, 8>), dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
                                          c->stream, part_d, part_i, nq, S, qs, ss, valid, hl, k, Qp, Zp, zres, perm, N,
                                          cand_out, nn));
@@ -1347,6 +1333,7 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     // the candidates in groups of 8 (one group unless 16 are re-ranked)
 #pragma unroll
     for (int cg = 0; cg < KL; cg += 8) {
+    if (cg >= k) break;  // lists longer than the candidates re-ranked
     // 32-bit byte offsets of the windows' origins in the 8-bit form (pixel
     // indices below 2^26): loads from a scalar base plus a 32-bit offset
     uint32_t eb[8];
@@ -1452,10 +1439,13 @@ void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_
                                int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const int32_t* perm,
                                int64_t npos,
                                const float* x, int H, int W, int w, int s, const float* ex, const uint32_t* ex_pk,
-                               const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist) {
+                               const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist, int list_len) {
   ProfScope ps(c, "select_rerank_full");
   if (nq == 0) return;
   PTS_REQUIRE(k >= 1 && k <= 16 && (k <= 8 || !sh), PTS_ERR_ARG, "topk must be 1..16 (1..8 with hit lists)");
+  PTS_REQUIRE(list_len == 0 || list_len == 8 || list_len == 16, PTS_ERR_ARG, "candidate lists hold 8 or 16");
+  const int kl = list_len ? list_len : (k <= 8 ? 8 : 16);
+  PTS_REQUIRE(k <= kl, PTS_ERR_ARG, "more candidates asked for than the lists hold");
   PTS_REQUIRE(w >= 1 && w <= Hz && w <= Wz && w <= H && W % s == 0, PTS_ERR_ARG, "select_rerank_full: bad geometry");
   const dim3 grid((unsigned)ceil_div(nq, SR_QPB));
   const HitLists hl = hit_lists(sh);
@@ -1470,8 +1460,13 @@ void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_
   using F = std::false_type;
   using K8 = std::integral_constant<int, 8>;
   using K16 = std::integral_constant<int, 16>;
-  if (k <= 8) pk ? go(T{}, K8{}) : go(F{}, K8{});
-  else pk ? go(T{}, K16{}) : go(F{}, K16{});
+  if (kl == 8) {
+    if (pk) go(T{}, K8{});
+    else go(F{}, K8{});
+  } else {
+    if (pk) go(T{}, K16{});
+    else go(F{}, K16{});
+  }
   check_launch("k_select_rerank_full");
 }
 

@@ -41,7 +41,7 @@ void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16
 void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
                              int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const float* Qp, int dp,
                              const float* Zp, const float* zres, const int32_t* perm, int64_t N, int32_t* cand_out,
-                             int32_t* nn);
+                             int32_t* nn, int list_len = 0);
 // pairs per tile of the leaf scan (the bucketing chunk)
 int leaf_scan_bf16_chunk();
 // Exact BF16 top-8 of every query over the members of its bucketed leaves
@@ -69,21 +69,22 @@ void launch_leaf_scan_bf16_exact(Ctx* c, const uint16_t* Qb, int64_t nq, int P, 
                                  int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles,
                                  const int32_t* pair_leaf, int hc, ScanHits* sh, int32_t* n_overflow);
 // Class-minimum candidates of the learned form's BF16 scan in one pass:
-// per pair (the pair_leaf layout: P per query), its 8 smallest class
-// minima as (score, leaf position) in part_d / part_i [nq * P][8] (16
-// classes: rows i and i + 16 of every 32-row tile, i < 16; each keeps its
-// smallest score and the row of its first occurrence).
+// per pair (the pair_leaf layout: P per query), its 16 class minima as
+// (score, leaf position) in part_d / part_i [nq * P][16] (classes: rows i
+// and i + 16 of every 32-row tile, i < 16; each keeps its smallest score and
+// the row of its first occurrence; a class with no row: FLT_MAX, INT_MAX).
 void launch_leaf_scan_bf16_class(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
                                  int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles, float* part_d,
                                  int32_t* part_i);
 // merge S partial lists per query as above and re-rank the best k by the
 // full-D FP32 distance gathered from the images x [H][W][4] and ex
 // [Hz][Wz][4] (read from its 8-bit form ex_pk / ex_srow when given: the same
-// values); nn = exemplar id, dist (optional) = its full-D distance
+// values); nn = exemplar id, dist (optional) = its full-D distance.
+// list_len: entries per list (8 or 16; 0: 8 for k <= 8, else 16)
 void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_i, int64_t nq, int S, int64_t qs,
                                int64_t ss, const int32_t* valid, const ScanHits* sh, int k, const int32_t* perm,
                                int64_t npos,
                                const float* x, int H, int W, int w, int s, const float* ex, const uint32_t* ex_pk,
-                               const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist);
+                               const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist, int list_len = 0);
 
 }  // namespace pts

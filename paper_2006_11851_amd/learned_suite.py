@@ -10,7 +10,8 @@ learned search/blend iterations from another initial output and measure,
 at every iterate, the energy gap to exhaustive search on the same image
 (G_t = E(x; nn_method) / E(x; nn_exact) - 1): the learned form with an
 exact FP32 scan of the proposed leaves (top-8 in PCA space, re-ranked in
-full dimension), the same with BF16 scans, and the plain tree.  Each exemplar's network proposes the leaves
+full dimension), the same with BF16 scans, the one-pass BF16 scan whose
+candidates are the query's 12 smallest class minima, and the plain tree.  Each exemplar's network proposes the leaves
 of that exemplar's tree.  Only C-ABI calls are sequenced here.
 """
 from __future__ import annotations
@@ -24,7 +25,7 @@ from . import synth, training
 
 def run_exemplar(ctx, wl, seed: int, iters: int = 10, train_iters: int = 2, extra_inits: int = 6,
                  per_source: int = 16384, epochs: float = 16.0, mode: str = "learned", margin: float = 0.2,
-                 n_proposals: int = 4, residual: int = 0, log=None):
+                 n_proposals: int = 4, residual: int = 0, class_topk: int = 12, log=None):
     w, s = wl.w[-1], wl.stride[-1]
     H = wl.out_size
     ex = wl.exemplar(seed)
@@ -45,7 +46,7 @@ def run_exemplar(ctx, wl, seed: int, iters: int = 10, train_iters: int = 2, extr
              ("learned_bf16", dict(mode="learned_bf16", margin=margin, n_proposals=n_proposals, rerank_full=1,
                                    residual=residual)),
              ("learned_bf16_class", dict(mode="learned_bf16_class", margin=margin, n_proposals=n_proposals,
-                                         rerank_full=1, residual=residual)),
+                                         rerank_full=1, residual=residual, topk=class_topk)),
              ("tree", dict(mode="tree")))
     for name, kw in forms:
         x = ctx.rgbs_from_u8(init2, 0.5)
