@@ -8,9 +8,11 @@ namespace pts {
 
 // nn[q] for projected queries qp [nq][ix.dp] (qb: their bf16(-2 q') [nq][ix.dk]).  When the form re-ranks in full
 // dimension it also writes the winner distance to dist (if non-null) and
-// returns true; otherwise the caller computes it.
+// returns true; otherwise the caller computes it.  *scan_overflows and work
+// as for search_learned below (its exact BF16 scan over the exemplar splits).
 bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
-                       const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist);
+                       const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist,
+                       int32_t** scan_overflows, int64_t* work);
 // returns the number of queries that fell back to the tree; *dist_done as
 // the return value above; *scan_overflows (if non-null) receives the device
 // counter of queries the BF16 scan sent to its per-query pass (null if none ran);

@@ -95,7 +95,17 @@ EstepStats estep_on(Ctx* c, ExView ex, Index* ix, const float* x, int H, int W, 
       float* qp = c->buf<float>("qproj", (size_t)nq * ix->dp);
       uint16_t* qb = c->buf<uint16_t>("qbf16", (size_t)nq * ix->dk);
       project_on(c, *ix, x, H, W, p.stride, qp, qb);
-      dist_done = search_brute_bf16(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist);
+      int32_t* novf = nullptr;
+      int64_t work[2] = {0, 0};
+      dist_done = search_brute_bf16(c, ex, *ix, x, H, W, p, qp, qb, nq, nn, dist, &novf, count_work ? work : nullptr);
+      st.scan_rows = work[0];
+      st.collect_rows = work[1];
+      if (timing && novf) {
+        int32_t h = 0;
+        PTS_HIP(hipMemcpyAsync(&h, novf, 4, hipMemcpyDeviceToHost, c->stream));
+        PTS_HIP(hipStreamSynchronize(c->stream));
+        st.scan_overflows = h;
+      }
       break;
     }
     case PTS_MODE_LEARNED:

@@ -7,23 +7,49 @@
 namespace pts {
 
 bool search_brute_bf16(Ctx* c, ExView ex, const Index& ix, const float* x, int H, int W, const pts_estep_params& p,
-                       const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist) {
+                       const float* qp, const uint16_t* qb, int64_t nq, int32_t* nn, float* dist,
+                       int32_t** scan_overflows, int64_t* work) {
   const int k = p.topk <= 0 ? 8 : p.topk;
   PTS_REQUIRE(k >= 1 && k <= 16, PTS_ERR_ARG, "topk must be 1..16");
-  const int kt = k <= 8 ? 8 : 16;  // list length per (split, query)
-  const int S = brute_splits(nq);
-  float* pd = c->buf<float>("bb_pd", (size_t)S * nq * kt);
-  int32_t* pi = c->buf<int32_t>("bb_pi", (size_t)S * nq * kt);
+  const int kt = k <= 8 ? 8 : 16;  // the exact BF16 top-kt, of which the best k are re-ranked
+  const int64_t N = ix.N;
+  PTS_REQUIRE(N > 0 && N < INT_MAX, PTS_ERR_ARG, "brute: bad N");
+  if (scan_overflows) *scan_overflows = nullptr;
   const float* zbn = p.residual ? ix.zbnorm_res.as<float>() : ix.zbnorm.as<float>();
   const float* zres = p.residual ? ix.zres.as<float>() : nullptr;
-  launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, ix.N, ix.dk, S, kt, pd, pi);
+  // Pass 1, the bound: the exemplar rows (leaf order) in S contiguous splits
+  // of at least 8192 rows, at most 16, every query scanning every split as it
+  // would the leaves proposed to it; the kt-th smallest of a query's class
+  // minima over all splits bounds its kt-th smallest key from above.
+  const int S = (int)std::min<int64_t>(16, std::max<int64_t>(1, N / 8192));
+  int32_t* soff = c->buf<int32_t>("bb_split_off", (size_t)S + 1);
+  launch_split_offsets(c, soff, S, N);
+  const int64_t npairs = nq * S;
+  int32_t* pair_leaf = c->buf<int32_t>("bb_pair_leaf", (size_t)std::max<int64_t>(1, npairs));
+  int32_t* pair_leaf2 = c->buf<int32_t>("bb_pair_leaf2", (size_t)std::max<int64_t>(1, npairs));
+  launch_fill_splits(c, pair_leaf, npairs, S);
+  const int chunk = leaf_scan_bf16_chunk();
+  int max_tiles = 0;
+  BucketBufs b = bucket_buffers(c, npairs, S, chunk, &max_tiles, "bbk");
+  launch_bucket(c, pair_leaf, npairs, S, chunk, b);
+  launch_leaf_scan_bf16_bound(c, qb, nq, S, ix.zbf.as<uint16_t>(), zbn, ix.dk, soff, b, max_tiles, pair_leaf,
+                              pair_leaf2, kt);
+  const uint64_t* tau = c->buf<uint64_t>("ls_tau_q", (size_t)std::max<int64_t>(1, nq));
+  if (work) work[0] = count_scan_rows(c, pair_leaf, npairs, soff);
+  // Pass 2: every (query, exemplar) score again, only those within the bound
+  // entering each lane's sorted top-kt (rare once the bound is known)
+  const int S2 = brute_splits(nq);
+  float* pd = c->buf<float>("bb_pd", (size_t)S2 * nq * kt);
+  int32_t* pi = c->buf<int32_t>("bb_pi", (size_t)S2 * nq * kt);
+  launch_brute_bf16_topk(c, qb, nq, ix.zbf.as<uint16_t>(), zbn, N, ix.dk, S2, kt, tau, pd, pi);
+  if (work) work[1] = work[0];
   if (p.rerank_full) {
-    launch_select_rerank_full(c, pd, pi, nq, S, 1, nq, nullptr, nullptr, k, ix.perm.as<int32_t>(), ix.N, x, H, W, ix.w,
+    launch_select_rerank_full(c, pd, pi, nq, S2, 1, nq, nullptr, nullptr, k, ix.perm.as<int32_t>(), N, x, H, W, ix.w,
                               p.stride, ex.img, ex.pk, ex.srow, ex.Hz, ex.Wz, nn, dist);
     return dist != nullptr;
   }
-  launch_merge_rerank_pca(c, pd, pi, nq, S, 1, nq, nullptr, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
-                          ix.perm.as<int32_t>(), ix.N, nullptr, nn);
+  launch_merge_rerank_pca(c, pd, pi, nq, S2, 1, nq, nullptr, nullptr, k, qp, ix.dp, ix.zproj.as<float>(), zres,
+                          ix.perm.as<int32_t>(), N, nullptr, nn);
   return false;
 }
 
@@ -112,13 +138,13 @@ int64_t search_learned(Ctx* c, ExView ex, const Index& ix, const float* x, int H
     // can hold a row within the query's bound (bucketed again)
     int32_t* pair_leaf2 = c->buf<int32_t>("ln_pair_leaf2", (size_t)nq * P1);
     launch_leaf_scan_bf16_bound(c, qb, nq, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b,
-                                max_tiles, pair_leaf, pair_leaf2);
+                                max_tiles, pair_leaf, pair_leaf2, 8);
     int max_tiles2 = 0;
     BucketBufs b2 = bucket_buffers(c, nq * P1, L, chunk, &max_tiles2, "bk2");
     b2.tile_order = ix.leaf_by_rows.as<int32_t>();
     launch_bucket(c, pair_leaf2, nq * P1, L, chunk, b2);
     launch_leaf_scan_bf16_collect(c, qb, nq, P1, ix.zbf.as<uint16_t>(), zbn, ix.dk, ix.leaf_off.as<int32_t>(), b2,
-                                  max_tiles2, pair_leaf2, hc, &sh, novf);
+                                  max_tiles2, pair_leaf2, hc, &sh, novf, 8);
     if (work) {
       work[0] = count_scan_rows(c, pair_leaf, nq * P1, ix.leaf_off.as<int32_t>());
       work[1] = count_scan_rows(c, pair_leaf2, nq * P1, ix.leaf_off.as<int32_t>());

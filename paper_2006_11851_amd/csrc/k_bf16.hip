@@ -171,137 +171,14 @@ __device__ __forceinline__ void stage_store(const StageRegs<KS, NTH>& R, BruteSm
   if (tid < BB_STAGE) S.zn[buf][tid] = (r0 + tid < row_end) ? R.zn : FLT_MAX;
 }
 
-// One wave: 64 queries (two B tiles) against the staged 128 rows.
-template <int KS, int KT>
-__device__ __forceinline__ void stage_compute(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
-                                              TopK<KT> (&top)[2], int64_t pos0, int lane, int nvalid) {
-#pragma unroll
-  for (int t = 0; t < BB_STAGE / 32; ++t) {
-    if (t * 32 >= nvalid) break;  // rows past the range: padding only
-    bf16x8 A[KS];
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
-      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
-    }
-    floatx16 cinit;
-    const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
-      cinit[4 * g + 0] = z4.x;
-      cinit[4 * g + 1] = z4.y;
-      cinit[4 * g + 2] = z4.z;
-      cinit[4 * g + 3] = z4.w;
-    }
-    const int64_t tpos = pos0 + t * 32 + 4 * (lane >> 5);
-#pragma unroll
-    for (int qt = 0; qt < 2; ++qt) {
-      floatx16 acc = cinit;
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc, 0, 0, 0);
-      float m = acc[0];
-#pragma unroll
-      for (int r = 1; r < 16; ++r) m = fminf(m, acc[r]);
-      if (__any(m < top[qt].d[KT - 1])) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float v = acc[r];
-          if (v < top[qt].d[KT - 1]) top[qt].insert(v, (int)(tpos + 8 * (r >> 2) + (r & 3)));
-        }
-      }
-    }
-  }
-}
-
-template <int KS, int KT>
-__global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restrict__ Qb, int64_t nq,
-                                                         const uint16_t* __restrict__ Zb,
-                                                         const float* __restrict__ zbn, int64_t N, int S,
-                                                         int64_t rows_per_split, float* __restrict__ part_d,
-                                                         int32_t* __restrict__ part_i) {
-  __shared__ BruteSmem<KS> sm;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int split = blockIdx.x % S;
-  const int64_t qb = blockIdx.x / S;
-  const int64_t row_begin = (int64_t)split * rows_per_split;
-  const int64_t row_end = min(N, row_begin + rows_per_split);
-  // query B fragments: lane holds K = 16 kk + 8 (lane / 32) .. + 7 of query lane % 32
-  bf16x8 B[2][KS];
-#pragma unroll
-  for (int qt = 0; qt < 2; ++qt) {
-    const int64_t q = qb * BB_QPB + wave * 64 + qt * 32 + (lane & 31);
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      uint4 u = make_uint4(0, 0, 0, 0);
-      if (q < nq) u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + (lane >> 5)];
-      B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
-    }
-  }
-  TopK<KT> top[2];
-  top[0].init();
-  top[1].init();
-  if (row_begin < row_end) {
-    const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
-    // stages load two ahead (two register sets): stage st + 2 is issued at
-    // step st and stored at step st + 1
-    StageRegs<KS> R[2];
-    stage_load<KS>(R[0], Zb, zbn, row_begin, row_end, tid);
-    stage_load<KS>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
-    stage_store<KS>(R[0], sm, 0, tid, row_begin, row_end);
-    lds_barrier();
-    for (int s0 = 0; s0 < nstages; s0 += 2) {
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int st = s0 + u;
-        if (st >= nstages) break;
-        // unconditional (past the end: the last rows again, never stored), so
-        // the wait before the store covers only the older stage
-        stage_load<KS>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
-        stage_compute<KS, KT>(sm, u, B, top, row_begin + (int64_t)st * BB_STAGE, lane,
-                          (int)min((int64_t)BB_STAGE, row_end - row_begin - (int64_t)st * BB_STAGE));
-        if (st + 1 < nstages)
-          stage_store<KS>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
-        lds_barrier();
-      }
-    }
-  }
-  // merge the two lanes that share a query: the k smallest of two sorted
-  // lists (in bitonic order; the merge kernels take them in any order)
-#pragma unroll
-  for (int qt = 0; qt < 2; ++qt) {
-    float od[KT];
-    int oi[KT];
-#pragma unroll
-    for (int t = 0; t < KT; ++t) {
-      od[t] = __shfl_xor(top[qt].d[t], 32, 64);
-      oi[t] = __shfl_xor(top[qt].i[t], 32, 64);
-    }
-    const int64_t q = qb * BB_QPB + wave * 64 + qt * 32 + (lane & 31);
-    if (lane < 32 && q < nq) {
-      float* pd = part_d + ((int64_t)split * nq + q) * KT;
-      int32_t* pi = part_i + ((int64_t)split * nq + q) * KT;
-#pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        const float a = top[qt].d[t], b = od[KT - 1 - t];
-        const int ia = top[qt].i[t], ib = oi[KT - 1 - t];
-        const bool take_a = a < b || (a == b && ia < ib);
-        pd[t] = take_a ? a : b;
-        pi[t] = take_a ? ia : ib;
-      }
-    }
-  }
-}
-
-// Class-minimum candidate rule for scans where most rows are near the
-// query (a leaf's members): a sorted per-lane top-k would insert on a large
-// share of rows, and under SIMT every value slot would pay for it.  Instead
-// each lane keeps, for each of its 8 classes (value slots r and r + 8 of the
-// 32x32 output, i.e. scan rows i with i % 16 fixed), the minimum score over
-// the scan and the 32-row tile holding it: v_min3 + compare + select per
-// class and tile.  The 16 classes of a query (two half-lanes) are ranked by
-// their minima and the best 4 contribute both rows of their tile (rows
-// i % 32 == b and b + 16): 8 candidates that always include the minimum.
+// Class minima of a scan: a sorted per-lane top-k would insert on a large
+// share of rows (and under SIMT every value slot would pay for it), so each
+// lane keeps instead, for each of its 8 classes (value slots r and r + 8 of
+// the 32x32 output, i.e. rows i and i + 16 of every 32-row tile, i < 16 fixed
+// per class and half-wave), the minimum score over the scan and the 32-row
+// tile holding it: v_min3 + compare + select per class and tile.  The bound
+// pass takes the K-th smallest class minimum of a query as its bound; the
+// class-candidate pass hands the class minima themselves to the re-rank.
 // FULL: all 128 rows of the stage are valid (no per-tile exit, so the whole
 // stage is one straight-line block the scheduler can interleave).
 // ROW: ct records the row of the minimum's first occurrence (its tile's
@@ -469,6 +346,141 @@ __device__ __forceinline__ void cmp_swap(uint64_t& a, uint64_t& b) {
   b = s ? a : b;
   a = lo;
 }
+
+// One wave: 64 queries (two B tiles) against the staged 128 rows.
+template <int KS, int KT>
+__device__ __forceinline__ void stage_compute(const BruteSmem<KS>& S, int buf, const bf16x8 (&B)[2][KS],
+                                              TopK<KT> (&top)[2], const float (&tv)[2], int64_t pos0, int lane,
+                                              int nvalid) {
+#pragma unroll
+  for (int t = 0; t < BB_STAGE / 32; ++t) {
+    if (t * 32 >= nvalid) break;  // rows past the range: padding only
+    bf16x8 A[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const uint4 u = stage_frag<KS>(S, buf, t, kk, lane);
+      A[kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+    floatx16 cinit;
+    const float* zr = &S.zn[buf][t * 32 + 4 * (lane >> 5)];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 z4 = *reinterpret_cast<const float4*>(zr + 8 * g);
+      cinit[4 * g + 0] = z4.x;
+      cinit[4 * g + 1] = z4.y;
+      cinit[4 * g + 2] = z4.z;
+      cinit[4 * g + 3] = z4.w;
+    }
+    const int64_t tpos = pos0 + t * 32 + 4 * (lane >> 5);
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt) {
+      floatx16 acc = cinit;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kk], B[qt][kk], acc, 0, 0, 0);
+      float m = acc[0];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) m = fminf(m, acc[r]);
+      // only scores within the query's bound can be among its KT smallest
+      const float lim = fminf(top[qt].d[KT - 1], tv[qt]);
+      if (__any(m < top[qt].d[KT - 1] && m <= tv[qt])) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float v = acc[r];
+          if (v < top[qt].d[KT - 1] && v <= lim) top[qt].insert(v, (int)(tpos + 8 * (r >> 2) + (r & 3)));
+        }
+      }
+    }
+  }
+}
+
+template <int KS, int KT>
+__global__ __launch_bounds__(512) void k_brute_bf16_topk(const uint16_t* __restrict__ Qb, int64_t nq,
+                                                         const uint16_t* __restrict__ Zb,
+                                                         const float* __restrict__ zbn, int64_t N, int S,
+                                                         int64_t rows_per_split,
+                                                         const uint64_t* __restrict__ tau_q,
+                                                         float* __restrict__ part_d,
+                                                         int32_t* __restrict__ part_i) {
+  __shared__ BruteSmem<KS> sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int split = blockIdx.x % S;
+  const int64_t qb = blockIdx.x / S;
+  const int64_t row_begin = (int64_t)split * rows_per_split;
+  const int64_t row_end = min(N, row_begin + rows_per_split);
+  // query B fragments: lane holds K = 16 kk + 8 (lane / 32) .. + 7 of query lane % 32
+  bf16x8 B[2][KS];
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt) {
+    const int64_t q = qb * BB_QPB + wave * 64 + qt * 32 + (lane & 31);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      uint4 u = make_uint4(0, 0, 0, 0);
+      if (q < nq) u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + (lane >> 5)];
+      B[qt][kk] = *reinterpret_cast<const bf16x8*>(&u);
+    }
+  }
+  TopK<KT> top[2];
+  top[0].init();
+  top[1].init();
+  // the query's bound (its KT-th smallest key is at most it); none: no filter
+  float tv[2];
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt) {
+    const int64_t q = qb * BB_QPB + wave * 64 + qt * 32 + (lane & 31);
+    tv[qt] = (tau_q && q < nq) ? key_score(tau_q[q]) : INFINITY;
+  }
+  if (row_begin < row_end) {
+    const int nstages = (int)ceil_div(row_end - row_begin, BB_STAGE);
+    // stages load two ahead (two register sets): stage st + 2 is issued at
+    // step st and stored at step st + 1
+    StageRegs<KS> R[2];
+    stage_load<KS>(R[0], Zb, zbn, row_begin, row_end, tid);
+    stage_load<KS>(R[1], Zb, zbn, row_begin + (int64_t)min(1, nstages - 1) * BB_STAGE, row_end, tid);
+    stage_store<KS>(R[0], sm, 0, tid, row_begin, row_end);
+    lds_barrier();
+    for (int s0 = 0; s0 < nstages; s0 += 2) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int st = s0 + u;
+        if (st >= nstages) break;
+        // unconditional (past the end: the last rows again, never stored), so
+        // the wait before the store covers only the older stage
+        stage_load<KS>(R[u], Zb, zbn, row_begin + (int64_t)min(st + 2, nstages - 1) * BB_STAGE, row_end, tid);
+        stage_compute<KS, KT>(sm, u, B, top, tv, row_begin + (int64_t)st * BB_STAGE, lane,
+                          (int)min((int64_t)BB_STAGE, row_end - row_begin - (int64_t)st * BB_STAGE));
+        if (st + 1 < nstages)
+          stage_store<KS>(R[u ^ 1], sm, u ^ 1, tid, row_begin + (int64_t)(st + 1) * BB_STAGE, row_end);
+        lds_barrier();
+      }
+    }
+  }
+  // merge the two lanes that share a query: the k smallest of two sorted
+  // lists (in bitonic order; the merge kernels take them in any order)
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt) {
+    float od[KT];
+    int oi[KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      od[t] = __shfl_xor(top[qt].d[t], 32, 64);
+      oi[t] = __shfl_xor(top[qt].i[t], 32, 64);
+    }
+    const int64_t q = qb * BB_QPB + wave * 64 + qt * 32 + (lane & 31);
+    if (lane < 32 && q < nq) {
+      float* pd = part_d + ((int64_t)split * nq + q) * KT;
+      int32_t* pi = part_i + ((int64_t)split * nq + q) * KT;
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const float a = top[qt].d[t], b = od[KT - 1 - t];
+        const int ia = top[qt].i[t], ib = oi[KT - 1 - t];
+        const bool take_a = a < b || (a == b && ia < ib);
+        pd[t] = take_a ? a : b;
+        pi[t] = take_a ? ia : ib;
+      }
+    }
+  }
+}
+
 // the 19-comparator sorting network for 8 keys (ascending)
 __device__ __forceinline__ void sort8(uint64_t (&k)[8]) {
   cmp_swap(k[0], k[2]); cmp_swap(k[1], k[3]); cmp_swap(k[4], k[6]); cmp_swap(k[5], k[7]);
@@ -487,8 +499,7 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
 
 struct LeafScanOut {
   // pass 1
-  uint64_t* pair_tau;  // [pairs] upper bound on the pair's 8th smallest key
-  float* pair_vmin;    // [pairs] the pair's smallest score
+  uint64_t* pair_keys;  // [pairs][16] the pair's class keys (two sorted runs of 8)
   // class-minimum candidates (pass 3): [pairs][8] (score, leaf position)
   float* part_d;
   int32_t* part_i;
@@ -497,7 +508,7 @@ struct LeafScanOut {
   int2* hits;             // [pairs][2][hs] (score bits, leaf position)
   int32_t* hit_cnt;       // [pairs][2] rows collected (may exceed hc: overflow)
   int hc;                 // slots the pass may fill per (pair, half), <= hs
-  int hs;                 // slot stride (the per-query pass needs P * 2 * hs >= 8 * FB_CHUNKS)
+  int hs;                 // slot stride (the per-query pass needs P * 2 * hs >= K * FB_CHUNKS)
 };
 
 // The collected rows of a query, as the re-rank kernels read them.
@@ -510,7 +521,7 @@ struct HitLists {
 
 // top <- the 8 smallest (score, position) keys among the query's collected
 // rows (the pair leaves and counts are loaded together, then the rows)
-constexpr int HL_PMAX = 9;  // pairs per query: up to 8 proposals + the tree's leaf
+constexpr int HL_PMAX = 16;  // pairs per query: up to 8 proposals + the tree's leaf, or 16 exemplar splits
 template <int K>
 __device__ __forceinline__ void top8_from_hits(TopLex<K>& top, const HitLists& L, int64_t q) {
   int n[2 * HL_PMAX];
@@ -693,7 +704,7 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
     init_lane(L1, 1);
   }
   if (row_begin < row_end) {
-    // stages load two ahead, as in the brute-force kernel: step st loads
+    // stages load two ahead: step st loads
     // stage st + 2 into the registers it frees, computes on LDS buffer st % 2
     // and stores stage st + 1 (loaded two steps earlier) into the other
     // buffer.  The two register sets are named, not indexed, so that they
@@ -733,9 +744,11 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
   }
   if constexpr (PASS == 1) {
     // rows of class c in half h of a tile: i = 8 (c / 4) + 4 h + (c % 4) and
-    // i + 16; a class's key takes the later of the two rows of its tile (an
-    // upper bound on the position of its minimum) unless that row is past
-    // the leaf.  The pair's bound: the 8th smallest of its 16 class keys.
+    // i + 16; a class's key takes the later of the two rows of its recorded
+    // tile (an upper bound on the position of its minimum) unless that row
+    // is past the leaf.  Each half writes its 8 keys, sorted; the classes are
+    // disjoint, so the k-th smallest of a query's class keys (over all its
+    // pairs) bounds its k-th smallest key from above.
 #pragma unroll
     for (int qt = 0; qt < 2; ++qt) {
       uint64_t k[8];
@@ -746,21 +759,10 @@ __device__ __forceinline__ void leaf_scan_tile(int t, BruteSmem<KS>& sm, const u
         k[c] = ct[qt][c] < 0 ? score_key(FLT_MAX, INT_MAX) : score_key(cm[qt][c], rk);
       }
       sort8(k);
-      uint64_t ok[8];
+      if (pr[qt] >= 0) {
+        uint64_t* dk = o.pair_keys + (int64_t)pr[qt] * 16 + 8 * h;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) ok[c] = shfl_xor_u64(k[c], 32);
-      // the 8th smallest of two sorted lists: min over splits of the larger ends
-      uint64_t best = ~0ull;
-#pragma unroll
-      for (int i = 0; i <= 8; ++i) {
-        const uint64_t a = i > 0 ? k[i - 1] : 0ull;
-        const uint64_t b = i < 8 ? ok[7 - i] : 0ull;
-        const uint64_t m = a > b ? a : b;
-        best = m < best ? m : best;
-      }
-      if (h == 0 && pr[qt] >= 0) {
-        o.pair_tau[pr[qt]] = best;
-        o.pair_vmin[pr[qt]] = key_score(k[0] < ok[0] ? k[0] : ok[0]);
+        for (int c = 0; c < 8; ++c) dk[c] = k[c];
       }
     }
   } else if constexpr (PASS == 3) {
@@ -813,28 +815,53 @@ __global__ __launch_bounds__(LS_QPB) void k_leaf_scan_bf16(const uint16_t* __res
   }
 }
 
-// tau[q] = the smallest pass-1 bound over the query's scanned pairs; a pair
-// whose smallest score exceeds the bound's score holds no row within it and
-// is left out of the collect pass (pair_leaf2 = -1), the others keep their leaf
-__global__ __launch_bounds__(256) void k_pair_tau_min(const int32_t* __restrict__ pair_leaf,
-                                                      const uint64_t* __restrict__ pair_tau,
-                                                      const float* __restrict__ pair_vmin, int64_t nq, int P,
-                                                      uint64_t* __restrict__ tau, int32_t* __restrict__ pair_leaf2) {
+// tau[q] = the K-th smallest class key over the query's scanned pairs (an
+// upper bound on its K-th smallest key: the classes hold disjoint rows); a
+// pair whose smallest score exceeds the bound's score holds no row within it
+// and is left out of the collect pass (pair_leaf2 = -1), the others keep
+// their leaf.  Each pair's keys come as two sorted runs of 8, so a run is
+// left as soon as one of its keys cannot enter the K smallest.
+template <int K>
+__global__ __launch_bounds__(256) void k_pair_tau_pool(const int32_t* __restrict__ pair_leaf,
+                                                       const uint64_t* __restrict__ pair_keys, int64_t nq, int P,
+                                                       uint64_t* __restrict__ tau, int32_t* __restrict__ pair_leaf2) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  uint64_t b = ~0ull;
+  // (an empty class's key, FLT_MAX: with fewer than K rows in all the
+  // query's leaves every row is within the bound)
+  uint64_t top[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) top[t] = score_key(FLT_MAX, INT_MAX);
   for (int j = 0; j < P; ++j) {
     const int64_t p = q * P + j;
     if (pair_leaf[p] < 0) continue;
-    const uint64_t v = pair_tau[p];
-    b = v < b ? v : b;
+    for (int run = 0; run < 2; ++run) {
+      const uint64_t* kp = pair_keys + p * 16 + 8 * run;
+      for (int c = 0; c < 8; ++c) {
+        uint64_t v = kp[c];
+        if (v >= top[K - 1]) break;  // the run is sorted: nothing later enters
+        // insertion into the sorted list
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const uint64_t lo = v < top[t] ? v : top[t];
+          v = v < top[t] ? top[t] : v;
+          top[t] = lo;
+        }
+      }
+    }
   }
+  const uint64_t b = top[K - 1];
   tau[q] = b;
   const float bv = key_score(b);
   for (int j = 0; j < P; ++j) {
     const int64_t p = q * P + j;
     const int l = pair_leaf[p];
-    pair_leaf2[p] = (l >= 0 && pair_vmin[p] <= bv) ? l : -1;
+    bool keep = false;
+    if (l >= 0) {
+      const uint64_t m0 = pair_keys[p * 16], m1 = pair_keys[p * 16 + 8];
+      keep = key_score(m0 < m1 ? m0 : m1) <= bv;
+    }
+    pair_leaf2[p] = keep ? l : -1;
   }
 }
 
@@ -853,22 +880,22 @@ __global__ __launch_bounds__(256) void k_hit_overflow(const int32_t* __restrict_
   if (over) list[atomicAdd(n, 1)] = (int32_t)q;
 }
 
-// The per-query exact top-8 for the overflowed queries, in two kernels.
+// The per-query exact top-K (K = 8 or 16) for the overflowed queries, in two kernels.
 // Chunks: the query's 32-row tiles (its collect pairs' leaves, pair after
 // pair) are dealt to FB_CHUNKS waves in turn; each wave runs the same matrix
 // products as the tile kernels (the query in all 32 columns, so each half of
 // the wave holds the same 16 rows of a tile: identical scores, the products
-// seeing the same operands in the same order), keeps a sorted top-8 of
+// seeing the same operands in the same order), keeps a sorted top-K of
 // (score, position) per lane over the rows within the query's bound (only
-// those can be among its 8 smallest keys), merges its two halves and writes the 8 into
-// the query's own slots (chunk c at 8 c: the query owns P * 2 * hs >= 8 *
-// FB_CHUNKS slots).  Merge: one thread per query takes the 8 best of the
-// chunk lists and leaves them in the slots of its first collect pair (count
-// 8, the other counts 0).  Waves and threads loop over the list, whose length
+// those can be among its K smallest keys), merges its two halves and writes
+// the K into the query's own slots (chunk c at K c: the query owns P * 2 * hs
+// >= K * FB_CHUNKS slots).  Merge: one thread per query takes the K best of
+// the chunk lists and leaves them in the slots of its first collect pair
+// (count K, contiguous from there; the other counts 0).  Waves and threads loop over the list, whose length
 // is read on the device.
 constexpr int FB_CHUNKS = 16;
-template <int KS>
-__global__ __launch_bounds__(256) void k_scan_top8_chunks(const uint16_t* __restrict__ Qb, int P,
+template <int KS, int K>
+__global__ __launch_bounds__(256) void k_scan_topk_chunks(const uint16_t* __restrict__ Qb, int P,
                                                           const uint16_t* __restrict__ Zb,
                                                           const float* __restrict__ zbn,
                                                           const int32_t* __restrict__ leaf_off,
@@ -896,7 +923,7 @@ __global__ __launch_bounds__(256) void k_scan_top8_chunks(const uint16_t* __rest
       const uint4 u = reinterpret_cast<const uint4*>(Qb + q * (KS * 16))[2 * kk + h];
       B[kk] = *reinterpret_cast<const bf16x8*>(&u);
     }
-    Top8Lex top;
+    TopLex<K> top;
     top.init();
     int g0 = 0;  // tiles of the earlier pairs
     for (int j = 0; j < P; ++j) {
@@ -922,30 +949,32 @@ __global__ __launch_bounds__(256) void k_scan_top8_chunks(const uint16_t* __rest
         for (int r = 0; r < 16; ++r) {
           const int pr = t0 + 8 * (r >> 2) + 4 * h + (r & 3);
           const float v = acc[r];
-          if (pr < re && (v < tv || (v == tv && pr <= tp)) && lex_lt(v, pr, top.d[7], top.i[7])) top.insert(v, pr);
+          if (pr < re && (v < tv || (v == tv && pr <= tp)) && lex_lt(v, pr, top.d[K - 1], top.i[K - 1]))
+            top.insert(v, pr);
         }
       }
       g0 += nt;
     }
-    float od[8];
-    int oi[8];
+    float od[K];
+    int oi[K];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < K; ++t) {
       od[t] = __shfl_xor(top.d[t], 32, 64);
       oi[t] = __shfl_xor(top.i[t], 32, 64);
     }
     if (lane == 0) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (lex_lt(od[t], oi[t], top.d[7], top.i[7])) top.insert(od[t], oi[t]);
-      int2* dst = hits + (q * P) * 2 * hs + 8 * c;
+      for (int t = 0; t < K; ++t)
+        if (lex_lt(od[t], oi[t], top.d[K - 1], top.i[K - 1])) top.insert(od[t], oi[t]);
+      int2* dst = hits + (q * P) * 2 * hs + K * c;
 #pragma unroll
-      for (int t = 0; t < 8; ++t) dst[t] = make_int2(__float_as_int(top.d[t]), top.i[t]);
+      for (int t = 0; t < K; ++t) dst[t] = make_int2(__float_as_int(top.d[t]), top.i[t]);
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_scan_top8_merge(int P, const int32_t* __restrict__ pair_leaf,
+template <int K>
+__global__ __launch_bounds__(256) void k_scan_topk_merge(int P, const int32_t* __restrict__ pair_leaf,
                                                          const int32_t* __restrict__ list,
                                                          const int32_t* __restrict__ n, int2* __restrict__ hits,
                                                          int32_t* __restrict__ hit_cnt, int hs) {
@@ -953,18 +982,18 @@ __global__ __launch_bounds__(256) void k_scan_top8_merge(int P, const int32_t* _
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
     const int64_t q = list[i];
     const int2* src = hits + (q * P) * 2 * hs;
-    Top8Lex top;
+    TopLex<K> top;
     top.init();
-    for (int e = 0; e < 8 * FB_CHUNKS; ++e) {
+    for (int e = 0; e < K * FB_CHUNKS; ++e) {
       const int2 v = src[e];
       const float sv = __int_as_float(v.x);
-      if (lex_lt(sv, v.y, top.d[7], top.i[7])) top.insert(sv, v.y);
+      if (lex_lt(sv, v.y, top.d[K - 1], top.i[K - 1])) top.insert(sv, v.y);
     }
     int j0 = 0;  // the first pair the query scans (it has at least one)
     while (j0 + 1 < P && pair_leaf[q * P + j0] < 0) ++j0;
     int2* dst = hits + (q * P + j0) * 2 * hs;
     int m = 0;
-    for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < K; ++t)
       if (top.i[t] != INT_MAX) dst[m++] = make_int2(__float_as_int(top.d[t]), top.i[t]);
     for (int jj = 0; jj < P; ++jj) {
       hit_cnt[(q * P + jj) * 2] = jj == j0 ? m : 0;
@@ -991,7 +1020,7 @@ int brute_splits(int64_t nq) {
 }
 
 void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16_t* Zb, const float* zbn, int64_t N,
-                            int dk, int S, int kt, float* part_d, int32_t* part_i) {
+                            int dk, int S, int kt, const uint64_t* tau_q, float* part_d, int32_t* part_i) {
   ProfScope ps(c, "brute_bf16_topk");
   if (nq == 0) return;
   PTS_REQUIRE(N > 0 && N < INT_MAX, PTS_ERR_ARG, "brute: bad N");
@@ -1001,12 +1030,37 @@ void launch_brute_bf16_topk(Ctx* c, const uint16_t* Qb, int64_t nq, const uint16
   PTS_REQUIRE(kt == 8 || kt == 16, PTS_ERR_ARG, "brute: list length must be 8 or 16");
   if (kt == 8) {
     PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_brute_bf16_topk<KSC, 8>), dim3((unsigned)(qblocks * S)), dim3(BB_QPB), 0,
-                                         c->stream, Qb, nq, Zb, zbn, N, S, rows, part_d, part_i));
+                                         c->stream, Qb, nq, Zb, zbn, N, S, rows, tau_q, part_d, part_i));
   } else {
     PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_brute_bf16_topk<KSC, 16>), dim3((unsigned)(qblocks * S)), dim3(BB_QPB),
-                                         0, c->stream, Qb, nq, Zb, zbn, N, S, rows, part_d, part_i));
+                                         0, c->stream, Qb, nq, Zb, zbn, N, S, rows, tau_q, part_d, part_i));
   }
   check_launch("k_brute_bf16_topk");
+}
+
+// pair_leaf[i] = i % S: every query scans every split of the exemplar set
+__global__ __launch_bounds__(256) void k_fill_splits(int32_t* __restrict__ pair_leaf, int64_t n, int S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pair_leaf[i] = (int32_t)(i % S);
+}
+
+// off[j] = min(N, j * ceil(N / S)), j = 0..S: the row ranges of the splits
+__global__ void k_split_offsets(int32_t* __restrict__ off, int S, int64_t N) {
+  const int j = threadIdx.x;
+  const int64_t per = (N + S - 1) / S;
+  if (j <= S) off[j] = (int32_t)min(N, (int64_t)j * per);
+}
+
+void launch_split_offsets(Ctx* c, int32_t* off, int S, int64_t N) {
+  PTS_REQUIRE(S >= 1 && S <= 255, PTS_ERR_ARG, "split count");
+  hipLaunchKernelGGL(k_split_offsets, dim3(1), dim3(256), 0, c->stream, off, S, N);
+  check_launch("k_split_offsets");
+}
+
+void launch_fill_splits(Ctx* c, int32_t* pair_leaf, int64_t n, int S) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_splits, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, pair_leaf, n, S);
+  check_launch("k_fill_splits");
 }
 
 static HitLists hit_lists(const ScanHits* sh) {
@@ -1052,11 +1106,12 @@ int64_t count_scan_rows(Ctx* c, const int32_t* pair_leaf, int64_t n, const int32
 
 void launch_leaf_scan_bf16_bound(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
                                  int dk, const int32_t* leaf_off, const BucketBufs& b, int max_tiles,
-                                 const int32_t* pair_leaf, int32_t* pair_leaf2) {
+                                 const int32_t* pair_leaf, int32_t* pair_leaf2, int K) {
+  PTS_REQUIRE(K == 8 || K == 16, PTS_ERR_ARG, "the scan keeps 8 or 16 candidates");
+  PTS_REQUIRE(P >= 1 && P <= HL_PMAX, PTS_ERR_ARG, "at most 16 scanned leaves per query");
   const int64_t npairs = nq * P;
   LeafScanOut o{};
-  o.pair_tau = c->buf<uint64_t>("ls_pair_tau", (size_t)std::max<int64_t>(1, npairs));
-  o.pair_vmin = c->buf<float>("ls_pair_vmin", (size_t)std::max<int64_t>(1, npairs));
+  o.pair_keys = c->buf<uint64_t>("ls_pair_keys", (size_t)std::max<int64_t>(1, npairs * 16));
   uint64_t* tau_q = c->buf<uint64_t>("ls_tau_q", (size_t)std::max<int64_t>(1, nq));
   if (nq == 0) return;
   if (max_tiles > 0) {
@@ -1069,9 +1124,13 @@ void launch_leaf_scan_bf16_bound(Ctx* c, const uint16_t* Qb, int64_t nq, int P, 
     check_launch("k_leaf_scan_bf16 (bound)");
   }
   ProfScope ps(c, "scan_tau_min");
-  hipLaunchKernelGGL(k_pair_tau_min, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf, o.pair_tau,
-                     o.pair_vmin, nq, P, tau_q, pair_leaf2);
-  check_launch("k_pair_tau_min");
+  if (K == 8)
+    hipLaunchKernelGGL(k_pair_tau_pool<8>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf,
+                       o.pair_keys, nq, P, tau_q, pair_leaf2);
+  else
+    hipLaunchKernelGGL(k_pair_tau_pool<16>, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, c->stream, pair_leaf,
+                       o.pair_keys, nq, P, tau_q, pair_leaf2);
+  check_launch("k_pair_tau_pool");
 }
 
 void launch_leaf_scan_bf16_class(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb, const float* zbn,
@@ -1093,14 +1152,16 @@ void launch_leaf_scan_bf16_class(Ctx* c, const uint16_t* Qb, int64_t nq, int P, 
 void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P, const uint16_t* Zb,
                                    const float* zbn, int dk, const int32_t* leaf_off, const BucketBufs& b,
                                    int max_tiles, const int32_t* pair_leaf2, int hc, ScanHits* sh,
-                                   int32_t* n_overflow) {
+                                   int32_t* n_overflow, int K) {
+  PTS_REQUIRE(K == 8 || K == 16, PTS_ERR_ARG, "the scan keeps 8 or 16 candidates");
   PTS_REQUIRE(hc >= 0 && hc <= LS_HC_MAX, PTS_ERR_ARG, "collect slots must be 0..14");
   int cap = 0;  // fewer fit beside the wider stage buffers of 96 and 128 dimensions
   PTS_KS_SWITCH(dk, cap = ls_hc_cap<KSC>());
   hc = std::min(hc, cap);
-  PTS_REQUIRE(P >= 1 && P <= HL_PMAX, PTS_ERR_ARG, "at most 9 scanned leaves per query");
-  // slot stride: hc, but room for the per-query pass's chunk lists too
-  const int hs = std::max(hc, (int)ceil_div(8 * FB_CHUNKS, 2 * P));
+  PTS_REQUIRE(P >= 1 && P <= HL_PMAX, PTS_ERR_ARG, "at most 16 scanned leaves per query");
+  // slot stride: hc, but room for the per-query pass's chunk lists (and for
+  // the K merged entries in the last pair's two halves) too
+  const int hs = std::max({hc, (int)ceil_div(K * FB_CHUNKS, 2 * P), (int)ceil_div(K, 2)});
   const int64_t npairs = nq * P;
   LeafScanOut o{};
   o.tau_q = c->buf<uint64_t>("ls_tau_q", (size_t)std::max<int64_t>(1, nq));
@@ -1130,13 +1191,21 @@ void launch_leaf_scan_bf16_collect(Ctx* c, const uint16_t* Qb, int64_t nq, int P
                      o.hit_cnt, nq, P, hc, list, n_overflow);
   check_launch("k_hit_overflow");
   // waves and threads loop over the list (its length is only known on the device)
-  PTS_REQUIRE((int64_t)P * 2 * hs >= 8 * FB_CHUNKS, PTS_ERR_ARG, "too few collect slots per query");
-  PTS_KS_SWITCH(dk, hipLaunchKernelGGL(k_scan_top8_chunks<KSC>, dim3(4 * c->n_cu), dim3(256), 0, c->stream, Qb, P,
-                                       Zb, zbn, leaf_off, pair_leaf2, list, n_overflow, o.tau_q, o.hits, hs));
-  check_launch("k_scan_top8_chunks");
-  hipLaunchKernelGGL(k_scan_top8_merge, dim3(64), dim3(256), 0, c->stream, P, pair_leaf2, list, n_overflow, o.hits,
-                     o.hit_cnt, hs);
-  check_launch("k_scan_top8_merge");
+  PTS_REQUIRE((int64_t)P * 2 * hs >= K * FB_CHUNKS, PTS_ERR_ARG, "too few collect slots per query");
+  if (K == 8) {
+    PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_scan_topk_chunks<KSC, 8>), dim3(4 * c->n_cu), dim3(256), 0, c->stream,
+                                         Qb, P, Zb, zbn, leaf_off, pair_leaf2, list, n_overflow, o.tau_q, o.hits, hs));
+    check_launch("k_scan_topk_chunks");
+    hipLaunchKernelGGL(k_scan_topk_merge<8>, dim3(64), dim3(256), 0, c->stream, P, pair_leaf2, list, n_overflow,
+                       o.hits, o.hit_cnt, hs);
+  } else {
+    PTS_KS_SWITCH(dk, hipLaunchKernelGGL((k_scan_topk_chunks<KSC, 16>), dim3(4 * c->n_cu), dim3(256), 0, c->stream,
+                                         Qb, P, Zb, zbn, leaf_off, pair_leaf2, list, n_overflow, o.tau_q, o.hits, hs));
+    check_launch("k_scan_topk_chunks");
+    hipLaunchKernelGGL(k_scan_topk_merge<16>, dim3(64), dim3(256), 0, c->stream, P, pair_leaf2, list, n_overflow,
+                       o.hits, o.hit_cnt, hs);
+  }
+  check_launch("k_scan_topk_merge");
 }
 
 // ---------------------------------------------------------------------------
@@ -1222,7 +1291,7 @@ void launch_merge_rerank_pca(Ctx* c, const float* part_d, const int32_t* part_i,
                              int32_t* nn, int list_len) {
   ProfScope ps(c, "merge_rerank");
   if (nq == 0) return;
-  PTS_REQUIRE(k >= 1 && k <= 16 && (k <= 8 || !sh), PTS_ERR_ARG, "topk must be 1..16 (1..8 with hit lists)");
+  PTS_REQUIRE(k >= 1 && k <= 16, PTS_ERR_ARG, "topk must be 1..16");
   PTS_REQUIRE(list_len == 0 || list_len == 8 || list_len == 16, PTS_ERR_ARG, "candidate lists hold 8 or 16");
   const int kl = list_len ? list_len : (k <= 8 ? 8 : 16);
   PTS_REQUIRE(k <= kl, PTS_ERR_ARG, "more candidates asked for than the lists hold");
@@ -1442,7 +1511,7 @@ void launch_select_rerank_full(Ctx* c, const float* part_d, const int32_t* part_
                                const float* ex_srow, int Hz, int Wz, int32_t* nn, float* dist, int list_len) {
   ProfScope ps(c, "select_rerank_full");
   if (nq == 0) return;
-  PTS_REQUIRE(k >= 1 && k <= 16 && (k <= 8 || !sh), PTS_ERR_ARG, "topk must be 1..16 (1..8 with hit lists)");
+  PTS_REQUIRE(k >= 1 && k <= 16, PTS_ERR_ARG, "topk must be 1..16");
   PTS_REQUIRE(list_len == 0 || list_len == 8 || list_len == 16, PTS_ERR_ARG, "candidate lists hold 8 or 16");
   const int kl = list_len ? list_len : (k <= 8 ? 8 : 16);
   PTS_REQUIRE(k <= kl, PTS_ERR_ARG, "more candidates asked for than the lists hold");
