@@ -190,6 +190,9 @@ def headline(a):
     if not a.no_cpu:
         cpu = cpu_baseline(ctx, ex, init, w, s, a.cpu_seconds, threads=1)
         extra["cpu_baseline_all_cores"] = cpu_baseline(ctx, ex, init, w, s, a.cpu_seconds, threads=0)
+    if not a.no_solve and a.workload == "ex1024_out2048":
+        # last: these replace the context's exemplar and index
+        extra["solve_small_workloads"] = small_solve_rows(ctx)
     out = {
         "metric": "NN queries/s + ms/iteration",
         "value": head["value"],
@@ -386,6 +389,34 @@ def solve_rows(ctx, wl, ex, learned, a):
                      "wall_s_with_index_builds": wall, "energy_final": float(tr["E"][-1])}
         log(f"solve {name}: iterations {sum(per_level):.1f} ms (per level {['%.1f' % v for v in per_level]}), "
             f"wall {wall:.1f} s with the coarse levels' index builds")
+    return out
+
+
+def small_solve_rows(ctx):
+    """The plain tree solve of the two small workloads (64^2 -> 128^2, one
+    level of 5 iterations; 256^2 -> 512^2, three levels of 10), every level's
+    index built by the solve: the sum of the per-iteration times and the wall
+    time with the index builds."""
+    import torch
+
+    from paper_2006_11851_amd import synth
+
+    out = {}
+    for name in ("ex64_out128", "ex256_out512"):
+        wl = synth.workload(name)
+        ex = wl.exemplar()
+        ctx.set_exemplar_u8(ex, 0.5)
+        x0 = ctx.rgbs_from_u8(wl.initial_output(ex), 0.5)
+        levels = [dict(w=wl.w[l], stride=wl.stride[l], iters=wl.iters, pca_dims=wl.pca_dims,
+                       branching=wl.branching, depth=wl.depth) for l in range(wl.levels)]
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, tr = ctx.solve(x0, levels, mode="tree", coarse_mode="tree")
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        out[name] = {"ms_iterations_total": float(np.sum(tr["ms"])), "iterations": int(len(tr["ms"])),
+                     "wall_s_with_index_builds": wall, "energy_final": float(tr["E"][-1])}
+        log(f"solve {name} (plain tree): iterations {out[name]['ms_iterations_total']:.1f} ms, wall {wall:.2f} s")
     return out
 
 
