@@ -835,10 +835,20 @@ __global__ __launch_bounds__(256) void k_pair_tau_pool(const int32_t* __restrict
   for (int j = 0; j < P; ++j) {
     const int64_t p = q * P + j;
     if (pair_leaf[p] < 0) continue;
+    // the pair's 16 keys in eight independent 16-byte loads
+    uint64_t kv[16];
+    const ulonglong2* kp = reinterpret_cast<const ulonglong2*>(pair_keys + p * 16);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const ulonglong2 u = kp[c];
+      kv[2 * c] = u.x;
+      kv[2 * c + 1] = u.y;
+    }
+#pragma unroll
     for (int run = 0; run < 2; ++run) {
-      const uint64_t* kp = pair_keys + p * 16 + 8 * run;
+#pragma unroll
       for (int c = 0; c < 8; ++c) {
-        uint64_t v = kp[c];
+        uint64_t v = kv[8 * run + c];
         if (v >= top[K - 1]) break;  // the run is sorted: nothing later enters
         // insertion into the sorted list
 #pragma unroll
