@@ -66,7 +66,7 @@ def log(msg):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU: --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
 
