@@ -380,7 +380,8 @@ def solve_rows(ctx, wl, ex, learned, a):
     for name, mode in modes:
         torch.cuda.synchronize()
         t0 = time.time()
-        _, tr = ctx.solve(x0, levels, mode=mode, coarse_mode="tree", rerank_full=a.rerank_full,
+        topk = a.class_topk if mode == "learned_bf16_class" else 8
+        _, tr = ctx.solve(x0, levels, mode=mode, coarse_mode="tree", topk=topk, rerank_full=a.rerank_full,
                           n_proposals=a.proposals, margin=a.margin, residual=a.residual, reuse_finest_index=True)
         torch.cuda.synchronize()
         wall = time.time() - t0
