@@ -1417,14 +1417,18 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     // indices below 2^26): loads from a scalar base plus a 32-bit offset
     uint32_t eb[8];
     int eyc[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      eb[c] = PK ? (uint32_t)cbase[cg + c][ql] * 4u : (uint32_t)cbase[cg + c][ql];
-      eyc[c] = crow[cg + c][ql];
-    }
     float acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    // NC windows gathered: 4 when the group holds no more candidates than
+    // that (the rest keep a zero sum and are masked after the butterfly)
+    auto gather = [&](auto ncv) {
+    constexpr int NC = decltype(ncv)::value;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      eb[c] = PK ? (uint32_t)cbase[cg + c][ql] * 4u : (uint32_t)cbase[cg + c][ql];
+      eyc[c] = crow[cg + c][ql];
+    }
     int dy = 0, dx = g;
     while (dx >= w) {
       dx -= w;
@@ -1437,7 +1441,7 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
       const float4 a = x[(int64_t)(v + dy) * W + xx];
       const uint32_t eo = (uint32_t)(dy * Wz + dx) * (PK ? 4u : 1u);
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
+      for (int c = 0; c < NC; ++c) {
         float4 b;
         if constexpr (PK) {
           // the rounded products, as stored in the RGBS image (contraction
@@ -1464,6 +1468,9 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
         ++dy;
       }
     }
+    };
+    if (k - cg <= 4) gather(std::integral_constant<int, 4>{});
+    else gather(std::integral_constant<int, 8>{});
     // halving butterfly over the 16 lanes: after it, lane g holds the full
     // sum of candidate ci(g) (lanes g and g^1 hold the same one)
     float b4[4];
