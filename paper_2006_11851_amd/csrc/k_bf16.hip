@@ -1409,7 +1409,8 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     const int v = qvu[0][ql], u = qvu[1][ql];
     float bbd = FLT_MAX;
     int bbi = INT_MAX;
-    // the candidates in groups of 8 (one group unless 16 are re-ranked)
+    // the candidates in groups of 8 (one group unless more than 8 are re-ranked; a last
+    // group of at most 4 gathers 4 windows)
 #pragma unroll
     for (int cg = 0; cg < KL; cg += 8) {
     if (cg >= k) break;  // lists longer than the candidates re-ranked
