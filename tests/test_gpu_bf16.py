@@ -89,6 +89,12 @@ def test_brute_bf16_ragged_and_rerank_full(gpu_ctx):
         nnk, _ = gpu_ctx.estep(x, w, s, mode="brute_bf16", topk=k)
         valid = helpers.topk_rerank_validity(Qp, Zp, None, allz, _np(nnk), k)
         assert valid.mean() >= 0.999, (k, valid.mean())
+    # the same with the full-dimension re-rank, over both forms of its last
+    # group of candidates (4 windows gathered for k = 9..12, 8 for 13..16)
+    for k in (3, 10, 12, 13, 16):
+        nnk, _ = gpu_ctx.estep(x, w, s, mode="brute_bf16", rerank_full=1, topk=k)
+        valid = helpers.topk_rerank_validity(Qp, Zp, None, allz, _np(nnk), k, Q_full=Q, Zm=Zm)
+        assert valid.mean() >= 0.999, ("full-D re-rank", k, valid.mean())
 
 
 def test_brute_bf16_energy_gap_ex512_w16(gpu_ctx):
