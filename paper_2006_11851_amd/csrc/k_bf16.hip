@@ -1332,18 +1332,21 @@ constexpr int SR_QPB = 256;
 
 // PK: the exemplar windows come from its 8-bit form (pk, srow), rebuilt as
 // the same floats the RGBS image holds (channel value / 255, the row's
-// guidance value), at 4 bytes a pixel instead of 16.
+// guidance value), at 4 bytes a pixel instead of 16.  The PK forms run four
+// waves per SIMD (at most 128 registers; the gathers are latency bound and
+// the fourth wave hides more of it than the registers it costs: 0.53 against
+// 0.59 ms for 8 candidates per query, 0.84 against 0.91 for 12).
 template <bool PK, int KL>
-__global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
+__global__ __launch_bounds__(SR_QPB) __attribute__((amdgpu_waves_per_eu(PK ? 4 : 1))) void k_select_rerank_full(
     const float* __restrict__ part_d, const int32_t* __restrict__ part_i, int64_t nq, int S, int64_t qs, int64_t ss,
     const int32_t* __restrict__ valid, HitLists hl, int k, const int32_t* __restrict__ perm, int64_t npos,
     const float4* __restrict__ x, int W, int w, int s, int cols, const float4* __restrict__ ex,
     const uint32_t* __restrict__ pk, const float* __restrict__ srow, int Hz, int Wz, int32_t* __restrict__ nn,
     float* __restrict__ dist) {
-  // per query of the block (phase 1, one thread each): the candidates, their
-  // window origins (pixel index, row) and the query window's row and column,
-  // so that the 16 lanes of a query in phase 2 do no index arithmetic of their own
-  __shared__ int32_t cand[KL][SR_QPB];
+  // per query of the block (phase 1, one thread each): the candidates' window
+  // origins (pixel index, row; row -1 for no candidate) and the query window's
+  // row and column, so that the 16 lanes of a query in phase 2 do no index
+  // arithmetic of their own beyond the winner's id
   __shared__ int32_t cbase[KL][SR_QPB];
   __shared__ int32_t crow[KL][SR_QPB];
   __shared__ int32_t qvu[2][SR_QPB];
@@ -1387,11 +1390,11 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
     for (int t = 0; t < KL; ++t) {
       const int pos = top.i[t];
       const int e = (t < k && pos >= 0 && pos < npos) ? perm[pos] : -1;
-      cand[t][tid] = e;
-      const int ee = (e < 0 || e >= N) ? 0 : e;  // an in-bounds window, result discarded in phase 2
+      const bool ok = e >= 0 && e < N;
+      const int ee = ok ? e : 0;  // an in-bounds window, result discarded in phase 2
       const int ey = ee / nu;
       cbase[t][tid] = ey * Wz + (ee - ey * nu);
-      crow[t][tid] = ey;
+      crow[t][tid] = ok ? ey : -1;
     }
     const int64_t qc = q < nq ? q : 0;
     const int qi = (int)(qc / cols);
@@ -1428,7 +1431,7 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       eb[c] = PK ? (uint32_t)cbase[cg + c][ql] * 4u : (uint32_t)cbase[cg + c][ql];
-      eyc[c] = crow[cg + c][ql];
+      eyc[c] = max(crow[cg + c][ql], 0);
     }
     int dy = 0, dx = g;
     while (dx >= w) {
@@ -1496,9 +1499,11 @@ __global__ __launch_bounds__(SR_QPB) void k_select_rerank_full(
       tot = keep + __shfl_xor(send, 2, 64);
     }
     tot += __shfl_xor(tot, 1, 64);
-    const int e = cand[cg + ci][ql];
-    float bd = (cg + ci < k && e >= 0 && e < N) ? tot : FLT_MAX;
-    int bi = (cg + ci < k && e >= 0 && e < N) ? e : INT_MAX;
+    // the candidate's exemplar id from its window origin
+    const int ey = crow[cg + ci][ql];
+    const int e = ey * nu + (cbase[cg + ci][ql] - ey * Wz);
+    float bd = (cg + ci < k && ey >= 0) ? tot : FLT_MAX;
+    int bi = (cg + ci < k && ey >= 0) ? e : INT_MAX;
 #pragma unroll
     for (int off = 2; off <= 8; off <<= 1) {
       const float od = __shfl_xor(bd, off, 64);
