@@ -1416,107 +1416,107 @@ __global__ __launch_bounds__(SR_QPB) __attribute__((amdgpu_waves_per_eu(PK ? 4 :
     // group of at most 4 gathers 4 windows)
 #pragma unroll
     for (int cg = 0; cg < KL; cg += 8) {
-    if (cg >= k) break;  // lists longer than the candidates re-ranked
-    // 32-bit byte offsets of the windows' origins in the 8-bit form (pixel
-    // indices below 2^26): loads from a scalar base plus a 32-bit offset
-    uint32_t eb[8];
-    int eyc[8];
-    float acc[8];
+      if (cg >= k) break;  // lists longer than the candidates re-ranked
+      // 32-bit byte offsets of the windows' origins in the 8-bit form (pixel
+      // indices below 2^26): loads from a scalar base plus a 32-bit offset
+      uint32_t eb[8];
+      int eyc[8];
+      float acc[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
-    // NC windows gathered: 4 when the group holds no more candidates than
-    // that (the rest keep a zero sum and are masked after the butterfly)
-    auto gather = [&](auto ncv) {
-    constexpr int NC = decltype(ncv)::value;
+      for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+      // NC windows gathered: 4 when the group holds no more candidates than
+      // that (the rest keep a zero sum and are masked after the butterfly)
+      auto gather = [&](auto ncv) {
+        constexpr int NC = decltype(ncv)::value;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      eb[c] = PK ? (uint32_t)cbase[cg + c][ql] * 4u : (uint32_t)cbase[cg + c][ql];
-      eyc[c] = max(crow[cg + c][ql], 0);
-    }
-    int dy = 0, dx = g;
-    while (dx >= w) {
-      dx -= w;
-      ++dy;
-    }
-#pragma unroll 4
-    for (int p = g; p < npx; p += 16) {
-      int xx = u + dx;
-      if (xx >= W) xx -= W;
-      const float4 a = x[(int64_t)(v + dy) * W + xx];
-      const uint32_t eo = (uint32_t)(dy * Wz + dx) * (PK ? 4u : 1u);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        float4 b;
-        if constexpr (PK) {
-          // the rounded products, as stored in the RGBS image (contraction
-          // off: not fused into the subtraction below)
-#pragma clang fp contract(off)
-          const float inv = 1.0f / 255.0f;
-          const uint32_t pv = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(pk) + (eb[c] + eo));
-          b.x = (float)(pv & 255u) * inv;
-          b.y = (float)((pv >> 8) & 255u) * inv;
-          b.z = (float)((pv >> 16) & 255u) * inv;
-          b.w = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(srow) + (uint32_t)(eyc[c] + dy) * 4u);
-        } else {
-          b = ex[eb[c] + eo];
+        for (int c = 0; c < NC; ++c) {
+          eb[c] = PK ? (uint32_t)cbase[cg + c][ql] * 4u : (uint32_t)cbase[cg + c][ql];
+          eyc[c] = max(crow[cg + c][ql], 0);
         }
-        const float t0 = a.x - b.x, t1 = a.y - b.y, t2 = a.z - b.z, t3 = a.w - b.w;
-        acc[c] = fmaf(t0, t0, acc[c]);
-        acc[c] = fmaf(t1, t1, acc[c]);
-        acc[c] = fmaf(t2, t2, acc[c]);
-        acc[c] = fmaf(t3, t3, acc[c]);
-      }
-      dx += 16;
-      while (dx >= w) {
-        dx -= w;
-        ++dy;
-      }
-    }
-    };
-    if (k - cg <= 4) gather(std::integral_constant<int, 4>{});
-    else gather(std::integral_constant<int, 8>{});
-    // halving butterfly over the 16 lanes: after it, lane g holds the full
-    // sum of candidate ci(g) (lanes g and g^1 hold the same one)
-    float b4[4];
-    const bool h8 = g & 8, h4 = g & 4, h2 = g & 2;
+        int dy = 0, dx = g;
+        while (dx >= w) {
+          dx -= w;
+          ++dy;
+        }
+#pragma unroll 4
+        for (int p = g; p < npx; p += 16) {
+          int xx = u + dx;
+          if (xx >= W) xx -= W;
+          const float4 a = x[(int64_t)(v + dy) * W + xx];
+          const uint32_t eo = (uint32_t)(dy * Wz + dx) * (PK ? 4u : 1u);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const float keep = h8 ? acc[t + 4] : acc[t];
-      const float send = h8 ? acc[t] : acc[t + 4];
-      b4[t] = keep + __shfl_xor(send, 8, 64);
-    }
-    float b2[2];
+          for (int c = 0; c < NC; ++c) {
+            float4 b;
+            if constexpr (PK) {
+              // the rounded products, as stored in the RGBS image (contraction
+              // off: not fused into the subtraction below)
+#pragma clang fp contract(off)
+              const float inv = 1.0f / 255.0f;
+              const uint32_t pv = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(pk) + (eb[c] + eo));
+              b.x = (float)(pv & 255u) * inv;
+              b.y = (float)((pv >> 8) & 255u) * inv;
+              b.z = (float)((pv >> 16) & 255u) * inv;
+              b.w = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(srow) + (uint32_t)(eyc[c] + dy) * 4u);
+            } else {
+              b = ex[eb[c] + eo];
+            }
+            const float t0 = a.x - b.x, t1 = a.y - b.y, t2 = a.z - b.z, t3 = a.w - b.w;
+            acc[c] = fmaf(t0, t0, acc[c]);
+            acc[c] = fmaf(t1, t1, acc[c]);
+            acc[c] = fmaf(t2, t2, acc[c]);
+            acc[c] = fmaf(t3, t3, acc[c]);
+          }
+          dx += 16;
+          while (dx >= w) {
+            dx -= w;
+            ++dy;
+          }
+        }
+      };
+      if (k - cg <= 4) gather(std::integral_constant<int, 4>{});
+      else gather(std::integral_constant<int, 8>{});
+      // halving butterfly over the 16 lanes: after it, lane g holds the full
+      // sum of candidate ci(g) (lanes g and g^1 hold the same one)
+      float b4[4];
+      const bool h8 = g & 8, h4 = g & 4, h2 = g & 2;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const float keep = h4 ? b4[t + 2] : b4[t];
-      const float send = h4 ? b4[t] : b4[t + 2];
-      b2[t] = keep + __shfl_xor(send, 4, 64);
-    }
-    float tot;
-    {
-      const float keep = h2 ? b2[1] : b2[0];
-      const float send = h2 ? b2[0] : b2[1];
-      tot = keep + __shfl_xor(send, 2, 64);
-    }
-    tot += __shfl_xor(tot, 1, 64);
-    // the candidate's exemplar id from its window origin
-    const int ey = crow[cg + ci][ql];
-    const int e = ey * nu + (cbase[cg + ci][ql] - ey * Wz);
-    float bd = (cg + ci < k && ey >= 0) ? tot : FLT_MAX;
-    int bi = (cg + ci < k && ey >= 0) ? e : INT_MAX;
-#pragma unroll
-    for (int off = 2; off <= 8; off <<= 1) {
-      const float od = __shfl_xor(bd, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (lex_lt(od, oi, bd, bi)) {
-        bd = od;
-        bi = oi;
+      for (int t = 0; t < 4; ++t) {
+        const float keep = h8 ? acc[t + 4] : acc[t];
+        const float send = h8 ? acc[t] : acc[t + 4];
+        b4[t] = keep + __shfl_xor(send, 8, 64);
       }
-    }
-    if (lex_lt(bd, bi, bbd, bbi)) {
-      bbd = bd;
-      bbi = bi;
-    }
+      float b2[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const float keep = h4 ? b4[t + 2] : b4[t];
+        const float send = h4 ? b4[t] : b4[t + 2];
+        b2[t] = keep + __shfl_xor(send, 4, 64);
+      }
+      float tot;
+      {
+        const float keep = h2 ? b2[1] : b2[0];
+        const float send = h2 ? b2[0] : b2[1];
+        tot = keep + __shfl_xor(send, 2, 64);
+      }
+      tot += __shfl_xor(tot, 1, 64);
+      // the candidate's exemplar id from its window origin
+      const int ey = crow[cg + ci][ql];
+      const int e = ey * nu + (cbase[cg + ci][ql] - ey * Wz);
+      float bd = (cg + ci < k && ey >= 0) ? tot : FLT_MAX;
+      int bi = (cg + ci < k && ey >= 0) ? e : INT_MAX;
+#pragma unroll
+      for (int off = 2; off <= 8; off <<= 1) {
+        const float od = __shfl_xor(bd, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (lex_lt(od, oi, bd, bi)) {
+          bd = od;
+          bi = oi;
+        }
+      }
+      if (lex_lt(bd, bi, bbd, bbi)) {
+        bbd = bd;
+        bbi = bi;
+      }
     }
     const float bd = bbd;
     const int bi = bbi;
