@@ -994,10 +994,19 @@ __global__ __launch_bounds__(256) void k_scan_topk_merge(int P, const int32_t* _
     const int2* src = hits + (q * P) * 2 * hs;
     TopLex<K> top;
     top.init();
-    for (int e = 0; e < K * FB_CHUNKS; ++e) {
-      const int2 v = src[e];
-      const float sv = __int_as_float(v.x);
-      if (lex_lt(sv, v.y, top.d[K - 1], top.i[K - 1])) top.insert(sv, v.y);
+    // 32 entries loaded together, then inserted in the same order (one
+    // memory latency per 32 entries instead of one per entry)
+    constexpr int NB = 32;
+    static_assert((K * FB_CHUNKS) % NB == 0, "whole batches");
+    for (int e0 = 0; e0 < K * FB_CHUNKS; e0 += NB) {
+      int2 v[NB];
+#pragma unroll
+      for (int e = 0; e < NB; ++e) v[e] = src[e0 + e];
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const float sv = __int_as_float(v[e].x);
+        if (lex_lt(sv, v[e].y, top.d[K - 1], top.i[K - 1])) top.insert(sv, v[e].y);
+      }
     }
     int j0 = 0;  // the first pair the query scans (it has at least one)
     while (j0 + 1 < P && pair_leaf[q * P + j0] < 0) ++j0;
